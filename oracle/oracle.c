@@ -1,0 +1,798 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU implementation of the per-rank fast multipole
+ * evaluation whose hot path the HIP library implements.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg load it; the
+ * product path never links, loads or calls anything in this directory, and
+ * this file shares no code, header, table or helper with the HIP library.
+ *
+ * What it computes (paper: Section II.A, the six FMM operators P2M, M2M,
+ * M2L, L2L, L2P, P2P; Section II.C, upward pass, dual tree traversal and
+ * downward pass; Section III and Table I, parameters P, theta, N_crit):
+ *
+ *   direct sum     phi_i = sum_{j: x_j != x_i} q_j / |x_i - x_j|,
+ *                  E_i   = sum_{j: x_j != x_i} q_j (x_i - x_j) / |x_i - x_j|^3
+ *                  (the plain definition that the FMM approximates)
+ *   local octree   root cube from the local bounding box, 64-bit Morton keys
+ *                  (3 bits per level, 21 levels; Section II.B), stable sort,
+ *                  a cell is split while it holds more than N_crit bodies
+ *   dual traversal recursive cell-pair walk (Section II.C, after Dehnen 2002)
+ *                  emitting M2L pairs (acceptance criterion met) and P2P
+ *                  pairs (both leaves), with a symmetric split rule
+ *   expansions     complex solid harmonics of degree n < p built from their
+ *                  textbook definition (associated Legendre functions and
+ *                  e^{i m phi}); translations from the addition theorem of
+ *                  the regular solid harmonics
+ *
+ * Every target output is accumulated by one thread in a fixed order, so the
+ * result is bit-identical for any OpenMP thread count.
+ *
+ * Pins (tests/test_oracle_*.py): direct sum against an independent
+ * vectorised evaluation and physical invariants; Legendre functions against
+ * scipy; multipole and local series against the Legendre addition theorem;
+ * M2L against the axisymmetric closed form and against bidegree Taylor
+ * coefficients extracted by contour integrals; M2M/L2L exactness; the tree
+ * against an independent recursive octree and published cell counts; list
+ * invariants and lattice counts; the a priori error bound of the whole FMM;
+ * energy symmetry; scaling and axis-permutation invariance; frozen-tree
+ * finite differences.  No function here is "parity unpinned".
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define ORC_MAXP 16
+#define ORC_LEVELS 21
+#define ORC_HMAX (2 * ORC_MAXP) /* harmonics needed up to degree 2p-2 */
+
+/* ------------------------------------------------------------------------ */
+/* Direct sum: the plain definition of potential and field.                 */
+/* ------------------------------------------------------------------------ */
+
+/* targets == NULL: every body is a target (outputs in input order, n rows);
+ * otherwise nt target indices, outputs in target order.                    */
+int oracle_direct(int64_t n, const double *x, const double *q, int64_t nt,
+                  const int64_t *targets, double *phi, double *field)
+{
+    if (n < 0 || nt < 0 || (n > 0 && (!x || !q))) return 1;
+    int64_t ntg = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < ntg; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+        double p = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double dx = xi - x[3 * j], dy = yi - x[3 * j + 1], dz = zi - x[3 * j + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2);
+            double qr = q[j] / r;
+            double qr3 = qr / r2;
+            p += qr;
+            ex += qr3 * dx;
+            ey += qr3 * dy;
+            ez += qr3 * dz;
+        }
+        if (phi) phi[t] = p;
+        if (field) {
+            field[3 * t] = ex;
+            field[3 * t + 1] = ey;
+            field[3 * t + 2] = ez;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Associated Legendre functions and solid harmonics (textbook definitions). */
+/* ------------------------------------------------------------------------ */
+
+static double fact(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+#define PIDX(n, m) ((n) * ((n) + 1) / 2 + (m))
+#define HIDX(n, m) ((n) * (n) + (n) + (m))
+
+/* P_n^m(x) for 0 <= m <= n < nmax, with the Condon-Shortley phase (-1)^m,
+ * from the standard recurrences in n at fixed m.                          */
+void oracle_legendre(double x, int nmax, double *P)
+{
+    double s = sqrt(fmax(0.0, (1.0 - x) * (1.0 + x)));
+    double pmm = 1.0;
+    for (int m = 0; m < nmax; ++m) {
+        if (m > 0) pmm *= -(2.0 * m - 1.0) * s;
+        P[PIDX(m, m)] = pmm;
+        if (m + 1 < nmax) P[PIDX(m + 1, m)] = x * (2.0 * m + 1.0) * pmm;
+        for (int n = m + 2; n < nmax; ++n)
+            P[PIDX(n, m)] = ((2.0 * n - 1.0) * x * P[PIDX(n - 1, m)] - (n + m - 1.0) * P[PIDX(n - 2, m)]) / (double)(n - m);
+    }
+}
+
+/* Solid harmonics of v for degrees n < nmax and all orders -n..n:
+ *   R_n^m(v) = r^n P_n^m(cos t) e^{i m f} / (n+m)!        (m >= 0)
+ *   I_n^m(v) = (n-m)! P_n^m(cos t) e^{i m f} / r^{n+1}     (m >= 0)
+ *   X_n^{-m} = (-1)^m conj(X_n^m)
+ * With these, 1/|x - y| = sum_{n,m} conj(R_n^m(y)) I_n^m(x) for |y| < |x|,
+ * and R_n^m(a + b) = sum_{k,l} R_k^l(a) R_{n-k}^{m-l}(b).
+ * Either output may be NULL; the irregular ones need v != 0.               */
+static void harmonics(const double v[3], int nmax, cplx *Rh, cplx *Ih)
+{
+    double P[(ORC_HMAX + 1) * (ORC_HMAX + 2) / 2];
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double ct = r > 0.0 ? v[2] / r : 1.0;
+    double ph = atan2(v[1], v[0]);
+    oracle_legendre(ct, nmax, P);
+    for (int n = 0; n < nmax; ++n) {
+        double rn = pow(r, (double)n);
+        double rin = (Ih && r > 0.0) ? 1.0 / pow(r, (double)(n + 1)) : 0.0;
+        for (int m = 0; m <= n; ++m) {
+            cplx e = cos(m * ph) + sin(m * ph) * I;
+            double sg = (m & 1) ? -1.0 : 1.0;
+            if (Rh) {
+                cplx val = rn * P[PIDX(n, m)] * e / fact(n + m);
+                Rh[HIDX(n, m)] = val;
+                Rh[HIDX(n, -m)] = sg * conj(val);
+            }
+            if (Ih) {
+                cplx val = fact(n - m) * P[PIDX(n, m)] * e * rin;
+                Ih[HIDX(n, m)] = val;
+                Ih[HIDX(n, -m)] = sg * conj(val);
+            }
+        }
+    }
+}
+
+/* Exported for the pins: complex values as (re, im) pairs, index n*n+n+m. */
+void oracle_harmonics(const double *v, int nmax, double *R, double *Iout)
+{
+    cplx Rh[(ORC_HMAX + 1) * (ORC_HMAX + 1)], Ih[(ORC_HMAX + 1) * (ORC_HMAX + 1)];
+    if (nmax > ORC_HMAX + 1) return;
+    harmonics(v, nmax, R ? Rh : NULL, Iout ? Ih : NULL);
+    for (int k = 0; k < nmax * nmax; ++k) {
+        if (R) { R[2 * k] = creal(Rh[k]); R[2 * k + 1] = cimag(Rh[k]); }
+        if (Iout) { Iout[2 * k] = creal(Ih[k]); Iout[2 * k + 1] = cimag(Ih[k]); }
+    }
+}
+
+static cplx hget(const cplx *H, int n, int m)
+{
+    if (n < 0 || m > n || m < -n) return 0.0;
+    return H[HIDX(n, m)];
+}
+
+/* ------------------------------------------------------------------------ */
+/* The five expansion operators on complex coefficient vectors of length p^2 */
+/* (index n*n+n+m, 0 <= n < p, -n <= m <= n).                                */
+/* ------------------------------------------------------------------------ */
+
+/* P2M (Section II.A): M_n^m = sum_j q_j conj(R_n^m(x_j - c)).              */
+static void p2m_add(const double *xj, double qj, const double c[3], int p, cplx *M)
+{
+    cplx Rh[ORC_MAXP * ORC_MAXP];
+    double v[3] = {xj[0] - c[0], xj[1] - c[1], xj[2] - c[2]};
+    harmonics(v, p, Rh, NULL);
+    for (int k = 0; k < p * p; ++k) M[k] += qj * conj(Rh[k]);
+}
+
+/* M2M (Section II.A): re-expansion of a child multipole about the parent
+ * center; x_j - c_par = (x_j - c_ch) + (c_ch - c_par) with the regular
+ * addition theorem gives M_n^m += sum_{k,l} M'_k^l conj(R_{n-k}^{m-l}(d)).  */
+static void m2m_add(const cplx *Mc, const double cch[3], const double cpar[3], int p, cplx *Mp)
+{
+    cplx Rh[ORC_MAXP * ORC_MAXP];
+    double d[3] = {cch[0] - cpar[0], cch[1] - cpar[1], cch[2] - cpar[2]};
+    harmonics(d, p, Rh, NULL);
+    for (int n = 0; n < p; ++n)
+        for (int m = -n; m <= n; ++m) {
+            cplx s = 0.0;
+            for (int k = 0; k <= n; ++k)
+                for (int l = -k; l <= k; ++l) s += Mc[HIDX(k, l)] * conj(hget(Rh, n - k, m - l));
+            Mp[HIDX(n, m)] += s;
+        }
+}
+
+/* M2L (Section II.A): with D = c_A - c_B and t = x - c_A,
+ * I_n^m(D + t) = sum_{j,s} (-1)^j conj(R_j^s(t)) I_{n+j}^{m+s}(D), so the
+ * local coefficients (of conj(R_j^s(t))) are
+ *   L_j^s += (-1)^j sum_{n<p,m} M_n^m I_{n+j}^{m+s}(D),   j < p.           */
+static void m2l_add(const cplx *M, const double cB[3], const double cA[3], int p, cplx *L)
+{
+    cplx Ih[(2 * ORC_MAXP) * (2 * ORC_MAXP)];
+    double D[3] = {cA[0] - cB[0], cA[1] - cB[1], cA[2] - cB[2]};
+    harmonics(D, 2 * p - 1, NULL, Ih);
+    for (int j = 0; j < p; ++j) {
+        double sj = (j & 1) ? -1.0 : 1.0;
+        for (int s = -j; s <= j; ++s) {
+            cplx acc = 0.0;
+            for (int n = 0; n < p; ++n)
+                for (int m = -n; m <= n; ++m) acc += M[HIDX(n, m)] * hget(Ih, n + j, m + s);
+            L[HIDX(j, s)] += sj * acc;
+        }
+    }
+}
+
+/* L2L (Section II.A): with t = t' + d (d = c_child - c_parent),
+ * conj(R_j^s(t)) = sum_{k,l} conj(R_k^l(t')) conj(R_{j-k}^{s-l}(d)), so
+ *   L'_k^l += sum_{j>=k,s} L_j^s conj(R_{j-k}^{s-l}(d)).                    */
+static void l2l_add(const cplx *Lp, const double cpar[3], const double cch[3], int p, cplx *Lc)
+{
+    cplx Rh[ORC_MAXP * ORC_MAXP];
+    double d[3] = {cch[0] - cpar[0], cch[1] - cpar[1], cch[2] - cpar[2]};
+    harmonics(d, p, Rh, NULL);
+    for (int k = 0; k < p; ++k)
+        for (int l = -k; l <= k; ++l) {
+            cplx s = 0.0;
+            for (int j = k; j < p; ++j)
+                for (int ss = -j; ss <= j; ++ss) s += Lp[HIDX(j, ss)] * conj(hget(Rh, j - k, ss - l));
+            Lc[HIDX(k, l)] += s;
+        }
+}
+
+/* L2P (Section II.A): phi(x) = sum_{j,s} L_j^s conj(R_j^s(x - c)) (real),
+ * E = -grad phi, using dR_n^m/dz = R_{n-1}^m,
+ * dR_n^m/dx = (R_{n-1}^{m+1} - R_{n-1}^{m-1})/2,
+ * dR_n^m/dy = -i (R_{n-1}^{m-1} + R_{n-1}^{m+1})/2.                        */
+static void l2p_eval(const cplx *L, const double c[3], int p, const double *x, double *phi, double *E)
+{
+    cplx Rh[ORC_MAXP * ORC_MAXP];
+    double v[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    harmonics(v, p, Rh, NULL);
+    cplx f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int j = 0; j < p; ++j)
+        for (int s = -j; s <= j; ++s) {
+            cplx Ljs = L[HIDX(j, s)];
+            f += Ljs * conj(hget(Rh, j, s));
+            if (j > 0) {
+                cplx dz = hget(Rh, j - 1, s);
+                cplx dx = 0.5 * (hget(Rh, j - 1, s + 1) - hget(Rh, j - 1, s - 1));
+                cplx dy = -0.5 * I * (hget(Rh, j - 1, s - 1) + hget(Rh, j - 1, s + 1));
+                gx += Ljs * conj(dx);
+                gy += Ljs * conj(dy);
+                gz += Ljs * conj(dz);
+            }
+        }
+    *phi = creal(f);
+    E[0] = -creal(gx);
+    E[1] = -creal(gy);
+    E[2] = -creal(gz);
+}
+
+/* Multipole series evaluated at x (for the pins): sum M_n^m I_n^m(x - c).  */
+static double m2p_eval(const cplx *M, const double c[3], int p, const double *x)
+{
+    cplx Ih[ORC_MAXP * ORC_MAXP];
+    double v[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    harmonics(v, p, NULL, Ih);
+    cplx f = 0.0;
+    for (int k = 0; k < p * p; ++k) f += M[k] * Ih[k];
+    return creal(f);
+}
+
+/* ---- exported single-operator entry points for the pins (interleaved
+ *      (re, im) doubles, p^2 complex coefficients) ---------------------- */
+static void to_c(const double *a, int k, cplx *z)
+{
+    for (int i = 0; i < k; ++i) z[i] = a[2 * i] + a[2 * i + 1] * I;
+}
+static void from_c(const cplx *z, int k, double *a)
+{
+    for (int i = 0; i < k; ++i) { a[2 * i] = creal(z[i]); a[2 * i + 1] = cimag(z[i]); }
+}
+
+void oracle_op_p2m(int64_t n, const double *x, const double *q, const double *c, int p, double *Mout)
+{
+    cplx M[ORC_MAXP * ORC_MAXP] = {0};
+    for (int64_t j = 0; j < n; ++j) p2m_add(x + 3 * j, q[j], c, p, M);
+    from_c(M, p * p, Mout);
+}
+double oracle_op_m2p(const double *Min, const double *c, int p, const double *x)
+{
+    cplx M[ORC_MAXP * ORC_MAXP];
+    to_c(Min, p * p, M);
+    return m2p_eval(M, c, p, x);
+}
+void oracle_op_m2m(const double *Min, const double *cch, const double *cpar, int p, double *Mout)
+{
+    cplx Mc[ORC_MAXP * ORC_MAXP], Mp[ORC_MAXP * ORC_MAXP] = {0};
+    to_c(Min, p * p, Mc);
+    m2m_add(Mc, cch, cpar, p, Mp);
+    from_c(Mp, p * p, Mout);
+}
+void oracle_op_m2l(const double *Min, const double *cB, const double *cA, int p, double *Lout)
+{
+    cplx M[ORC_MAXP * ORC_MAXP], L[ORC_MAXP * ORC_MAXP] = {0};
+    to_c(Min, p * p, M);
+    m2l_add(M, cB, cA, p, L);
+    from_c(L, p * p, Lout);
+}
+void oracle_op_l2l(const double *Lin, const double *cpar, const double *cch, int p, double *Lout)
+{
+    cplx Lp[ORC_MAXP * ORC_MAXP], Lc[ORC_MAXP * ORC_MAXP] = {0};
+    to_c(Lin, p * p, Lp);
+    l2l_add(Lp, cpar, cch, p, Lc);
+    from_c(Lc, p * p, Lout);
+}
+void oracle_op_l2p(const double *Lin, const double *c, int p, int64_t n, const double *x, double *phi, double *E)
+{
+    cplx L[ORC_MAXP * ORC_MAXP];
+    to_c(Lin, p * p, L);
+    for (int64_t i = 0; i < n; ++i) l2p_eval(L, c, p, x + 3 * i, phi + i, E + 3 * i);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local octree (Section II.B: Morton keys, 3 bits per level, 21 levels in a */
+/* 64-bit key; Section II.C: tree from the local bounding box).              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    int32_t ncrit;
+    double theta, t4;
+    double lo[3], S, scale;
+    uint64_t *key;    /* sorted keys            [n]  */
+    int32_t *perm;    /* sorted -> input index  [n]  */
+    int64_t ncell, nleaf;
+    int32_t depth;
+    int32_t *lvl, *beg, *end, *par, *cbeg, *nch;
+    uint64_t *ckey;
+    int32_t *ix;      /* lattice coordinates at the cell's own level [3*ncell] */
+    double *ctr;      /* lattice centers [3*ncell] */
+    /* lists (CSR by target cell; source ascending).  With a target subset only
+     * the target cells that matter are stored; the counts are always full.  */
+    int64_t n_m2l, n_p2p, n_m2l_stored, n_p2p_stored;
+    int64_t *m2l_off, *p2p_off;
+    int32_t *m2l_src, *p2p_src;
+    uint8_t *need;    /* target cell is an ancestor of (or is) a sampled leaf */
+} otree;
+
+typedef struct { uint64_t k; int64_t i; } kv;
+
+static int cmp_kv(const void *a, const void *b)
+{
+    const kv *x = (const kv *)a, *y = (const kv *)b;
+    if (x->k != y->k) return x->k < y->k ? -1 : 1;
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Key of one body (step T2): i_d = min(2^21 - 1, floor((x_d - lo_d) * scale)),
+ * bit b of i_x at key bit 3b+2, of i_y at 3b+1, of i_z at 3b.            */
+static uint64_t body_key(const double *x, const double lo[3], double scale)
+{
+    uint64_t c[3];
+    for (int d = 0; d < 3; ++d) {
+        double s = (x[d] - lo[d]) * scale;
+        double f = floor(s);
+        uint64_t v = f < 0.0 ? 0 : (uint64_t)f;
+        if (v > (1u << ORC_LEVELS) - 1) v = (1u << ORC_LEVELS) - 1;
+        c[d] = v;
+    }
+    uint64_t k = 0;
+    for (int b = 0; b < ORC_LEVELS; ++b) {
+        k |= ((c[0] >> b) & 1ull) << (3 * b + 2);
+        k |= ((c[1] >> b) & 1ull) << (3 * b + 1);
+        k |= ((c[2] >> b) & 1ull) << (3 * b);
+    }
+    return k;
+}
+
+/* Multipole acceptance (step T6): R_A + R_B < theta |c_A - c_B| with R the
+ * radius of the cube's bounding sphere, decided exactly on the lattice of
+ * half-units of the finer cell (see the tree documentation).               */
+static int mac(const otree *t, int a, int b)
+{
+    int la = t->lvl[a], lb = t->lvl[b];
+    int f = la > lb ? la : lb;
+    int64_t sa = (int64_t)1 << (f - la + 1), sb = (int64_t)1 << (f - lb + 1);
+    int64_t d2 = 0;
+    for (int d = 0; d < 3; ++d) {
+        int64_t ca = (2 * (int64_t)t->ix[3 * a + d] + 1) << (f - la);
+        int64_t cb = (2 * (int64_t)t->ix[3 * b + d] + 1) << (f - lb);
+        d2 += (ca - cb) * (ca - cb);
+    }
+    double lhs = (double)(3 * (sa + sb) * (sa + sb));
+    return lhs < t->t4 * (double)d2;
+}
+
+static int is_leaf(const otree *t, int c) { return t->nch[c] == 0; }
+
+/* ---- growable pair buffer ---- */
+typedef struct { uint64_t *v; int64_t n, cap; } pbuf;
+static void pb_push(pbuf *b, uint64_t x)
+{
+    if (b->n == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 1024;
+        b->v = (uint64_t *)realloc(b->v, (size_t)b->cap * sizeof(uint64_t));
+    }
+    b->v[b->n++] = x;
+}
+
+typedef struct { otree *t; pbuf m2l, p2p; } tctx;
+
+/* Dual tree traversal (step T7, Section II.C).  Pairs are packed as
+ * target << 32 | source.                                                    */
+static void interact(tctx *c, int a, int b)
+{
+    otree *t = c->t;
+    if (mac(t, a, b)) {
+        t->n_m2l++;
+        if (t->need[a]) pb_push(&c->m2l, ((uint64_t)a << 32) | (uint32_t)b);
+        return;
+    }
+    int la = is_leaf(t, a), lb = is_leaf(t, b);
+    if (la && lb) {
+        t->n_p2p++;
+        if (t->need[a]) pb_push(&c->p2p, ((uint64_t)a << 32) | (uint32_t)b);
+        return;
+    }
+    int split_a, split_b;
+    if (la) { split_a = 0; split_b = 1; }
+    else if (lb) { split_a = 1; split_b = 0; }
+    else if (t->lvl[a] < t->lvl[b]) { split_a = 1; split_b = 0; }
+    else if (t->lvl[b] < t->lvl[a]) { split_a = 0; split_b = 1; }
+    else { split_a = 1; split_b = 1; }
+    if (split_a && split_b) {
+        for (int i = 0; i < t->nch[a]; ++i)
+            for (int j = 0; j < t->nch[b]; ++j) interact(c, t->cbeg[a] + i, t->cbeg[b] + j);
+    } else if (split_a) {
+        for (int i = 0; i < t->nch[a]; ++i) interact(c, t->cbeg[a] + i, b);
+    } else {
+        for (int j = 0; j < t->nch[b]; ++j) interact(c, a, t->cbeg[b] + j);
+    }
+}
+
+static void csr_from_pairs(pbuf *b, int64_t ncell, int64_t **off, int32_t **src)
+{
+    qsort(b->v, (size_t)b->n, sizeof(uint64_t), cmp_u64);
+    *off = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    *src = (int32_t *)malloc((size_t)(b->n ? b->n : 1) * sizeof(int32_t));
+    for (int64_t k = 0; k < b->n; ++k) {
+        (*off)[(b->v[k] >> 32) + 1]++;
+        (*src)[k] = (int32_t)(b->v[k] & 0xffffffffu);
+    }
+    for (int64_t c = 0; c < ncell; ++c) (*off)[c + 1] += (*off)[c];
+    free(b->v);
+    b->v = NULL;
+}
+
+/* Build the tree and the lists.  targets (nt indices into the input order)
+ * restrict which target cells keep their lists: leaves holding a target and
+ * their ancestors.  targets == NULL keeps everything; nt < 0 keeps nothing
+ * (count only).  Returns NULL on invalid input.                            */
+void *oracle_tree_new(int64_t n, const double *x, int32_t ncrit, double theta,
+                      int64_t nt, const int64_t *targets)
+{
+    if (n <= 0 || !x || ncrit < 1 || !(theta > 0.0 && theta < 1.0)) return NULL;
+    otree *t = (otree *)calloc(1, sizeof(otree));
+    t->n = n;
+    t->ncrit = ncrit;
+    t->theta = theta;
+    t->t4 = 4.0 * theta * theta;
+
+    /* T1: root cube anchored at the per-axis minima, side = largest extent. */
+    double hi[3];
+    for (int d = 0; d < 3; ++d) { t->lo[d] = x[d]; hi[d] = x[d]; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            if (x[3 * i + d] < t->lo[d]) t->lo[d] = x[3 * i + d];
+            if (x[3 * i + d] > hi[d]) hi[d] = x[3 * i + d];
+        }
+    t->S = 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (hi[d] - t->lo[d] > t->S) t->S = hi[d] - t->lo[d];
+    if (t->S == 0.0) t->S = 1.0;
+    t->scale = ldexp(1.0, ORC_LEVELS) / t->S;
+
+    /* T2 + T3: keys, stable sort with ties broken by input index. */
+    kv *a = (kv *)malloc((size_t)n * sizeof(kv));
+    for (int64_t i = 0; i < n; ++i) { a[i].k = body_key(x + 3 * i, t->lo, t->scale); a[i].i = i; }
+    qsort(a, (size_t)n, sizeof(kv), cmp_kv);
+    t->key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    t->perm = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) { t->key[i] = a[i].k; t->perm[i] = (int32_t)a[i].i; }
+    free(a);
+
+    /* T4: cells in breadth-first order, which is (level, key) order. */
+    int64_t cap = 1024;
+    t->lvl = (int32_t *)malloc(cap * sizeof(int32_t));
+    t->beg = (int32_t *)malloc(cap * sizeof(int32_t));
+    t->end = (int32_t *)malloc(cap * sizeof(int32_t));
+    t->par = (int32_t *)malloc(cap * sizeof(int32_t));
+    t->cbeg = (int32_t *)malloc(cap * sizeof(int32_t));
+    t->nch = (int32_t *)malloc(cap * sizeof(int32_t));
+    t->ckey = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    int64_t nc = 1;
+    t->lvl[0] = 0; t->beg[0] = 0; t->end[0] = (int32_t)n; t->par[0] = -1; t->ckey[0] = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        int l = t->lvl[c];
+        t->cbeg[c] = -1;
+        t->nch[c] = 0;
+        if (!(t->end[c] - t->beg[c] > ncrit && l < ORC_LEVELS)) continue;
+        int shift = 3 * (ORC_LEVELS - l - 1);
+        int64_t i = t->beg[c];
+        while (i < t->end[c]) {
+            uint64_t ck = t->key[i] >> shift;
+            int64_t j = i;
+            while (j < t->end[c] && (t->key[j] >> shift) == ck) ++j;
+            if (nc == cap) {
+                cap *= 2;
+                t->lvl = (int32_t *)realloc(t->lvl, cap * sizeof(int32_t));
+                t->beg = (int32_t *)realloc(t->beg, cap * sizeof(int32_t));
+                t->end = (int32_t *)realloc(t->end, cap * sizeof(int32_t));
+                t->par = (int32_t *)realloc(t->par, cap * sizeof(int32_t));
+                t->cbeg = (int32_t *)realloc(t->cbeg, cap * sizeof(int32_t));
+                t->nch = (int32_t *)realloc(t->nch, cap * sizeof(int32_t));
+                t->ckey = (uint64_t *)realloc(t->ckey, cap * sizeof(uint64_t));
+            }
+            if (t->nch[c] == 0) t->cbeg[c] = (int32_t)nc;
+            t->nch[c]++;
+            t->lvl[nc] = l + 1; t->beg[nc] = (int32_t)i; t->end[nc] = (int32_t)j;
+            t->par[nc] = (int32_t)c; t->ckey[nc] = ck;
+            ++nc;
+            i = j;
+        }
+    }
+    t->ncell = nc;
+    t->nleaf = 0;
+    t->depth = 0;
+    for (int64_t c = 0; c < nc; ++c) {
+        if (t->nch[c] == 0) t->nleaf++;
+        if (t->lvl[c] > t->depth) t->depth = t->lvl[c];
+    }
+
+    /* T5: lattice coordinates and centers c_d = lo_d + (i_d + 1/2) h_l. */
+    t->ix = (int32_t *)malloc((size_t)nc * 3 * sizeof(int32_t));
+    t->ctr = (double *)malloc((size_t)nc * 3 * sizeof(double));
+    for (int64_t c = 0; c < nc; ++c) {
+        uint64_t k = t->ckey[c];
+        int l = t->lvl[c];
+        int32_t v[3] = {0, 0, 0};
+        for (int b = 0; b < l; ++b) {
+            v[0] |= (int32_t)(((k >> (3 * b + 2)) & 1ull) << b);
+            v[1] |= (int32_t)(((k >> (3 * b + 1)) & 1ull) << b);
+            v[2] |= (int32_t)(((k >> (3 * b)) & 1ull) << b);
+        }
+        double h = ldexp(t->S, -l);
+        for (int d = 0; d < 3; ++d) {
+            t->ix[3 * c + d] = v[d];
+            double off = ((double)v[d] + 0.5) * h;
+            t->ctr[3 * c + d] = t->lo[d] + off;
+        }
+    }
+
+    /* Which target cells keep lists. */
+    t->need = (uint8_t *)calloc((size_t)nc, 1);
+    if (!targets && nt >= 0) {
+        memset(t->need, 1, (size_t)nc);
+    } else if (targets && nt > 0) {
+        int32_t *leaf_of = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+        for (int64_t c = 0; c < nc; ++c)
+            if (t->nch[c] == 0)
+                for (int32_t i = t->beg[c]; i < t->end[c]; ++i) leaf_of[t->perm[i]] = (int32_t)c;
+        for (int64_t s = 0; s < nt; ++s)
+            for (int32_t c = leaf_of[targets[s]]; c >= 0; c = t->par[c]) t->need[c] = 1;
+        free(leaf_of);
+    }
+
+    /* T7: lists. */
+    tctx cx = {t, {0}, {0}};
+    interact(&cx, 0, 0);
+    t->n_m2l_stored = cx.m2l.n;
+    t->n_p2p_stored = cx.p2p.n;
+    csr_from_pairs(&cx.m2l, nc, &t->m2l_off, &t->m2l_src);
+    csr_from_pairs(&cx.p2p, nc, &t->p2p_off, &t->p2p_src);
+    return t;
+}
+
+void oracle_tree_free(void *h)
+{
+    otree *t = (otree *)h;
+    if (!t) return;
+    free(t->key); free(t->perm);
+    free(t->lvl); free(t->beg); free(t->end); free(t->par); free(t->cbeg); free(t->nch); free(t->ckey);
+    free(t->ix); free(t->ctr); free(t->need);
+    free(t->m2l_off); free(t->m2l_src); free(t->p2p_off); free(t->p2p_src);
+    free(t);
+}
+
+/* info: [ncell, nleaf, depth, n_m2l, n_p2p, n_m2l_stored, n_p2p_stored]
+ * box:  [lo_x, lo_y, lo_z, S, scale]                                      */
+void oracle_tree_info(const void *h, int64_t *info, double *box)
+{
+    const otree *t = (const otree *)h;
+    if (info) {
+        info[0] = t->ncell; info[1] = t->nleaf; info[2] = t->depth;
+        info[3] = t->n_m2l; info[4] = t->n_p2p;
+        info[5] = t->n_m2l_stored; info[6] = t->n_p2p_stored;
+    }
+    if (box) {
+        for (int d = 0; d < 3; ++d) box[d] = t->lo[d];
+        box[3] = t->S;
+        box[4] = t->scale;
+    }
+}
+
+/* Any pointer may be NULL.  Lists are exported as (target, source) pairs in
+ * canonical (target, source) order.                                        */
+void oracle_tree_export(const void *h, uint64_t *keys, int32_t *perm, int32_t *lvl, uint64_t *ckey,
+                        int32_t *beg, int32_t *end, int32_t *par, int32_t *cbeg, int32_t *nch,
+                        double *centers, int32_t *m2l, int32_t *p2p)
+{
+    const otree *t = (const otree *)h;
+    if (keys) memcpy(keys, t->key, (size_t)t->n * sizeof(uint64_t));
+    if (perm) memcpy(perm, t->perm, (size_t)t->n * sizeof(int32_t));
+    if (lvl) memcpy(lvl, t->lvl, (size_t)t->ncell * sizeof(int32_t));
+    if (ckey) memcpy(ckey, t->ckey, (size_t)t->ncell * sizeof(uint64_t));
+    if (beg) memcpy(beg, t->beg, (size_t)t->ncell * sizeof(int32_t));
+    if (end) memcpy(end, t->end, (size_t)t->ncell * sizeof(int32_t));
+    if (par) memcpy(par, t->par, (size_t)t->ncell * sizeof(int32_t));
+    if (cbeg) memcpy(cbeg, t->cbeg, (size_t)t->ncell * sizeof(int32_t));
+    if (nch) memcpy(nch, t->nch, (size_t)t->ncell * sizeof(int32_t));
+    if (centers) memcpy(centers, t->ctr, (size_t)t->ncell * 3 * sizeof(double));
+    if (m2l)
+        for (int64_t c = 0; c < t->ncell; ++c)
+            for (int64_t k = t->m2l_off[c]; k < t->m2l_off[c + 1]; ++k) {
+                m2l[2 * k] = (int32_t)c;
+                m2l[2 * k + 1] = t->m2l_src[k];
+            }
+    if (p2p)
+        for (int64_t c = 0; c < t->ncell; ++c)
+            for (int64_t k = t->p2p_off[c]; k < t->p2p_off[c + 1]; ++k) {
+                p2p[2 * k] = (int32_t)c;
+                p2p[2 * k + 1] = t->p2p_src[k];
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* FMM evaluation on a built tree (steps T8-T10).                            */
+/* ------------------------------------------------------------------------ */
+
+/* xpos == NULL: the coordinates the tree was built from.  Otherwise the
+ * bodies sit at xpos (input order) while the tree, centers and lists stay
+ * frozen (used for finite differences of the frozen-tree FMM).
+ * targets == NULL: all bodies, outputs in input order; else nt targets, which
+ * must be a subset of the targets the tree was built for.                  */
+int oracle_fmm_at(const void *h, const double *xpos, const double *q, int p,
+                  int64_t nt, const int64_t *targets, double *phi, double *field)
+{
+    const otree *t = (const otree *)h;
+    if (!t || !q || p < 1 || p > ORC_MAXP) return 1;
+    const int64_t n = t->n, nc = t->ncell;
+    const int P2 = p * p;
+    (void)n;
+    /* Sorted body coordinates. */
+    double *xs = (double *)malloc((size_t)t->n * 3 * sizeof(double));
+    double *qs = (double *)malloc((size_t)t->n * sizeof(double));
+    if (!xpos) return (free(xs), free(qs), 2);
+    for (int64_t i = 0; i < t->n; ++i) {
+        int32_t o = t->perm[i];
+        for (int d = 0; d < 3; ++d) xs[3 * i + d] = xpos[3 * (int64_t)o + d];
+        qs[i] = q[o];
+    }
+    cplx *M = (cplx *)calloc((size_t)nc * P2, sizeof(cplx));
+    cplx *L = (cplx *)calloc((size_t)nc * P2, sizeof(cplx));
+
+    /* Upward pass (Section II.C): P2M at leaves, then M2M from the finest
+     * level up; each parent gathers its children in order.                 */
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t c = 0; c < nc; ++c)
+        if (t->nch[c] == 0)
+            for (int32_t i = t->beg[c]; i < t->end[c]; ++i) p2m_add(xs + 3 * (int64_t)i, qs[i], t->ctr + 3 * c, p, M + c * P2);
+    for (int l = t->depth - 1; l >= 0; --l) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t c = 0; c < nc; ++c) {
+            if (t->lvl[c] != l || t->nch[c] == 0) continue;
+            for (int k = 0; k < t->nch[c]; ++k) {
+                int64_t ch = t->cbeg[c] + k;
+                m2m_add(M + ch * P2, t->ctr + 3 * ch, t->ctr + 3 * c, p, M + c * P2);
+            }
+        }
+    }
+
+    /* M2L over each (kept) target cell's list, sources ascending. */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t c = 0; c < nc; ++c)
+        for (int64_t k = t->m2l_off[c]; k < t->m2l_off[c + 1]; ++k) {
+            int64_t s = t->m2l_src[k];
+            m2l_add(M + s * P2, t->ctr + 3 * s, t->ctr + 3 * c, p, L + c * P2);
+        }
+
+    /* Downward pass: L2L from the root down. */
+    for (int l = 1; l <= t->depth; ++l) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t c = 0; c < nc; ++c) {
+            if (t->lvl[c] != l || !t->need[c]) continue;
+            int64_t pa = t->par[c];
+            l2l_add(L + pa * P2, t->ctr + 3 * pa, t->ctr + 3 * c, p, L + c * P2);
+        }
+    }
+
+    /* Targets: sorted position -> leaf. */
+    int32_t *leaf_of_sorted = (int32_t *)malloc((size_t)t->n * sizeof(int32_t));
+    int32_t *inv = (int32_t *)malloc((size_t)t->n * sizeof(int32_t));
+    for (int64_t c = 0; c < nc; ++c)
+        if (t->nch[c] == 0)
+            for (int32_t i = t->beg[c]; i < t->end[c]; ++i) leaf_of_sorted[i] = (int32_t)c;
+    for (int64_t i = 0; i < t->n; ++i) inv[t->perm[i]] = (int32_t)i;
+
+    int64_t ntg = targets ? nt : t->n;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t s = 0; s < ntg; ++s) {
+        int64_t orig = targets ? targets[s] : s;
+        int64_t i = inv[orig];
+        int64_t c = leaf_of_sorted[i];
+        if (!t->need[c]) { bad |= 1; continue; }
+        const double *xi = xs + 3 * i;
+        /* P2P (Section II.A): source leaves ascending, bodies in sorted order. */
+        double pp = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int64_t k = t->p2p_off[c]; k < t->p2p_off[c + 1]; ++k) {
+            int64_t b = t->p2p_src[k];
+            for (int32_t j = t->beg[b]; j < t->end[b]; ++j) {
+                double dx = xi[0] - xs[3 * (int64_t)j], dy = xi[1] - xs[3 * (int64_t)j + 1], dz = xi[2] - xs[3 * (int64_t)j + 2];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0) continue;
+                double r = sqrt(r2);
+                double qr = qs[j] / r;
+                double qr3 = qr / r2;
+                pp += qr;
+                ex += qr3 * dx;
+                ey += qr3 * dy;
+                ez += qr3 * dz;
+            }
+        }
+        /* L2P. */
+        double lp, E[3];
+        l2p_eval(L + c * P2, t->ctr + 3 * c, p, xi, &lp, E);
+        if (phi) phi[s] = lp + pp;
+        if (field) {
+            field[3 * s] = E[0] + ex;
+            field[3 * s + 1] = E[1] + ey;
+            field[3 * s + 2] = E[2] + ez;
+        }
+    }
+    free(leaf_of_sorted);
+    free(inv);
+    free(xs);
+    free(qs);
+    free(M);
+    free(L);
+    return bad ? 3 : 0;
+}
+
+/* Convenience: one-shot FMM at the coordinates the tree was built from.   */
+int oracle_fmm(const void *h, const double *x, const double *q, int p, int64_t nt,
+               const int64_t *targets, double *phi, double *field)
+{
+    return oracle_fmm_at(h, x, q, p, nt, targets, phi, field);
+}
+
+/* For the a priori error bound: per M2L pair the ratio pieces are computed
+ * by the tests from the exported lists and centers; nothing else needed.   */
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

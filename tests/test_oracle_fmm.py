@@ -1,0 +1,181 @@
+"""Pins of the oracle's whole FMM evaluation.
+
+* With N_crit >= N the tree is one leaf and the FMM is the direct sum.
+* The error against the direct sum stays inside the a priori bound of the
+  truncated expansions (error O(theta^P), Section III.A), target by target.
+* Error falls monotonically with the expansion order P.
+* Energy symmetry, power-of-two scaling, axis permutation invariance.
+* Target-subset mode equals the full evaluation bit for bit; the result does
+  not depend on the OpenMP thread count.
+* Frozen-tree finite differences of L = sum_i w_i phi_i equal
+  -(w E^q + q E^w), the adjoint the GPU implements.
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1405_7487_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_single_leaf_fmm_is_the_direct_sum():
+    x, q, _ = W.uniform_cube(700, 5)
+    x[-3:] = x[:3]
+    T = oracle.Tree(x, 700, 0.4)
+    assert T.ncell == 1 and T.n_p2p == 1 and T.n_m2l == 0
+    phi, E = T.fmm(q, 4)
+    pd, Ed = oracle.direct(x, q)
+    assert rel(phi, pd) < 1e-14 and rel(E, Ed) < 1e-14
+
+
+def _a_priori_bound(x, q, T, e, p, targets):
+    """Per-target bounds on |phi_fmm - phi_direct| and |E_fmm - E_direct|."""
+    perm, beg, end, par = e["perm"], e["begin"], e["end"], e["parent"]
+    ctr = e["centers"]
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    leaf_of = np.empty(perm.size, np.int64)
+    for c in np.nonzero(e["nchild"] == 0)[0]:
+        leaf_of[beg[c]:end[c]] = c
+    off = np.zeros(T.ncell + 1, np.int64)
+    np.add.at(off, e["m2l"][:, 0] + 1, 1)
+    off = np.cumsum(off)
+    src = e["m2l"][:, 1]
+    bphi = np.zeros(len(targets))
+    bE = np.zeros(len(targets))
+    for k, i in enumerate(targets):
+        c = leaf_of[inv[i]]
+        while c >= 0:
+            ri = np.linalg.norm(x[i] - ctr[c])
+            for b in src[off[c]:off[c + 1]]:
+                d = np.linalg.norm(ctr[c] - ctr[b])
+                js = perm[beg[b]:end[b]]
+                rj = np.linalg.norm(x[js] - ctr[b], axis=1)
+                th = (ri + rj) / d
+                assert np.all(th < 1.0)
+                aq = np.abs(q[js])
+                bphi[k] += np.sum(aq * th ** p / (d * (1 - th)))
+                bE[k] += np.sum(aq * (p * th ** (p - 1) / (1 - th) + th ** p / (1 - th) ** 2)) / d ** 2
+            c = par[c]
+    return bphi, bE
+
+
+@pytest.mark.parametrize("case", ["cube16k", "plummer"])
+def test_error_within_a_priori_bound(case):
+    if case == "cube16k":
+        x, q, _ = W.make_config("cube16k")
+        ncrit, theta, p = 64, 0.4, 4
+    else:
+        x, q, _ = W.plummer(6000, 1)
+        q = np.random.default_rng(2).uniform(-1, 1, 6000)
+        ncrit, theta, p = 16, 0.35, 5
+    tg = W.sample_targets(x.shape[0], 150)
+    T = oracle.Tree(x, ncrit, theta, targets=tg)
+    e = T.export()
+    phi, E = T.fmm(q, p, targets=tg)
+    pd, Ed = oracle.direct(x, q, targets=tg)
+    bphi, bE = _a_priori_bound(x, q, T, e, p, tg)
+    slack = 1e-12 * (np.abs(pd) + 1)
+    assert np.all(np.abs(phi - pd) <= bphi + slack)
+    assert np.all(np.linalg.norm(E - Ed, axis=1) <= bE + 1e-12 * (np.linalg.norm(Ed, axis=1) + 1))
+    # the bound is not vacuous: the error is a visible fraction of it
+    has = bphi > 0
+    assert np.max(np.abs(phi - pd)[has] / bphi[has]) > 1e-3
+
+
+def test_error_falls_monotonically_with_p():
+    x, q, _ = W.uniform_cube(4096, 11)
+    T = oracle.Tree(x, 32, 0.4)
+    pd, Ed = oracle.direct(x, q)
+    errs = []
+    for p in range(2, 15):
+        phi, E = T.fmm(q, p)
+        errs.append((rel(phi, pd), rel(E, Ed)))
+    ep = [a for a, _ in errs]
+    eE = [b for _, b in errs]
+    assert all(ep[k + 1] < ep[k] for k in range(len(ep) - 1)), ep
+    assert all(eE[k + 1] < eE[k] for k in range(len(eE) - 1)), eE
+    assert ep[-1] < 1e-10
+
+
+def test_energy_symmetry():
+    x, q, rng = W.uniform_cube(3000, 12)
+    w = W.adjoint_weights(rng, 3000)
+    T = oracle.Tree(x, 24, 0.4)
+    pq, _ = T.fmm(q, 6)
+    pw, _ = T.fmm(w, 6)
+    assert abs(w @ pq - q @ pw) < 1e-13 * (np.abs(w) @ np.abs(pq))
+
+
+def test_scaling_and_axis_permutation():
+    x, q, _ = W.plummer(3000, 4)
+    q = np.random.default_rng(4).uniform(-1, 1, 3000)
+    T = oracle.Tree(x, 16, 0.4)
+    phi, E = T.fmm(q, 6)
+    T2 = oracle.Tree(2.0 * x, 16, 0.4)
+    phi2, E2 = T2.fmm(q, 6)
+    assert rel(phi2, phi / 2) < 1e-14 and rel(E2, E / 4) < 1e-14
+    xp = x[:, [1, 2, 0]]
+    T3 = oracle.Tree(xp, 16, 0.4)
+    assert (T3.ncell, T3.n_m2l, T3.n_p2p) == (T.ncell, T.n_m2l, T.n_p2p)
+    phi3, E3 = T3.fmm(q, 6)
+    assert rel(phi3, phi) < 1e-13 and rel(E3[:, [2, 0, 1]], E) < 1e-13
+
+
+def test_target_subset_is_bit_identical_to_full():
+    x, q, _ = W.plummer(5000, 6)
+    T = oracle.Tree(x, 16, 0.4)
+    phi, E = T.fmm(q, 5)
+    tg = W.sample_targets(5000, 300)
+    Ts = oracle.Tree(x, 16, 0.4, targets=tg)
+    assert Ts.n_m2l == T.n_m2l and Ts.n_m2l_stored < T.n_m2l
+    ps, Es = Ts.fmm(q, 5, targets=tg)
+    assert np.array_equal(ps, phi[tg]) and np.array_equal(Es, E[tg])
+
+
+def test_thread_count_does_not_change_bits():
+    code = (
+        "import sys,numpy as np; sys.path.insert(0, %r); import oracle;"
+        "from paper_1405_7487_amd import workloads as W;"
+        "x,q,_=W.plummer(4000,8); T=oracle.Tree(x,12,0.4); p,E=T.fmm(q,6);"
+        "sys.stdout.write(p.tobytes().hex()[:4000]+E.tobytes().hex()[-4000:])" % ROOT
+    )
+    outs = []
+    for nt in ("1", "4"):
+        env = dict(os.environ, OMP_NUM_THREADS=nt)
+        outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                                   text=True, check=True).stdout)
+    assert outs[0] == outs[1] and len(outs[0]) == 8000
+
+
+def test_frozen_tree_finite_differences_equal_adjoint():
+    x, q, rng = W.uniform_cube(2000, 13)
+    w = W.adjoint_weights(rng, 2000)
+    p = 6
+    T = oracle.Tree(x, 16, 0.4)
+    _, Eq = T.fmm(q, p)
+    _, Ew = T.fmm(w, p)
+    g_adj = -(w[:, None] * Eq + q[:, None] * Ew)
+    # coordinates away from close neighbours keep the O(h^2) term small
+    from scipy.spatial import cKDTree
+    dmin = cKDTree(x).query(x, 2)[0][:, 1]
+    cand = np.nonzero(dmin > 0.04)[0]
+    sel = np.random.default_rng(1).choice(cand, 8, replace=False)
+    h = 1e-5
+    for k in sel:
+        for d in range(3):
+            xp = x.copy(); xp[k, d] += h
+            xm = x.copy(); xm[k, d] -= h
+            Lp = w @ T.fmm(q, p, x=xp)[0]
+            Lm = w @ T.fmm(q, p, x=xm)[0]
+            g = (Lp - Lm) / (2 * h)
+            assert abs(g - g_adj[k, d]) < 1e-5 * (1 + abs(g_adj[k, d])), (k, d, g, g_adj[k, d])
