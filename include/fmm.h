@@ -1,0 +1,198 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) fast multipole library.
+ *
+ * The library evaluates, on one GPU, the per-rank part of the fast multipole
+ * method of AbdulJabbar, Yokota & Keyes, "Asynchronous Execution of the Fast
+ * Multipole Method Using Charm++" (arXiv 1405.7487): for N bodies with
+ * coordinates x and charges q it returns the Laplace potential and field
+ *
+ *     phi_i = sum_{j: x_j != x_i} q_j / |x_i - x_j|,
+ *     E_i   = -grad_i phi_i = sum_j q_j (x_i - x_j) / |x_i - x_j|^3,
+ *
+ * approximated with the paper's six operators P2M, M2M, M2L, L2L, L2P and
+ * P2P (Section II.A), a local octree built from the rank's own bounding box
+ * with 64-bit Morton keys (Section II.B), an upward pass, a dual tree
+ * traversal and a downward pass (Section II.C), under the parameters P
+ * (expansion order), theta (acceptance criterion) and N_crit (maximum bodies
+ * per leaf) of Table I.  Expansions are solid spherical harmonics of degree
+ * n < p; the error falls as O(theta^p) (Section III.A).  The kernel carries
+ * no 1/(4 pi) factor and coincident bodies do not interact.
+ *
+ * Conventions for every entry point
+ *   - All array arguments are DEVICE pointers on the current HIP device,
+ *     contiguous, in the caller's original body order.  x and field are
+ *     N x 3 row-major; q, phi, grad_phi, dq are length N; dx is N x 3.
+ *   - The element type of every caller array is given by fmm_dtype (float64
+ *     or float32).  Tree geometry is always computed in float64; float32
+ *     coordinates are widened exactly.
+ *   - The caller owns every array it passes.  The library never keeps a
+ *     caller pointer after a call returns.  A plan owns its internal device
+ *     buffers, obtained through the fmm_allocator given to fmm_build (or an
+ *     internal caching pool when that pointer is NULL) and released by
+ *     fmm_destroy.
+ *   - Work is enqueued on hip_stream (a hipStream_t; NULL = default stream).
+ *     fmm_build synchronises that stream, because the tree's sizes depend on
+ *     the data.  fmm_evaluate_plan and fmm_adjoint are asynchronous.
+ *   - Every entry point returns a status; no C++ exception crosses the ABI.
+ *     fmm_last_error() returns a thread-local message about the last failure.
+ *   - Calls on one plan must not overlap; distinct plans are independent.
+ */
+#ifndef FMM_H_
+#define FMM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define FMM_API __attribute__((visibility("default")))
+#else
+#define FMM_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_ERR_INVALID = 1,     /* bad argument: NULL pointer, n < 0, p, theta or ncrit out of range */
+    FMM_ERR_NOMEM = 2,       /* an allocation failed; everything already allocated was released   */
+    FMM_ERR_DEVICE = 3,      /* a HIP runtime call failed                                        */
+    FMM_ERR_UNSUPPORTED = 4, /* n >= 2^31 (indices are 32-bit) or a list would overflow         */
+    FMM_ERR_NONFINITE = 5    /* a coordinate is NaN or infinite                                  */
+} fmm_status;
+
+typedef enum { FMM_F64 = 0, FMM_F32 = 1 } fmm_dtype;
+
+typedef enum {
+    FMM_PREC_FP64 = 0,  /* every stage in float64 (the plain FP64 GPU FMM)                       */
+    FMM_PREC_MIXED = 1  /* P2P, P2M, L2P and the bulk of M2L in float32 with float32 accumulation;
+                           float64 for M2M/L2L and coefficient accumulation at coarse levels      */
+} fmm_precision;
+
+/* Method parameters (Table I: P, theta, N_crit). */
+typedef struct {
+    int32_t p;                  /* expansion order: degrees 0 <= n < p, 1 <= p <= 16             */
+    double theta;               /* acceptance: R_A + R_B < theta |c_A - c_B|, 0 < theta < 1,
+                                   R = radius of the cell's bounding sphere                      */
+    int32_t ncrit;              /* a cell holding more than ncrit bodies is split (>= 1)         */
+    int32_t precision;          /* fmm_precision                                                 */
+    int32_t coarse_fp64_levels; /* MIXED: levels 0 .. coarse_fp64_levels-1 keep float64
+                                   multipole/local coefficients and translations (default 3)    */
+    int32_t kahan;              /* MIXED: compensated P2P sums across source batches (default 1) */
+} fmm_params;
+
+/* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3, kahan=1. */
+FMM_API void fmm_params_default(fmm_params *prm);
+
+/* Device memory provider.  alloc returns a device pointer of at least `bytes`
+ * bytes usable on `stream`, or NULL on failure; free returns it.  Both are
+ * called from the thread that calls the library. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} fmm_allocator;
+
+typedef struct fmm_plan fmm_plan; /* opaque: tree, lists, operators, buffers */
+
+/* Counts and timings of a plan (host struct filled by fmm_plan_stats). */
+typedef struct {
+    int64_t n, ncell, nleaf;
+    int32_t depth, p;
+    int64_t n_m2l;           /* all M2L pairs                                  */
+    int64_t n_m2l_same;      /* M2L pairs between cells of one level            */
+    int64_t n_m2l_cross;     /* M2L pairs between cells of different levels     */
+    int64_t n_p2p;           /* P2P leaf pairs                                 */
+    int64_t p2p_body_pairs;  /* sum over P2P pairs of |A| * |B|                */
+    int64_t m2l_stencil;     /* same-level offsets per target octant class     */
+    int64_t m2l_offsets;     /* distinct same-level offsets (operators)        */
+    int64_t m2l_slots;       /* slot entries scanned by the batched M2L         */
+    int64_t device_bytes;    /* bytes held by the plan                          */
+    /* milliseconds of the last call, per phase (HIP events on the stream) */
+    double ms_build, ms_sort, ms_traverse;
+    double ms_p2m, ms_m2m, ms_m2l, ms_l2l, ms_l2p, ms_p2p, ms_evaluate, ms_adjoint;
+} fmm_stats;
+
+/* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are
+ * (target, source) cell pairs in ascending (target, source) order. */
+typedef struct {
+    uint64_t *keys;      /* [n] sorted Morton keys                           */
+    int32_t *perm;       /* [n] sorted position -> original body index       */
+    int32_t *level;      /* [ncell] cells in (level, key) order              */
+    uint64_t *cell_key;  /* [ncell] key >> 3*(21 - level)                    */
+    int32_t *begin, *end;/* [ncell] body range in sorted order               */
+    int32_t *parent;     /* [ncell] -1 for the root                          */
+    int32_t *child_begin;/* [ncell] first child (children are contiguous)    */
+    int32_t *nchild;     /* [ncell]                                          */
+    double *centers;     /* [3*ncell] lattice centers                        */
+    int32_t *m2l;        /* [2*n_m2l]                                        */
+    int32_t *p2p;        /* [2*n_p2p]                                        */
+} fmm_tree_export;
+
+/* Builds the tree, the interaction lists and the work schedule for the
+ * coordinates x (N x 3, dtype).  Steps: root cube from the local bounding
+ * box; 21-bit lattice coordinates and 64-bit Morton keys (Section II.B);
+ * stable radix sort; cells split while they hold more than ncrit bodies;
+ * lattice centers; dual tree traversal emitting M2L and P2P pairs (Section
+ * II.C).  Synchronises hip_stream.  On success *out holds a plan that must be
+ * released with fmm_destroy.  n == 0 gives a valid empty plan.
+ * Errors: FMM_ERR_INVALID (x or out NULL with n > 0, n < 0, bad params),
+ * FMM_ERR_UNSUPPORTED (n >= 2^31), FMM_ERR_NONFINITE, FMM_ERR_NOMEM,
+ * FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params *prm,
+                     const fmm_allocator *alloc, void *hip_stream, fmm_plan **out);
+
+/* Evaluates potential and field for charges q (length N, the plan's dtype)
+ * on the plan's tree: P2M, M2M (upward pass), M2L, L2L, L2P and P2P, then
+ * scatters the results to the caller's order.  phi (length N) is required;
+ * field (N x 3) may be NULL.  Asynchronous on hip_stream.
+ * Errors: FMM_ERR_INVALID (NULL plan/q/phi), FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_evaluate_plan(fmm_plan *plan, const void *q, void *phi, void *field, void *hip_stream);
+
+/* One call = fmm_build + fmm_evaluate_plan + fmm_destroy, with the method
+ * parameters given as scalars (kahan on, coarse_fp64_levels 3). */
+FMM_API fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t p,
+                        double theta, int32_t ncrit, int32_t precision, const fmm_allocator *alloc,
+                        void *phi, void *field, void *hip_stream);
+
+/* Adjoint of L = sum_i w_i phi_i with w = grad_phi.  The plan's lists are
+ * symmetric, so the FMM operator is symmetric and
+ *     dL/dq = FMM potential with charges w,
+ *     dL/dx = -(w * E^q + q * E^w)   (E^q, E^w: FMM fields of q and of w).
+ * field_q is E^q from the forward call (N x 3) or NULL, in which case it is
+ * recomputed on the same tree.  dq (N) and dx (N x 3) are outputs; either may
+ * be NULL.  Asynchronous on hip_stream.
+ * Errors: FMM_ERR_INVALID (NULL plan/q/grad_phi), FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_adjoint(fmm_plan *plan, const void *q, const void *grad_phi, const void *field_q,
+                       void *dq, void *dx, void *hip_stream);
+
+/* Copies counts and the last per-phase timings into *out (host). */
+FMM_API fmm_status fmm_plan_stats(const fmm_plan *plan, fmm_stats *out);
+
+/* Copies the tree and the canonical lists to host buffers (synchronises the
+ * plan's stream). */
+FMM_API fmm_status fmm_export_tree(const fmm_plan *plan, const fmm_tree_export *out);
+
+/* Per-phase event timing on (1) or off (0, default).  Timing adds one event
+ * pair per phase to the stream. */
+FMM_API fmm_status fmm_set_timing(fmm_plan *plan, int32_t on);
+
+/* Releases the plan and its device buffers (synchronises its stream). NULL is a no-op. */
+FMM_API void fmm_destroy(fmm_plan *plan);
+
+/* Thread-local description of the last failure ("" if none). */
+FMM_API const char *fmm_last_error(void);
+
+/* Diagnostic of the matrix-core lane layout the batched M2L relies on: runs
+ * one 16x16x4 MFMA on the current device (f64 != 0: float64, else float32)
+ * with A[i][k] = i + 1 + 100 k, B[0][j] = 1 + 1000 j, B[k>0][j] = 0 and copies
+ * the 64 lanes x 4 accumulators (lane-major; 256 floats or doubles) to the
+ * HOST buffer out_host.  Expected: lane l, slot e holds (i + 1)(1 + 1000 j)
+ * with i = 4 (l / 16) + e, j = l % 16.  Errors: FMM_ERR_INVALID, FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_debug_mfma_layout(int32_t f64, void *out_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H_ */

@@ -1,0 +1,166 @@
+// internal.hpp -- shared declarations of the gfx950 FMM library (not installed).
+//
+// Layout of the data in HBM (one plan):
+//   bodies   : sorted by Morton key; float4/double4 (u_x, u_y, u_z, q) with u
+//              the offset from the body's leaf center (small magnitudes keep
+//              float32 differences accurate deep in the tree)
+//   cells    : structure of arrays in (level, key) order; a level is a
+//              contiguous index range
+//   coefs    : per cell P2pad = roundup(p^2, 16) reals, real solid-harmonic
+//              basis scaled per level (multipole / h^n, local * h^{n+1})
+//   lists    : same-level M2L as a slot table [tile][k][64] (source cell of
+//              stencil entry k for each of 64 targets of one octant class);
+//              cross-level M2L and P2P as CSR by target cell
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+constexpr int kLevels = 21;       // 64-bit Morton key: 3 bits x 21 levels
+constexpr int kTileW = 64;        // targets per batched-M2L tile
+constexpr int kMaxP = 16;
+
+struct Error : std::runtime_error {
+    fmm_status code;
+    Error(fmm_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define FMM_HIP(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            throw ::fmm::Error(FMM_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define FMM_CHECK(cond, code, msg)                   \
+    do {                                             \
+        if (!(cond)) throw ::fmm::Error(code, msg);  \
+    } while (0)
+
+inline int p2pad_of(int p) { return ((p * p + 15) / 16) * 16; }
+
+// ---------------------------------------------------------------- memory
+struct Allocator {
+    fmm_allocator user{};
+    bool has_user = false;
+    hipStream_t stream = nullptr;
+    void *alloc(size_t bytes);
+    void free(void *p);
+};
+
+// A device buffer owned by a plan.
+struct Buf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ---------------------------------------------------------------- plan
+struct Level {
+    int64_t start = 0, count = 0;   // cells [start, start + count)
+    int64_t tile0 = 0, ntile = 0;   // batched-M2L tiles of this level
+};
+
+struct Timer;
+
+}  // namespace fmm
+
+struct fmm_plan {
+    // parameters
+    int64_t n = 0;
+    int p = 8, P2 = 64, P2pad = 64;
+    double theta = 0.4, t4 = 0.64;
+    int ncrit = 64, precision = FMM_PREC_MIXED, cfl = 3, kahan = 1;
+    fmm_dtype dtype = FMM_F64;
+    int timing = 0;
+    fmm::Allocator al;
+    std::vector<fmm::Buf> owned;
+    int64_t bytes_held = 0;
+
+    // root box
+    double lo[3] = {0, 0, 0}, S = 1.0, scale = 1.0;
+
+    // tree
+    int64_t ncell = 0, nleaf = 0, ncoarse = 0;
+    int depth = 0;
+    std::vector<fmm::Level> lv;
+    uint64_t *keys = nullptr;      // [n]
+    int32_t *perm = nullptr;       // [n]
+    int32_t *leaf_of = nullptr;    // [n] sorted body -> leaf cell
+    int32_t *c_lvl = nullptr, *c_beg = nullptr, *c_end = nullptr, *c_par = nullptr;
+    int32_t *c_cbeg = nullptr, *c_nch = nullptr;
+    uint64_t *c_key = nullptr;
+    int32_t *c_ix = nullptr;       // [3*ncell] lattice coords at own level
+    double *c_ctr = nullptr;       // [3*ncell]
+    int32_t *leaves = nullptr;     // [nleaf] leaf cell indices (ascending)
+    void *ubody = nullptr;         // [n] float4 or double4 (u, q)
+
+    // lists
+    int64_t n_m2l_same = 0, n_m2l_cross = 0, n_p2p = 0, p2p_body_pairs = 0;
+    int64_t *p2p_off = nullptr;  int32_t *p2p_src = nullptr;   // CSR over cells
+    int64_t *m2lx_off = nullptr; int32_t *m2lx_src = nullptr;  // cross-level M2L
+    // batched same-level M2L
+    int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius
+    int64_t ntile = 0;
+    int32_t *tile_tgt = nullptr;     // [ntile*64] target cell or -1
+    int32_t *tile_cls = nullptr;     // [ntile] octant class
+    int32_t *slots = nullptr;        // [ntile*K*64] source cell or -1
+    int32_t *st_op = nullptr;        // [8*K] operator index of stencil entry
+    int32_t *st_kidx = nullptr;      // [8*(2R+1)^3] stencil entry of (class, t) or -1
+    std::vector<int32_t> h_st_t;     // [8*K*3] offsets (host copy)
+    std::vector<int32_t> h_ops_t;    // [nops*3]
+    void *ops = nullptr;             // M2L operators, fragment layout, compute type
+    double *ops64 = nullptr;         // (mixed) float64 operators, for coarse targets? unused
+    void *m2m_c = nullptr, *l2l_c = nullptr;   // [8][P2pad][P2pad] compute type
+    double *m2m_d = nullptr, *l2l_d = nullptr; // float64 versions
+
+    // coefficients
+    void *Mc = nullptr, *Lc = nullptr;    // [ncell*P2pad] compute type
+    double *M64 = nullptr, *L64 = nullptr;// [ncoarse*P2pad]
+    // evaluation outputs in sorted order, compute type
+    void *phi_s = nullptr, *E_s = nullptr;    // [n], [3n]
+    void *phi_s2 = nullptr, *E_s2 = nullptr;  // second right-hand side (adjoint)
+    void *ubody2 = nullptr;
+
+    // stats
+    fmm_stats st{};
+};
+
+namespace fmm {
+
+// ---------------------------------------------------------------- launchers
+// sort.hip
+void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s);
+void scan_exclusive_i32to64(const int32_t *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s);
+// stable LSD radix sort of 64-bit keys (optionally with 32-bit values) on bits [0, bits)
+void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s);
+
+// tree.hip
+void tree_build(fmm_plan *P, const void *x, hipStream_t s);
+// traverse.hip
+void traverse(fmm_plan *P, hipStream_t s);
+// expansions.hip
+void make_operators(fmm_plan *P, hipStream_t s);
+void upward(fmm_plan *P, const void *ub, hipStream_t s);
+void downward_l2l(fmm_plan *P, hipStream_t s);
+void l2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
+// m2l.hip
+void m2l(fmm_plan *P, hipStream_t s);
+// p2p.hip
+void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
+// api.hip helpers
+void gather_bodies(fmm_plan *P, const void *q, void *ub, hipStream_t s);
+
+void *plan_alloc(fmm_plan *P, size_t bytes);
+inline dim3 grid1(int64_t n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+}  // namespace fmm

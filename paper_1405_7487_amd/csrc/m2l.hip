@@ -1,0 +1,297 @@
+// m2l.hip -- multipole-to-local translations on gfx950 (Section II.A; the
+// paper notes that M2L and P2P take more than 90% of the run time).
+//
+// Same-level pairs.  With level-scaled coefficients the M2L operator between
+// two cells of one level depends only on their integer offset t, so the
+// translation L(A) += T(t) M(A - t) is a dense p^2 x p^2 product.  A block
+// owns a tile of 64 targets of one level and one octant class (so they share
+// one stencil of offsets); for every stencil entry k it multiplies the common
+// operator T(t_k) by the 64 gathered source multipoles with MFMA
+// (v_mfma_{f32,f64}_16x16x4), accumulating in registers; each target's sum is
+// written once, without atomics, in a fixed order.
+//
+// Cross-level pairs (a leaf against a finer cell) use a generic kernel that
+// builds the operator of the actual offset on the fly.
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace fmm {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <class T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ acc_t run(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ acc_t run(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// D[i][j] = sum_k A[i][k] B[k][j] with 16x16x4 tiles: lane l holds
+// A[l%16][l/16], B[l/16][l%16] and D[4(l/16) + e][l%16] in accumulator e.
+template <class T, int RT>
+__global__ __launch_bounds__(256) void k_m2l_tiles(const int32_t *tile_cls, const int32_t *tile_tgt,
+                                                   const int32_t *slots, const int32_t *st_op, int K, const T *Tf,
+                                                   const T *M, T *L, int64_t tile0)
+{
+    constexpr int P2pad = RT * 16, Q = RT * 4;
+    typedef typename Mfma<T>::acc_t acc_t;
+    const int64_t tile = tile0 + blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int col = wave * 16 + j;
+    const int cls = tile_cls[tile];
+    acc_t acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = acc_t{0, 0, 0, 0};
+    const int32_t *sl = slots + tile * (int64_t)K * kTileW + col;
+    const int32_t *opk = st_op + (int64_t)cls * K;
+    for (int k = 0; k < K; ++k) {
+        const int src = sl[(int64_t)k * kTileW];
+        if (__ballot(src >= 0) == 0ull) continue;
+        const int op = opk[k];
+        T b[Q];
+        if (src >= 0) {
+            const T *mp = M + (int64_t)src * P2pad + g * Q;
+#pragma unroll
+            for (int s = 0; s < Q; ++s) b[s] = mp[s];
+        } else {
+#pragma unroll
+            for (int s = 0; s < Q; ++s) b[s] = 0;
+        }
+        const T *tp = Tf + ((int64_t)(op * 4 + g) * Q) * P2pad + (lane & 15) * RT;
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            T a[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) a[r] = tp[(int64_t)s * P2pad + r];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = Mfma<T>::run(a[r], b[s], acc[r]);
+        }
+    }
+    const int tgt = tile_tgt[tile * kTileW + col];
+    if (tgt < 0) return;
+    T *dst = L + (int64_t)tgt * P2pad;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[16 * r + 4 * g + e] = acc[r][e];
+}
+
+// ------------------------------------------------------- cross-level pairs
+struct cd {
+    double re, im;
+};
+
+__device__ __forceinline__ cd hget(const cd *H, int nmax, int n, int m)
+{
+    if (n < 0 || n >= nmax || m > n || m < -n) return {0.0, 0.0};
+    if (m >= 0) return H[n * (n + 1) / 2 + m];
+    cd v = H[n * (n + 1) / 2 - m];
+    return (m & 1) ? cd{-v.re, v.im} : cd{v.re, -v.im};
+}
+
+__device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
+{
+    n = 0;
+    while ((n + 1) * (n + 1) <= r) ++n;
+    const int o = r - n * n;
+    if (o == 0) { m = 0; im = 0; }
+    else { m = (o + 1) / 2; im = (o & 1) ? 0 : 1; }
+}
+
+// One wave per target cell; float64 arithmetic.  For a source of level l_B
+// and a target of level l_A, with tau = (c_A - c_B)/h_A and rho = h_B/h_A:
+//     Lt_j^s += (-1)^j sum_{n,m} rho^n Mt_n^m I_{n+j}^{m+s}(tau).
+// One 64-thread block (one wave) per target cell, so every barrier below is
+// reached by the whole block.
+template <class TM>
+__global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *off, const int32_t *src,
+                                                  const int32_t *lvl, const double *ctr, double S, int p, int P2pad,
+                                                  const TM *M, TM *L)
+{
+    const int lane = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    if (c >= ncell) return;
+    const int64_t k0 = off[c], k1 = off[c + 1];
+    if (k0 == k1) return;
+    __shared__ cd H[(2 * kMaxP) * (2 * kMaxP + 1) / 2];
+    const int nI = 2 * p - 1, P2 = p * p;
+    const double hA = ldexp(S, -lvl[c]);
+    double acc[4] = {0, 0, 0, 0};  // rows lane, lane+64, lane+128, lane+192
+    for (int64_t k = k0; k < k1; ++k) {
+        const int b = src[k];
+        const double tx = (ctr[3 * c] - ctr[3 * b]) / hA, ty = (ctr[3 * c + 1] - ctr[3 * b + 1]) / hA,
+                     tz = (ctr[3 * c + 2] - ctr[3 * b + 2]) / hA;
+        const double rho = ldexp(1.0, lvl[c] - lvl[b]);
+        // irregular table: diagonal by lane 0, columns by lanes < nI
+        const double r2 = tx * tx + ty * ty + tz * tz, ir2 = 1.0 / r2;
+        if (lane == 0) {
+            cd mm = {1.0 / sqrt(r2), 0.0};
+            for (int m = 0; m < nI; ++m) {
+                if (m > 0) {
+                    const double f = -(2.0 * m - 1.0) * ir2;
+                    mm = cd{(mm.re * tx - mm.im * ty) * f, (mm.re * ty + mm.im * tx) * f};
+                }
+                H[m * (m + 1) / 2 + m] = mm;
+            }
+        }
+        __syncthreads();
+        if (lane < nI) {
+            const int m = lane;
+            cd mm = H[m * (m + 1) / 2 + m], p2 = {0, 0}, p1 = mm;
+            for (int n = m + 1; n < nI; ++n) {
+                cd cur;
+                if (n == m + 1) cur = cd{mm.re * (2.0 * m + 1.0) * tz * ir2, mm.im * (2.0 * m + 1.0) * tz * ir2};
+                else {
+                    const double a = (2.0 * n - 1.0) * tz, bb = -(double)((n + m - 1) * (n - m - 1));
+                    cur = cd{(a * p1.re + bb * p2.re) * ir2, (a * p1.im + bb * p2.im) * ir2};
+                }
+                H[n * (n + 1) / 2 + m] = cur;
+                p2 = p1;
+                p1 = cur;
+            }
+        }
+        __syncthreads();
+        const TM *mb = M + (int64_t)b * P2pad;
+        for (int q = 0; q < 4; ++q) {
+            const int row = lane + 64 * q;
+            if (row >= P2) break;
+            int j, s, rim;
+            rdecode(row, j, s, rim);
+            double sum = 0.0;
+            double rn = 1.0;
+            int ncur = 0;
+            for (int colx = 0; colx < P2; ++colx) {
+                int n, m, cim;
+                rdecode(colx, n, m, cim);
+                while (ncur < n) { rn *= rho; ++ncur; }
+                cd d;
+                if (m == 0) d = hget(H, nI, n + j, s);
+                else {
+                    cd a = hget(H, nI, n + j, m + s), bq = hget(H, nI, n + j, s - m);
+                    const double sg = (m & 1) ? -1.0 : 1.0;
+                    if (!cim) d = {a.re + sg * bq.re, a.im + sg * bq.im};
+                    else d = {-(a.im - sg * bq.im), a.re - sg * bq.re};
+                }
+                const double v = rim ? d.im : d.re;
+                sum += v * rn * (double)mb[colx];
+            }
+            acc[q] += (j & 1) ? -sum : sum;
+        }
+        __syncthreads();
+    }
+    TM *dl = L + c * P2pad;
+    for (int q = 0; q < 4; ++q) {
+        const int row = lane + 64 * q;
+        if (row < P2) dl[row] = (TM)((double)dl[row] + acc[q]);
+    }
+}
+
+__global__ void k_mfma_probe_f32(float *out)
+{
+    const int l = threadIdx.x;
+    v4f acc = {0, 0, 0, 0};
+    // A[i][k] = i + 1 + 100 k (lane i + 16 k); B[k][j] = 1 + 1000 j for k = 0, else 0
+    // (lane j + 16 k); so D[i][j] = (i + 1)(1 + 1000 j)
+    const float a = (float)((l & 15) + 1 + 100 * (l >> 4));
+    const float b = (l >> 4) == 0 ? 1.0f + (float)(l & 15) * 1000.0f : 0.0f;
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    for (int e = 0; e < 4; ++e) out[l * 4 + e] = acc[e];
+}
+__global__ void k_mfma_probe_f64(double *out)
+{
+    const int l = threadIdx.x;
+    v4d acc = {0, 0, 0, 0};
+    const double a = (double)((l & 15) + 1 + 100 * (l >> 4));
+    const double b = (l >> 4) == 0 ? 1.0 + (double)(l & 15) * 1000.0 : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int e = 0; e < 4; ++e) out[l * 4 + e] = acc[e];
+}
+
+template <class T, int RT>
+void launch_tiles(fmm_plan *P, hipStream_t s)
+{
+    const int64_t nt = P->ntile;
+    const int64_t chunk = 1 << 20;
+    for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
+        const int64_t nb = std::min(chunk, nt - t0);
+        k_m2l_tiles<T, RT><<<(unsigned)nb, 256, 0, s>>>(P->tile_cls, P->tile_tgt, P->slots, P->st_op, P->K,
+                                                        static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
+                                                        static_cast<T *>(P->Lc), t0);
+        FMM_HIP(hipGetLastError());
+    }
+}
+
+template <class T>
+void dispatch_tiles(fmm_plan *P, hipStream_t s)
+{
+    switch (P->P2pad / 16) {
+    case 1: launch_tiles<T, 1>(P, s); break;
+    case 2: launch_tiles<T, 2>(P, s); break;
+    case 3: launch_tiles<T, 3>(P, s); break;
+    case 4: launch_tiles<T, 4>(P, s); break;
+    case 6: launch_tiles<T, 6>(P, s); break;
+    case 7: launch_tiles<T, 7>(P, s); break;
+    case 8: launch_tiles<T, 8>(P, s); break;
+    case 9: launch_tiles<T, 9>(P, s); break;
+    case 11: launch_tiles<T, 11>(P, s); break;
+    case 13: launch_tiles<T, 13>(P, s); break;
+    case 15: launch_tiles<T, 15>(P, s); break;
+    case 16: launch_tiles<T, 16>(P, s); break;
+    default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported padded coefficient count");
+    }
+}
+
+}  // namespace
+
+void m2l(fmm_plan *P, hipStream_t s)
+{
+    const bool f64 = P->precision == FMM_PREC_FP64;
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    // root (and any cell outside the tiles) starts from zero
+    FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * P->P2pad, s));
+    if (P->ntile > 0 && P->K > 0) {
+        if (f64) dispatch_tiles<double>(P, s);
+        else dispatch_tiles<float>(P, s);
+    } else {
+        FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * P->P2pad * P->ncell, s));
+    }
+    if (P->n_m2l_cross > 0) {
+        const unsigned nb = (unsigned)P->ncell;
+        if (f64)
+            k_m2l_cross<double><<<nb, 64, 0, s>>>(P->ncell, P->m2lx_off, P->m2lx_src, P->c_lvl, P->c_ctr, P->S, P->p,
+                                                   P->P2pad, static_cast<const double *>(P->Mc),
+                                                   static_cast<double *>(P->Lc));
+        else
+            k_m2l_cross<float><<<nb, 64, 0, s>>>(P->ncell, P->m2lx_off, P->m2lx_src, P->c_lvl, P->c_ctr, P->S, P->p,
+                                                  P->P2pad, static_cast<const float *>(P->Mc),
+                                                  static_cast<float *>(P->Lc));
+        FMM_HIP(hipGetLastError());
+    }
+}
+
+void mfma_probe(int f64, void *out_host)
+{
+    void *d = nullptr;
+    FMM_HIP(hipMalloc(&d, 64 * 4 * sizeof(double)));
+    if (f64) k_mfma_probe_f64<<<1, 64>>>(static_cast<double *>(d));
+    else k_mfma_probe_f32<<<1, 64>>>(static_cast<float *>(d));
+    FMM_HIP(hipGetLastError());
+    FMM_HIP(hipMemcpy(out_host, d, 64 * 4 * (f64 ? sizeof(double) : sizeof(float)), hipMemcpyDeviceToHost));
+    FMM_HIP(hipFree(d));
+}
+
+}  // namespace fmm

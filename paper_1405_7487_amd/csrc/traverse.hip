@@ -1,0 +1,481 @@
+// traverse.hip -- dual tree traversal on gfx950 (Section II.C of the paper,
+// after Dehnen 2002).
+//
+// The walk starts from the pair (root, root).  A pair whose cells satisfy the
+// acceptance criterion R_A + R_B < theta |c_A - c_B| becomes an M2L pair; a
+// pair of two leaves becomes a P2P pair; otherwise the coarser cell is split
+// (both when they share a level; a leaf is never split).  The rule treats
+// both sides alike, so every list is symmetric.
+//
+// The GPU walks the pair frontier one generation at a time: each frontier
+// pair expands into its child pairs, which are classified at once; counts,
+// scan and write passes keep the output deterministic.  Unlike the paper's
+// code, which never forms lists, the lists are materialised here so that the
+// translation work can be regrouped:
+//   * same-level M2L pairs go to a slot table.  For a target of octant class c
+//     (its position inside its parent) the offsets t = i_A - i_B of its
+//     same-level sources form a fixed stencil S_c, the same at every level;
+//     slot [tile][k][lane] holds the source of stencil entry k of the lane's
+//     target, or -1;
+//   * cross-level M2L pairs and P2P pairs are sorted into CSR by target.
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+namespace fmm {
+
+namespace {
+
+// Exact acceptance test on the lattice of half-units of the finer cell:
+// 3 (s_A + s_B)^2 < (4 theta^2) * D^2 with sides s = 2^{f-l+1} and center
+// coordinates 2^{f-l} (2 i + 1), D^2 the squared distance of the centers.
+__device__ __forceinline__ bool mac_dev(int la, int ax, int ay, int az, int lb, int bx, int by, int bz, double t4)
+{
+    const int f = la > lb ? la : lb;
+    const int64_t sa = 1ll << (f - la + 1), sb = 1ll << (f - lb + 1);
+    const int64_t dx = ((2ll * ax + 1) << (f - la)) - ((2ll * bx + 1) << (f - lb));
+    const int64_t dy = ((2ll * ay + 1) << (f - la)) - ((2ll * by + 1) << (f - lb));
+    const int64_t dz = ((2ll * az + 1) << (f - la)) - ((2ll * bz + 1) << (f - lb));
+    const int64_t d2 = dx * dx + dy * dy + dz * dz;
+    const double lhs = (double)(3 * (sa + sb) * (sa + sb));
+    return lhs < __dmul_rn(t4, (double)d2);
+}
+
+struct TreeView {
+    const int32_t *lvl, *nch, *cbeg, *ix;
+    const uint64_t *key;
+    const int32_t *tile_pos;  // cell -> tile*64 + lane (or -1)
+    const int32_t *kidx;      // [8][(2R+1)^3]
+    int32_t *slots;
+    int K, R;
+    double t4;
+};
+
+// Classification of one child pair: 0 = same-level M2L, 1 = cross-level M2L,
+// 2 = P2P, 3 = split further.
+__device__ __forceinline__ int classify(const TreeView &T, int a, int b)
+{
+    const int la = T.lvl[a], lb = T.lvl[b];
+    if (mac_dev(la, T.ix[3 * a], T.ix[3 * a + 1], T.ix[3 * a + 2], lb, T.ix[3 * b], T.ix[3 * b + 1], T.ix[3 * b + 2],
+                T.t4))
+        return la == lb ? 0 : 1;
+    if (T.nch[a] == 0 && T.nch[b] == 0) return 2;
+    return 3;
+}
+
+// The split rule of the traversal for a pair that was not accepted and is
+// not two leaves.
+__device__ __forceinline__ void split_rule(const TreeView &T, int a, int b, bool &sa, bool &sb)
+{
+    const bool leafa = T.nch[a] == 0, leafb = T.nch[b] == 0;
+    const int la = T.lvl[a], lb = T.lvl[b];
+    if (leafa) { sa = false; sb = true; }
+    else if (leafb) { sa = true; sb = false; }
+    else if (la < lb) { sa = true; sb = false; }
+    else if (lb < la) { sa = false; sb = true; }
+    else { sa = true; sb = true; }
+}
+
+__global__ __launch_bounds__(256) void k_expand_count(TreeView T, const int2 *F, int64_t nf, int32_t *c_cross,
+                                                      int32_t *c_p2p, int32_t *c_next, unsigned long long *n_same)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int a = F[i].x, b = F[i].y;
+    bool sa, sb;
+    split_rule(T, a, b, sa, sb);
+    const int na = sa ? T.nch[a] : 1, nb = sb ? T.nch[b] : 1;
+    const int a0 = sa ? T.cbeg[a] : a, b0 = sb ? T.cbeg[b] : b;
+    int cx = 0, cp = 0, cn = 0, cs = 0;
+    for (int u = 0; u < na; ++u)
+        for (int v = 0; v < nb; ++v) {
+            int k = classify(T, a0 + u, b0 + v);
+            cs += k == 0;
+            cx += k == 1;
+            cp += k == 2;
+            cn += k == 3;
+        }
+    c_cross[i] = cx;
+    c_p2p[i] = cp;
+    c_next[i] = cn;
+    if (cs) atomicAdd(n_same, (unsigned long long)cs);
+}
+
+__global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F, int64_t nf, const int64_t *o_cross,
+                                                      const int64_t *o_p2p, const int64_t *o_next, uint64_t *cross,
+                                                      uint64_t *p2p, int2 *next, int cbits, int *err)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int a = F[i].x, b = F[i].y;
+    bool sa, sb;
+    split_rule(T, a, b, sa, sb);
+    const int na = sa ? T.nch[a] : 1, nb = sb ? T.nch[b] : 1;
+    const int a0 = sa ? T.cbeg[a] : a, b0 = sb ? T.cbeg[b] : b;
+    int64_t ox = o_cross[i], op = o_p2p[i], on = o_next[i];
+    const int W = 2 * T.R + 1;
+    for (int u = 0; u < na; ++u)
+        for (int v = 0; v < nb; ++v) {
+            const int x = a0 + u, y = b0 + v;
+            const int k = classify(T, x, y);
+            if (k == 0) {
+                const int tx = T.ix[3 * x] - T.ix[3 * y], ty = T.ix[3 * x + 1] - T.ix[3 * y + 1],
+                          tz = T.ix[3 * x + 2] - T.ix[3 * y + 2];
+                const int cls = (int)(T.key[x] & 7u);
+                int kk = -1;
+                if (abs(tx) <= T.R && abs(ty) <= T.R && abs(tz) <= T.R)
+                    kk = T.kidx[cls * W * W * W + ((tx + T.R) * W + (ty + T.R)) * W + (tz + T.R)];
+                const int pos = T.tile_pos[x];
+                if (kk < 0 || pos < 0) {
+                    atomicOr(err, 1);
+                } else {
+                    const int64_t tile = pos / kTileW, lane = pos % kTileW;
+                    T.slots[(tile * T.K + kk) * kTileW + lane] = y;
+                }
+            } else if (k == 1) {
+                cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
+            } else if (k == 2) {
+                p2p[op++] = ((uint64_t)x << cbits) | (uint64_t)y;
+            } else {
+                next[on++] = make_int2(x, y);
+            }
+        }
+}
+
+// Cell class keys for the stable class-major ordering of each level.
+__global__ __launch_bounds__(256) void k_class_keys(const int32_t *lvl, const uint64_t *key, int64_t nc, uint64_t *ck,
+                                                    int32_t *idx, int32_t *cnt)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int g = lvl[c] * 8 + (int)(key[c] & 7u);
+    ck[c] = (uint64_t)g;
+    idx[c] = (int32_t)c;
+    atomicAdd(&cnt[g], 1);
+}
+
+__global__ __launch_bounds__(256) void k_fill_tiles(const uint64_t *ck, const int32_t *idx, int64_t nc,
+                                                    const int64_t *gstart, const int64_t *gtile, int32_t *tile_tgt,
+                                                    int32_t *tile_pos)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nc) return;
+    const int g = (int)ck[j];
+    const int c = idx[j];
+    if (gtile[g] < 0) {  // level 0: no same-level partner
+        tile_pos[c] = -1;
+        return;
+    }
+    const int64_t r = j - gstart[g];
+    const int64_t p = (gtile[g] + r / kTileW) * kTileW + r % kTileW;
+    tile_tgt[p] = c;
+    tile_pos[c] = (int32_t)p;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// CSR offsets: off[c] = first position whose target is >= c.
+__global__ __launch_bounds__(256) void k_csr_offsets(const uint64_t *keys, int64_t np, int cbits, int64_t nc,
+                                                     int64_t *off)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nc) return;
+    const uint64_t want = (uint64_t)c << cbits;
+    int64_t lo = 0, hi = np;
+    while (lo < hi) {
+        int64_t m = lo + ((hi - lo) >> 1);
+        if (keys[m] < want) lo = m + 1;
+        else hi = m;
+    }
+    off[c] = lo;
+}
+
+__global__ __launch_bounds__(256) void k_csr_sources(const uint64_t *keys, int64_t np, int cbits, int32_t *src,
+                                                     const int32_t *beg, const int32_t *end,
+                                                     unsigned long long *body_pairs)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t bp = 0;
+    if (k < np) {
+        const uint64_t key = keys[k];
+        const int32_t s = (int32_t)(key & ((1ull << cbits) - 1));
+        const int32_t t = (int32_t)(key >> cbits);
+        src[k] = s;
+        if (body_pairs) bp = (uint64_t)(end[t] - beg[t]) * (uint64_t)(end[s] - beg[s]);
+    }
+    if (body_pairs) {
+        for (int o = 32; o > 0; o >>= 1) bp += __shfl_xor(bp, o, 64);
+        if ((threadIdx.x & 63) == 0 && bp) atomicAdd(body_pairs, (unsigned long long)bp);
+    }
+}
+
+// Same-level acceptance as the traversal evaluates it (equal sides: s = 2,
+// D = 2 |t| in half-units).
+bool mac_same_level(int64_t t2, double t4) { return 48.0 < t4 * (double)(4 * t2); }
+
+int ceil_div2(int v) { return (v >= 0) ? (v + 1) / 2 : -((-v) / 2); }
+
+}  // namespace
+
+// Host: the stencils S_c and the operator table.
+static void build_stencils(fmm_plan *P)
+{
+    const double t4 = P->t4;
+    // parent offsets that fail the criterion satisfy |T|^2 <= 12 / t4
+    const int rT = (int)std::floor(std::sqrt(12.0 / t4)) + 1;
+    const int R = 2 * rT + 1;
+    std::vector<std::vector<std::array<int, 3>>> S(8);
+    std::map<std::array<int, 3>, int> uni;
+    for (int c = 0; c < 8; ++c) {
+        const int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
+        for (int tx = -R; tx <= R; ++tx)
+            for (int ty = -R; ty <= R; ++ty)
+                for (int tz = -R; tz <= R; ++tz) {
+                    if (!mac_same_level((int64_t)tx * tx + (int64_t)ty * ty + (int64_t)tz * tz, t4)) continue;
+                    const int Tx = ceil_div2(tx - cx), Ty = ceil_div2(ty - cy), Tz = ceil_div2(tz - cz);
+                    if (mac_same_level((int64_t)Tx * Tx + (int64_t)Ty * Ty + (int64_t)Tz * Tz, t4)) continue;
+                    S[c].push_back({tx, ty, tz});
+                    uni[{tx, ty, tz}] = 0;
+                }
+    }
+    int id = 0;
+    P->h_ops_t.clear();
+    for (auto &kv : uni) {
+        kv.second = id++;
+        P->h_ops_t.insert(P->h_ops_t.end(), kv.first.begin(), kv.first.end());
+    }
+    size_t K = 0;
+    for (int c = 0; c < 8; ++c) K = std::max(K, S[c].size());
+    P->K = (int)K;
+    P->R = R;
+    P->nops = id;
+    // stencil entries ordered by operator index so that all classes sweep the
+    // operator table in the same order
+    std::vector<int32_t> op(8 * K, -1), kidx((size_t)8 * (2 * R + 1) * (2 * R + 1) * (2 * R + 1), -1);
+    P->h_st_t.assign(8 * K * 3, 0);
+    const int W = 2 * R + 1;
+    for (int c = 0; c < 8; ++c) {
+        std::sort(S[c].begin(), S[c].end());
+        for (size_t k = 0; k < S[c].size(); ++k) {
+            const auto &t = S[c][k];
+            op[c * K + k] = uni[t];
+            for (int d = 0; d < 3; ++d) P->h_st_t[(c * K + k) * 3 + d] = t[d];
+            kidx[(size_t)c * W * W * W + ((t[0] + R) * W + (t[1] + R)) * W + (t[2] + R)] = (int32_t)k;
+        }
+    }
+    P->st_op = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<size_t>(1, op.size())));
+    P->st_kidx = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * kidx.size()));
+    FMM_HIP(hipMemcpy(P->st_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice));
+    FMM_HIP(hipMemcpy(P->st_kidx, kidx.data(), sizeof(int32_t) * kidx.size(), hipMemcpyHostToDevice));
+}
+
+static int bits_for(int64_t v)
+{
+    int b = 1;
+    while ((1ll << b) <= v) ++b;
+    return b;
+}
+
+static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int64_t **off, int32_t **src,
+                        unsigned long long *body_pairs, hipStream_t s)
+{
+    radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s);
+    *off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (P->ncell + 1)));
+    *src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, np)));
+    k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits, P->ncell, *off);
+    FMM_HIP(hipGetLastError());
+    if (np > 0) {
+        k_csr_sources<<<grid1(np, 256), 256, 0, s>>>(keys, np, cbits, *src, P->c_beg, P->c_end, body_pairs);
+        FMM_HIP(hipGetLastError());
+    }
+}
+
+void traverse(fmm_plan *P, hipStream_t s)
+{
+    Allocator &al = P->al;
+    const int64_t nc = P->ncell;
+    build_stencils(P);
+
+    // Octant-class tiles per level (levels >= 1).
+    const int G = (kLevels + 1) * 8;
+    uint64_t *ck = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * nc));
+    int32_t *idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc));
+    int32_t *gcnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * G));
+    FMM_HIP(hipMemsetAsync(gcnt, 0, sizeof(int32_t) * G, s));
+    k_class_keys<<<grid1(nc, 256), 256, 0, s>>>(P->c_lvl, P->c_key, nc, ck, idx, gcnt);
+    FMM_HIP(hipGetLastError());
+    radix_sort_u64(ck, idx, nc, 8, al, s);
+    std::vector<int32_t> hcnt(G);
+    FMM_HIP(hipMemcpyAsync(hcnt.data(), gcnt, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> gstart(G), gtile(G);
+    int64_t acc = 0, tiles = 0;
+    for (int g = 0; g < G; ++g) {
+        gstart[g] = acc;
+        acc += hcnt[g];
+        const int l = g / 8;
+        if (l == 0 || hcnt[g] == 0) {
+            gtile[g] = -1;
+            continue;
+        }
+        gtile[g] = tiles;
+        tiles += (hcnt[g] + kTileW - 1) / kTileW;
+    }
+    for (int l = 0; l <= P->depth; ++l) {
+        P->lv[l].tile0 = (l == 0) ? 0 : -1;
+        P->lv[l].ntile = 0;
+        for (int c = 0; c < 8; ++c) {
+            const int g = l * 8 + c;
+            if (gtile[g] < 0) continue;
+            if (P->lv[l].tile0 < 0) P->lv[l].tile0 = gtile[g];
+            P->lv[l].ntile += (hcnt[g] + kTileW - 1) / kTileW;
+        }
+        if (P->lv[l].tile0 < 0) P->lv[l].tile0 = tiles;
+    }
+    P->ntile = tiles;
+    int64_t *d_gs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 2 * G));
+    FMM_HIP(hipMemcpyAsync(d_gs, gstart.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, s));
+    FMM_HIP(hipMemcpyAsync(d_gs + G, gtile.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, s));
+    P->tile_tgt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, tiles * kTileW)));
+    P->tile_cls = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, tiles)));
+    int32_t *tile_pos = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc));
+    if (tiles > 0) {
+        k_fill_i32<<<grid1(tiles * kTileW, 256), 256, 0, s>>>(P->tile_tgt, tiles * kTileW, -1);
+        FMM_HIP(hipGetLastError());
+    }
+    k_fill_tiles<<<grid1(nc, 256), 256, 0, s>>>(ck, idx, nc, d_gs, d_gs + G, P->tile_tgt, tile_pos);
+    FMM_HIP(hipGetLastError());
+    {
+        std::vector<int32_t> tc(std::max<int64_t>(1, tiles), 0);
+        for (int g = 0; g < G; ++g)
+            if (gtile[g] >= 0)
+                for (int64_t t = 0; t < (hcnt[g] + kTileW - 1) / kTileW; ++t) tc[gtile[g] + t] = g % 8;
+        FMM_HIP(hipMemcpyAsync(P->tile_cls, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice, s));
+        FMM_HIP(hipStreamSynchronize(s));
+    }
+    al.free(d_gs);
+    al.free(gcnt);
+    al.free(idx);
+    al.free(ck);
+
+    const int64_t nslots = tiles * (int64_t)P->K * kTileW;
+    P->slots = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nslots)));
+    if (nslots > 0) {
+        k_fill_i32<<<grid1(nslots, 256), 256, 0, s>>>(P->slots, nslots, -1);
+        FMM_HIP(hipGetLastError());
+    }
+
+    TreeView T;
+    T.lvl = P->c_lvl;
+    T.nch = P->c_nch;
+    T.cbeg = P->c_cbeg;
+    T.ix = P->c_ix;
+    T.key = P->c_key;
+    T.tile_pos = tile_pos;
+    T.kidx = P->st_kidx;
+    T.slots = P->slots;
+    T.K = P->K;
+    T.R = P->R;
+    T.t4 = P->t4;
+
+    const int cbits = bits_for(nc);
+    FMM_CHECK(2 * cbits <= 64, FMM_ERR_UNSUPPORTED, "too many cells");
+    // Growable outputs.
+    std::vector<std::pair<uint64_t *, int64_t>> cross_parts, p2p_parts;
+    int64_t ncross = 0, np2p = 0;
+    unsigned long long *d_cnt = static_cast<unsigned long long *>(al.alloc(sizeof(unsigned long long) * 2));
+    FMM_HIP(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * 2, s));
+    int *d_err = static_cast<int *>(al.alloc(sizeof(int)));
+    FMM_HIP(hipMemsetAsync(d_err, 0, sizeof(int), s));
+
+    int32_t h_root_nch = 0;
+    FMM_HIP(hipMemcpyAsync(&h_root_nch, P->c_nch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    int2 *F = nullptr;
+    int64_t nf = 0;
+    if (h_root_nch == 0) {
+        // single leaf: the only pair is P2P(root, root)
+        uint64_t *pp = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t)));
+        uint64_t zero = 0;
+        FMM_HIP(hipMemcpy(pp, &zero, sizeof(uint64_t), hipMemcpyHostToDevice));
+        p2p_parts.push_back({pp, 1});
+        np2p = 1;
+    } else {
+        F = static_cast<int2 *>(al.alloc(sizeof(int2)));
+        int2 r0 = make_int2(0, 0);
+        FMM_HIP(hipMemcpy(F, &r0, sizeof(int2), hipMemcpyHostToDevice));
+        nf = 1;
+    }
+    int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3));
+    while (nf > 0) {
+        int32_t *cnts = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 3 * nf));
+        int64_t *offs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3 * nf));
+        k_expand_count<<<grid1(nf, 256), 256, 0, s>>>(T, F, nf, cnts, cnts + nf, cnts + 2 * nf, d_cnt);
+        FMM_HIP(hipGetLastError());
+        for (int j = 0; j < 3; ++j) scan_exclusive_i32to64(cnts + j * nf, offs + j * nf, nf, d_tot + j, al, s);
+        int64_t tot[3];
+        FMM_HIP(hipMemcpyAsync(tot, d_tot, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipStreamSynchronize(s));
+        uint64_t *cx = tot[0] ? static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * tot[0])) : nullptr;
+        uint64_t *pp = tot[1] ? static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * tot[1])) : nullptr;
+        int2 *nx = tot[2] ? static_cast<int2 *>(al.alloc(sizeof(int2) * tot[2])) : nullptr;
+        k_expand_write<<<grid1(nf, 256), 256, 0, s>>>(T, F, nf, offs, offs + nf, offs + 2 * nf, cx, pp, nx, cbits,
+                                                      d_err);
+        FMM_HIP(hipGetLastError());
+        if (cx) cross_parts.push_back({cx, tot[0]});
+        if (pp) p2p_parts.push_back({pp, tot[1]});
+        ncross += tot[0];
+        np2p += tot[1];
+        al.free(offs);
+        al.free(cnts);
+        al.free(F);
+        F = nx;
+        nf = tot[2];
+    }
+    if (F) al.free(F);
+    al.free(d_tot);
+    al.free(tile_pos);
+
+    int h_err = 0;
+    unsigned long long h_cnt[2];
+    FMM_HIP(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipMemcpyAsync(h_cnt, d_cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    FMM_CHECK(h_err == 0, FMM_ERR_DEVICE, "traversal: same-level pair outside its stencil");
+    P->n_m2l_same = (int64_t)h_cnt[0];
+    P->n_m2l_cross = ncross;
+    P->n_p2p = np2p;
+
+    // Concatenate, sort and convert to CSR.
+    auto concat = [&](std::vector<std::pair<uint64_t *, int64_t>> &parts, int64_t tot) {
+        uint64_t *all = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * std::max<int64_t>(1, tot)));
+        int64_t o = 0;
+        for (auto &pr : parts) {
+            FMM_HIP(hipMemcpyAsync(all + o, pr.first, sizeof(uint64_t) * pr.second, hipMemcpyDeviceToDevice, s));
+            o += pr.second;
+        }
+        return all;
+    };
+    uint64_t *p2p_all = concat(p2p_parts, np2p);
+    uint64_t *cross_all = concat(cross_parts, ncross);
+    FMM_HIP(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s));
+    sort_to_csr(P, p2p_all, np2p, cbits, &P->p2p_off, &P->p2p_src, d_cnt, s);
+    sort_to_csr(P, cross_all, ncross, cbits, &P->m2lx_off, &P->m2lx_src, nullptr, s);
+    FMM_HIP(hipMemcpyAsync(h_cnt, d_cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    P->p2p_body_pairs = (int64_t)h_cnt[0];
+    for (auto &pr : p2p_parts) al.free(pr.first);
+    for (auto &pr : cross_parts) al.free(pr.first);
+    al.free(p2p_all);
+    al.free(cross_all);
+    al.free(d_err);
+    al.free(d_cnt);
+}
+
+}  // namespace fmm

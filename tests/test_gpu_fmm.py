@@ -1,0 +1,201 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tree, keys, permutation, cells, centers and lists must be bit-exact; the
+FP64 GPU FMM must match the oracle FMM within 1e-6 relative L2 (expected:
+roundoff, ~1e-13) and the mixed FP32/MFMA path within 1e-4, on potential and
+field.  Sizes span many tiles and leave ragged tails (counts not multiples of
+64 targets per tile, leaves with few bodies, cross-level pairs).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1405_7487_amd as F
+from paper_1405_7487_amd import workloads as W
+
+from gpu_util import dev, gpu_fmm, host, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def test_mfma_lane_layout():
+    for f64 in (False, True):
+        out = np.asarray(F.mfma_layout(f64), dtype=np.float64)
+        exp = np.zeros(256)
+        for l in range(64):
+            for e in range(4):
+                i, j = 4 * (l // 16) + e, l % 16
+                exp[4 * l + e] = (i + 1) * (1 + 1000 * j)
+        assert np.array_equal(out, exp), f"f64={f64}"
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
+def test_single_leaf_is_direct_sum(precision, tol):
+    x, q, _ = W.uniform_cube(1500, 3)
+    x[-4:] = x[:4]  # coincident bodies: their pair is skipped
+    plan, phi, E = gpu_fmm(x, q, 4, 0.4, 4096, precision)
+    st = plan.stats()
+    assert st["ncell"] == 1 and st["n_p2p"] == 1 and st["n_m2l"] == 0
+    pd, Ed = oracle.direct(x, q)
+    assert rel(phi, pd) < tol and rel(E, Ed) < tol
+
+
+def _compare_tree(plan, x, ncrit, theta):
+    g = plan.export_tree()
+    T = oracle.Tree(x, ncrit, theta)
+    o = T.export()
+    for k in ("keys", "perm", "level", "begin", "end", "parent", "child_begin", "nchild"):
+        assert np.array_equal(g[k], o[k]), k
+    assert np.array_equal(g["ckey"], o["ckey"])
+    assert np.array_equal(g["centers"].view(np.uint64), o["centers"].view(np.uint64))
+    assert np.array_equal(g["m2l"], o["m2l"]), "m2l lists"
+    assert np.array_equal(g["p2p"], o["p2p"]), "p2p lists"
+    return T
+
+
+@pytest.mark.parametrize("case", ["cube16k", "plummer", "dups"])
+def test_tree_and_lists_bit_exact(case):
+    if case == "cube16k":
+        x, q, _ = W.make_config("cube16k")
+        ncrit, theta = 64, 0.4
+    elif case == "plummer":
+        x, _, _ = W.plummer(30000, 5)
+        ncrit, theta = 32, 0.35
+    else:
+        x, _, _ = W.uniform_cube(5000, 6)
+        x[2500:] = x[:2500]
+        x[:100] = x[0]
+        ncrit, theta = 16, 0.5
+    plan = F.Plan(dev(x), F.Params(p=4, theta=theta, ncrit=ncrit, precision="fp64"))
+    T = _compare_tree(plan, x, ncrit, theta)
+    st = plan.stats()
+    assert (st["ncell"], st["nleaf"], st["depth"]) == (T.ncell, T.nleaf, T.depth)
+    assert (st["n_m2l"], st["n_p2p"]) == (T.n_m2l, T.n_p2p)
+
+
+def test_float32_coordinates_widen_exactly():
+    x, _, _ = W.plummer(8000, 9)
+    x32 = x.astype(np.float32)
+    plan = F.Plan(dev(x32, torch.float32), F.Params(p=4, theta=0.4, ncrit=24, precision="mixed"))
+    _compare_tree(plan, x32.astype(np.float64), 24, 0.4)
+
+
+@pytest.mark.parametrize("case", ["cube16k", "plummer"])
+def test_fmm_matches_oracle(case):
+    if case == "cube16k":
+        x, q, _ = W.make_config("cube16k")
+        p, theta, ncrit = 4, 0.4, 64
+    else:
+        x, _, _ = W.plummer(40000, 2)
+        q = np.random.default_rng(3).uniform(-1, 1, 40000)
+        p, theta, ncrit = 6, 0.35, 32
+    T = oracle.Tree(x, ncrit, theta)
+    po, Eo = T.fmm(q, p)
+    _, p64, E64 = gpu_fmm(x, q, p, theta, ncrit, "fp64")
+    e64 = (rel(p64, po), rel(E64, Eo))
+    assert e64[0] < 1e-6 and e64[1] < 1e-6
+    assert e64[0] < 1e-11 and e64[1] < 1e-11, e64  # roundoff only
+    _, pm, Em = gpu_fmm(x, q, p, theta, ncrit, "mixed")
+    em = (rel(pm, po), rel(Em, Eo))
+    assert em[0] < 1e-4 and em[1] < 1e-4, em
+    if case == "cube16k":
+        # and against the plain definition: the direct sum, all targets
+        pd, Ed = oracle.direct(x, q)
+        assert rel(p64, pd) < 1e-3 and rel(E64, Ed) < 1e-3
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 9, 10, 12])
+def test_orders_and_padding(p):
+    # every padded coefficient width the batched M2L is instantiated for
+    x, q, _ = W.uniform_cube(9000, 20 + p)
+    T = oracle.Tree(x, 40, 0.45)
+    po, Eo = T.fmm(q, p)
+    _, p64, E64 = gpu_fmm(x, q, p, 0.45, 40, "fp64")
+    assert rel(p64, po) < 1e-11 and rel(E64, Eo) < 1e-11
+    _, pm, Em = gpu_fmm(x, q, p, 0.45, 40, "mixed")
+    assert rel(pm, po) < 1e-4 and rel(Em, Eo) < 1e-4
+
+
+def test_coarse_fp64_levels_variants():
+    x, _, _ = W.plummer(20000, 4)
+    q = np.random.default_rng(1).uniform(-1, 1, 20000)
+    T = oracle.Tree(x, 16, 0.4)
+    po, Eo = T.fmm(q, 6)
+    for cfl in (0, 1, 3, 30 - 8):
+        plan = F.Plan(dev(x), F.Params(p=6, theta=0.4, ncrit=16, precision="mixed", coarse_fp64_levels=cfl))
+        phi, E = plan.evaluate(dev(q))
+        assert rel(host(phi), po) < 1e-4 and rel(host(E), Eo) < 1e-4, cfl
+
+
+def test_adjoint_matches_oracle_composition():
+    x, q, rng = W.uniform_cube(12000, 7)
+    w = W.adjoint_weights(rng, 12000)
+    p, theta, ncrit = 5, 0.4, 32
+    T = oracle.Tree(x, ncrit, theta)
+    _, Eq = T.fmm(q, p)
+    pw, Ew = T.fmm(w, p)
+    dq_ref = pw
+    dx_ref = -(w[:, None] * Eq + q[:, None] * Ew)
+    for precision, tol in (("fp64", 1e-11), ("mixed", 1e-4)):
+        plan = F.Plan(dev(x), F.Params(p=p, theta=theta, ncrit=ncrit, precision=precision))
+        dq, dx = plan.adjoint(dev(q), dev(w))          # recompute E^q
+        assert rel(host(dq), dq_ref) < tol and rel(host(dx), dx_ref) < tol, precision
+        _, E = plan.evaluate(dev(q))
+        dq2, dx2 = plan.adjoint(dev(q), dev(w), E)     # reuse E^q
+        assert rel(host(dq2), dq_ref) < tol and rel(host(dx2), dx_ref) < tol, precision
+
+
+def test_autograd_function():
+    x, q, rng = W.uniform_cube(6000, 8)
+    w = W.adjoint_weights(rng, 6000)
+    for recompute in (False, True):
+        prm = F.Params(p=5, theta=0.4, ncrit=32, precision="fp64")
+        prm.recompute = recompute
+        xt = dev(x).requires_grad_(True)
+        qt = dev(q).requires_grad_(True)
+        phi, E = F.FMMFunction.apply(xt, qt, prm)
+        L = (dev(w) * phi).sum()
+        L.backward()
+        T = oracle.Tree(x, 32, 0.4)
+        _, Eq = T.fmm(q, 5)
+        pw, Ew = T.fmm(w, 5)
+        assert rel(host(qt.grad), pw) < 1e-11
+        assert rel(host(xt.grad), -(w[:, None] * Eq + q[:, None] * Ew)) < 1e-11
+
+
+def test_deterministic_bits():
+    x, _, _ = W.plummer(30000, 11)
+    q = np.random.default_rng(0).uniform(-1, 1, 30000)
+    outs = []
+    for _ in range(2):
+        plan, phi, E = gpu_fmm(x, q, 6, 0.4, 32, "mixed")
+        outs.append((phi.tobytes(), E.tobytes()))
+    assert outs[0] == outs[1]
+
+
+def test_error_paths():
+    x, q, _ = W.uniform_cube(100, 1)
+    bad = [dict(p=0), dict(p=17), dict(theta=0.0), dict(theta=1.0), dict(ncrit=0)]
+    for kw in bad:
+        prm = F.Params(**{**dict(p=4, theta=0.4, ncrit=8), **kw})
+        with pytest.raises(F.FMMError) as ei:
+            F.Plan(dev(x), prm)
+        assert ei.value.code == 1
+    xn = x.copy()
+    xn[17, 1] = np.nan
+    with pytest.raises(F.FMMError) as ei:
+        F.Plan(dev(xn), F.Params(p=4))
+    assert ei.value.code == 5
+    xi = x.copy()
+    xi[3, 0] = np.inf
+    with pytest.raises(F.FMMError) as ei:
+        F.Plan(dev(xi), F.Params(p=4))
+    assert ei.value.code == 5
+    # empty input is a valid no-op
+    plan = F.Plan(torch.zeros((0, 3), dtype=torch.float64, device="cuda:0"), F.Params(p=4))
+    phi, E = plan.evaluate(torch.zeros(0, dtype=torch.float64, device="cuda:0"))
+    assert phi.numel() == 0
+    # one body
+    plan, phi, E = gpu_fmm(x[:1], q[:1], 4, 0.4, 8, "mixed")
+    assert phi[0] == 0.0 and np.all(E == 0.0)
