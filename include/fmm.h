@@ -188,8 +188,9 @@ FMM_API const char *fmm_last_error(void);
  * one 16x16x4 MFMA on the current device (f64 != 0: float64, else float32)
  * with A[i][k] = i + 1 + 100 k, B[0][j] = 1 + 1000 j, B[k>0][j] = 0 and copies
  * the 64 lanes x 4 accumulators (lane-major; 256 floats or doubles) to the
- * HOST buffer out_host.  Expected: lane l, slot e holds (i + 1)(1 + 1000 j)
- * with i = 4 (l / 16) + e, j = l % 16.  Errors: FMM_ERR_INVALID, FMM_ERR_DEVICE. */
+ * HOST buffer out_host.  Lane l, slot e holds (i + 1)(1 + 1000 j) with
+ * j = l % 16 and i = 4 (l / 16) + e (float32) or l / 16 + 4 e (float64), as
+ * measured on gfx950.  Errors: FMM_ERR_INVALID, FMM_ERR_DEVICE. */
 FMM_API fmm_status fmm_debug_mfma_layout(int32_t f64, void *out_host);
 
 #ifdef __cplusplus

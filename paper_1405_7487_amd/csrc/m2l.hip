@@ -24,8 +24,11 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <class T> struct Mfma;
+// Accumulator e of lane l holds row acc_row(l/16, e) of the 16x16 tile:
+// 4 (l/16) + e for float32, l/16 + 4 e for float64.
 template <> struct Mfma<float> {
     typedef v4f acc_t;
+    static __device__ __forceinline__ int acc_row(int g, int e) { return 4 * g + e; }
     static __device__ __forceinline__ acc_t run(float a, float b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -33,6 +36,7 @@ template <> struct Mfma<float> {
 };
 template <> struct Mfma<double> {
     typedef v4d acc_t;
+    static __device__ __forceinline__ int acc_row(int g, int e) { return g + 4 * e; }
     static __device__ __forceinline__ acc_t run(double a, double b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -40,7 +44,7 @@ template <> struct Mfma<double> {
 };
 
 // D[i][j] = sum_k A[i][k] B[k][j] with 16x16x4 tiles: lane l holds
-// A[l%16][l/16], B[l/16][l%16] and D[4(l/16) + e][l%16] in accumulator e.
+// A[l%16][l/16], B[l/16][l%16] and D[acc_row(l/16, e)][l%16] in accumulator e.
 template <class T, int RT>
 __global__ __launch_bounds__(256) void k_m2l_tiles(const int32_t *tile_cls, const int32_t *tile_tgt,
                                                    const int32_t *slots, const int32_t *st_op, int K, const T *Tf,
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(256) void k_m2l_tiles(const int32_t *tile_cls, cons
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[16 * r + 4 * g + e] = acc[r][e];
+        for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[r][e];
 }
 
 // ------------------------------------------------------- cross-level pairs

@@ -33,6 +33,7 @@ namespace {
 // coordinates 2^{f-l} (2 i + 1), D^2 the squared distance of the centers.
 __device__ __forceinline__ bool mac_dev(int la, int ax, int ay, int az, int lb, int bx, int by, int bz, double t4)
 {
+#pragma clang fp contract(off)
     const int f = la > lb ? la : lb;
     const int64_t sa = 1ll << (f - la + 1), sb = 1ll << (f - lb + 1);
     const int64_t dx = ((2ll * ax + 1) << (f - la)) - ((2ll * bx + 1) << (f - lb));
@@ -40,7 +41,7 @@ __device__ __forceinline__ bool mac_dev(int la, int ax, int ay, int az, int lb, 
     const int64_t dz = ((2ll * az + 1) << (f - la)) - ((2ll * bz + 1) << (f - lb));
     const int64_t d2 = dx * dx + dy * dy + dz * dz;
     const double lhs = (double)(3 * (sa + sb) * (sa + sb));
-    return lhs < __dmul_rn(t4, (double)d2);
+    return lhs < t4 * (double)d2;
 }
 
 struct TreeView {

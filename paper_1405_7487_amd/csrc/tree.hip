@@ -97,10 +97,11 @@ __device__ __forceinline__ uint32_t compact3(uint64_t v)
 }
 
 // Lattice coordinate: min(2^21 - 1, floor((x - lo) * scale)); the
-// subtraction and the product round once each (no fused multiply-add).
+// subtraction and the product round once each (contraction is off).
 __device__ __forceinline__ uint64_t lattice(double x, double lo, double scale)
 {
-    double s = __dmul_rn(__dsub_rn(x, lo), scale);
+#pragma clang fp contract(off)
+    double s = (x - lo) * scale;
     double f = floor(s);
     uint64_t v = f <= 0.0 ? 0ull : (uint64_t)f;
     const uint64_t top = (1ull << kLevels) - 1;
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(256) void k_write_children(const uint64_t *keys, co
 __global__ __launch_bounds__(256) void k_geometry(const uint64_t *ckey, const int32_t *lvl, int64_t ncell, double lx,
                                                   double ly, double lz, double S, int32_t *ix, double *ctr)
 {
+#pragma clang fp contract(off)
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     uint64_t k = ckey[c];
@@ -194,7 +196,8 @@ __global__ __launch_bounds__(256) void k_geometry(const uint64_t *ckey, const in
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         ix[3 * c + d] = (int32_t)v[d];
-        ctr[3 * c + d] = __dadd_rn(lo[d], __dmul_rn((double)v[d] + 0.5, h));
+        const double off = ((double)v[d] + 0.5) * h;  // rounds once (no fused multiply-add)
+        ctr[3 * c + d] = lo[d] + off;
     }
 }
 
