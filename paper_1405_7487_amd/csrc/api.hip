@@ -345,6 +345,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         P->t4 = 4.0 * pr.theta * pr.theta;
         P->ncrit = pr.ncrit;
         P->precision = pr.precision;
+        P->TW = m2l_tile_width(pr.p, pr.precision == FMM_PREC_FP64);
         P->cfl = pr.coarse_fp64_levels;
         P->kahan = pr.kahan ? 1 : 0;
         P->dtype = dtype;
@@ -365,6 +366,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         traverse(P, s);
         allocator_flush(P->al);
         make_operators(P, s);
+        m2l_prepare(P);
         const bool f64 = P->precision == FMM_PREC_FP64;
         const size_t esz = f64 ? sizeof(double) : sizeof(float);
         const size_t ncoef = (size_t)P->ncell * P->P2pad;
@@ -549,7 +551,7 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
     st.p2p_body_pairs = P->p2p_body_pairs;
     st.m2l_stencil = P->K;
     st.m2l_offsets = P->nops;
-    st.m2l_slots = P->ntile * (int64_t)P->K * kTileW;
+    st.m2l_slots = P->ntile * (int64_t)P->K * P->TW;
     st.device_bytes = P->bytes_held;
     {
         std::lock_guard<std::mutex> lk(g_ev_mu);
@@ -611,16 +613,16 @@ fmm_status fmm_export_tree(const fmm_plan *Pc, const fmm_tree_export *o)
         if (o->m2l) {
             std::vector<uint64_t> v;
             csr_pairs(P->m2lx_off, P->m2lx_src, P->n_m2l_cross, v);
-            const int64_t ns = P->ntile * (int64_t)P->K * kTileW;
+            const int64_t ns = P->ntile * (int64_t)P->K * P->TW;
             if (ns > 0) {
-                std::vector<int32_t> sl(ns), tg(P->ntile * kTileW);
+                std::vector<int32_t> sl(ns), tg(P->ntile * P->TW);
                 FMM_HIP(hipMemcpy(sl.data(), P->slots, sizeof(int32_t) * ns, hipMemcpyDeviceToHost));
                 FMM_HIP(hipMemcpy(tg.data(), P->tile_tgt, sizeof(int32_t) * tg.size(), hipMemcpyDeviceToHost));
                 for (int64_t t = 0; t < P->ntile; ++t)
                     for (int64_t k = 0; k < P->K; ++k)
-                        for (int l = 0; l < kTileW; ++l) {
-                            const int32_t sv = sl[(t * P->K + k) * kTileW + l];
-                            if (sv >= 0) v.push_back(((uint64_t)(uint32_t)tg[t * kTileW + l] << 32) | (uint32_t)sv);
+                        for (int l = 0; l < P->TW; ++l) {
+                            const int32_t sv = sl[(t * P->K + k) * P->TW + l];
+                            if (sv >= 0) v.push_back(((uint64_t)(uint32_t)tg[t * P->TW + l] << 32) | (uint32_t)sv);
                         }
             }
             std::sort(v.begin(), v.end());

@@ -8,8 +8,8 @@
 //              contiguous index range
 //   coefs    : per cell P2pad = roundup(p^2, 16) reals, real solid-harmonic
 //              basis scaled per level (multipole / h^n, local * h^{n+1})
-//   lists    : same-level M2L as a slot table [tile][k][64] (source cell of
-//              stencil entry k for each of 64 targets of one octant class);
+//   lists    : same-level M2L as a slot table [tile][k][TW] (source cell of
+//              stencil entry k for each of TW targets of one octant class);
 //              cross-level M2L and P2P as CSR by target cell
 #pragma once
 
@@ -26,7 +26,6 @@
 namespace fmm {
 
 constexpr int kLevels = 21;       // 64-bit Morton key: 3 bits x 21 levels
-constexpr int kTileW = 64;        // targets per batched-M2L tile
 constexpr int kMaxP = 16;
 
 struct Error : std::runtime_error {
@@ -110,10 +109,13 @@ struct fmm_plan {
     int64_t *m2lx_off = nullptr; int32_t *m2lx_src = nullptr;  // cross-level M2L
     // batched same-level M2L
     int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius
+    int TW = 64;                     // targets per batched-M2L tile (64, 128 or 256)
+    int KS = 1;                      // stencil chunks per tile (parallel split, reduced in order)
     int64_t ntile = 0;
-    int32_t *tile_tgt = nullptr;     // [ntile*64] target cell or -1
+    int32_t *tile_tgt = nullptr;     // [ntile*TW] target cell or -1
     int32_t *tile_cls = nullptr;     // [ntile] octant class
-    int32_t *slots = nullptr;        // [ntile*K*64] source cell or -1
+    int32_t *slots = nullptr;        // [ntile*K*TW] source cell or -1
+    void *m2l_part = nullptr;        // [KS][ntile*TW][P2pad] partial sums when KS > 1
     int32_t *st_op = nullptr;        // [8*K] operator index of stencil entry
     int32_t *st_kidx = nullptr;      // [8*(2R+1)^3] stencil entry of (class, t) or -1
     std::vector<int32_t> h_st_t;     // [8*K*3] offsets (host copy)
@@ -154,6 +156,8 @@ void upward(fmm_plan *P, const void *ub, hipStream_t s);
 void downward_l2l(fmm_plan *P, hipStream_t s);
 void l2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
 // m2l.hip
+int m2l_tile_width(int p, bool f64);
+void m2l_prepare(fmm_plan *P);
 void m2l(fmm_plan *P, hipStream_t s);
 // p2p.hip
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);

@@ -43,55 +43,191 @@ template <> struct Mfma<double> {
     }
 };
 
-// D[i][j] = sum_k A[i][k] B[k][j] with 16x16x4 tiles: lane l holds
-// A[l%16][l/16], B[l/16][l%16] and D[acc_row(l/16, e)][l%16] in accumulator e.
-template <class T, int RT>
-__global__ __launch_bounds__(256) void k_m2l_tiles(const int32_t *tile_cls, const int32_t *tile_tgt,
-                                                   const int32_t *slots, const int32_t *st_op, int K, const T *Tf,
-                                                   const T *M, T *L, int64_t tile0)
+template <class T> struct Vec16;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <> struct Vec16<float> {
+    typedef f4v t;
+    static constexpr int n = 4;
+};
+template <> struct Vec16<double> {
+    typedef d2v t;
+    static constexpr int n = 2;
+};
+
+// Column groups of 16 targets per wave: more groups reuse each operator
+// fragment more often but need more accumulator registers.
+__host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (RT <= 4 ? 2 : 1); }
+
+// Input steps of the operator per LDS stage: the largest divisor of Q = 4 RT
+// whose stage (4 groups x steps x P2pad values) fits in 32 KiB.
+__host__ __device__ constexpr int m2l_sch(int RT, int bytes)
 {
-    constexpr int P2pad = RT * 16, Q = RT * 4;
+    int best = 1;
+    for (int sc = 1; sc <= 4 * RT; ++sc)
+        if ((4 * RT) % sc == 0 && 4 * sc * 16 * RT * bytes <= 32768) best = sc;
+    return best;
+}
+
+// Batched same-level M2L.  Block = 4 waves = one tile of TW = 64 CG targets of
+// one octant class, restricted to the stencil chunk [k0, k1) (ks = block mod
+// KS, so that blocks on one XCD share a chunk of operators in its L2).  For
+// every stencil entry k the block stages the common operator T(t_k) in LDS;
+// each wave multiplies it by its 16 CG gathered source multipoles:
+//     D[i][j] = sum_k A[i][k] B[k][j] (16x16x4 MFMA), A = operator fragment
+//     (lane l: A[l%16][l/16]), B = multipoles (lane l: B[l/16][l%16]); lane l
+//     accumulates D[acc_row(l/16, e)][l%16] in slot e.
+// The next stage of the operator and the next sources are fetched while the
+// current stage is multiplied.
+template <class T, int RT, int CG, int SCH>
+__global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__ tile_cls,
+                                                     const int32_t *__restrict__ slots, const int32_t *__restrict__ st_op,
+                                                     int K, int KS, const T *__restrict__ Tf, const T *__restrict__ M,
+                                                     T *__restrict__ part, const int32_t *__restrict__ tile_tgt,
+                                                     T *__restrict__ L, int64_t ntile)
+{
+    constexpr int P2pad = 16 * RT, Q = 4 * RT, NC = Q / SCH, TW = 64 * CG;
+    constexpr int STAGE = 4 * SCH * P2pad;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int NV = STAGE / VN;
+    constexpr int PV = (NV + 255) / 256;
+    typedef typename Vec16<T>::t vec_t;
     typedef typename Mfma<T>::acc_t acc_t;
-    const int64_t tile = tile0 + blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = lane & 15, g = lane >> 4;
-    const int col = wave * 16 + j;
+    __shared__ __align__(16) T lds[STAGE];
+
+    const int64_t b = blockIdx.x;
+    const int ks = (int)(b % KS);
+    const int64_t tile = b / KS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
     const int cls = tile_cls[tile];
-    acc_t acc[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) acc[r] = acc_t{0, 0, 0, 0};
-    const int32_t *sl = slots + tile * (int64_t)K * kTileW + col;
+    const int Kc = (K + KS - 1) / KS;
+    const int k0 = ks * Kc, k1 = min(K, k0 + Kc);
+    const int32_t *sl = slots + tile * (int64_t)K * TW + wave * CG * 16 + j;
     const int32_t *opk = st_op + (int64_t)cls * K;
-    for (int k = 0; k < K; ++k) {
-        const int src = sl[(int64_t)k * kTileW];
-        if (__ballot(src >= 0) == 0ull) continue;
-        const int op = opk[k];
-        T b[Q];
-        if (src >= 0) {
-            const T *mp = M + (int64_t)src * P2pad + g * Q;
+
+    acc_t acc[CG][RT];
 #pragma unroll
-            for (int s = 0; s < Q; ++s) b[s] = mp[s];
-        } else {
+    for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
-            for (int s = 0; s < Q; ++s) b[s] = 0;
-        }
-        const T *tp = Tf + ((int64_t)(op * 4 + g) * Q) * P2pad + (lane & 15) * RT;
-#pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            T a[RT];
-#pragma unroll
-            for (int r = 0; r < RT; ++r) a[r] = tp[(int64_t)s * P2pad + r];
-#pragma unroll
-            for (int r = 0; r < RT; ++r) acc[r] = Mfma<T>::run(a[r], b[s], acc[r]);
-        }
+        for (int r = 0; r < RT; ++r) acc[cg][r] = acc_t{0, 0, 0, 0};
+
+    if (k0 < k1) {
+        T bc[CG][Q], bn[CG][Q];
+        int srcc[CG], srcn[CG];
+        vec_t treg[PV];
+        // operator stage (k, c): rows s in [c SCH, (c+1) SCH) of the 4 groups
+#define M2L_LOAD_STAGE(KK, CC)                                                                     \
+    {                                                                                              \
+        int op_ = opk[KK];                                                                         \
+        op_ = op_ < 0 ? 0 : op_;                                                                   \
+        _Pragma("unroll") for (int u = 0; u < PV; ++u)                                             \
+        {                                                                                          \
+            const int v = tid + 256 * u;                                                           \
+            if (v < NV) {                                                                          \
+                const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);        \
+                treg[u] = *reinterpret_cast<const vec_t *>(                                        \
+                    Tf + ((int64_t)(op_ * 4 + gg) * Q + (CC) * SCH) * P2pad + rem);                \
+            }                                                                                      \
+        }                                                                                          \
     }
-    const int tgt = tile_tgt[tile * kTileW + col];
+#define M2L_STORE_STAGE()                                                                          \
+    {                                                                                              \
+        _Pragma("unroll") for (int u = 0; u < PV; ++u)                                             \
+        {                                                                                          \
+            const int v = tid + 256 * u;                                                           \
+            if (v < NV) *reinterpret_cast<vec_t *>(lds + v * VN) = treg[u];                         \
+        }                                                                                          \
+    }
+#define M2L_LOAD_B(KK, DST, SRC)                                                                   \
+    {                                                                                              \
+        _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                                          \
+        {                                                                                          \
+            const int sv = sl[(int64_t)(KK) * TW + cg * 16];                                      \
+            SRC[cg] = sv;                                                                          \
+            const vec_t *mp = reinterpret_cast<const vec_t *>(M + (int64_t)(sv < 0 ? 0 : sv) * P2pad + g * Q); \
+            _Pragma("unroll") for (int v = 0; v < Q / VN; ++v)                                     \
+            {                                                                                      \
+                vec_t x = sv >= 0 ? mp[v] : vec_t{};                                               \
+                _Pragma("unroll") for (int w = 0; w < VN; ++w) DST[cg][v * VN + w] = x[w];         \
+            }                                                                                      \
+        }                                                                                          \
+    }
+        M2L_LOAD_STAGE(k0, 0);
+        M2L_STORE_STAGE();
+        M2L_LOAD_B(k0, bc, srcc);
+        for (int k = k0; k < k1; ++k) {
+            bool any = false;
+#pragma unroll
+            for (int cg = 0; cg < CG; ++cg) any |= srcc[cg] >= 0;
+            const bool active = __ballot(any) != 0ull;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const bool has_next = (c + 1 < NC) || (k + 1 < k1);
+                if (c + 1 < NC) M2L_LOAD_STAGE(k, c + 1)
+                else if (k + 1 < k1) M2L_LOAD_STAGE(k + 1, 0)
+                if (c == 0 && k + 1 < k1) M2L_LOAD_B(k + 1, bn, srcn)
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int ss = 0; ss < SCH; ++ss) {
+                        T a[RT];
+                        const T *ap = lds + g * (SCH * P2pad) + ss * P2pad + j * RT;
+#pragma unroll
+                        for (int r = 0; r < RT; ++r) a[r] = ap[r];
+#pragma unroll
+                        for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+                            for (int r = 0; r < RT; ++r) acc[cg][r] = Mfma<T>::run(a[r], bc[cg][c * SCH + ss], acc[cg][r]);
+                    }
+                }
+                __syncthreads();
+                if (has_next) M2L_STORE_STAGE()
+            }
+            if (k + 1 < k1) {
+#pragma unroll
+                for (int cg = 0; cg < CG; ++cg) {
+                    srcc[cg] = srcn[cg];
+#pragma unroll
+                    for (int s2 = 0; s2 < Q; ++s2) bc[cg][s2] = bn[cg][s2];
+                }
+            }
+        }
+#undef M2L_LOAD_STAGE
+#undef M2L_STORE_STAGE
+#undef M2L_LOAD_B
+    }
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+        const int col = wave * CG * 16 + cg * 16 + j;
+        T *dst;
+        if (KS == 1) {
+            const int tgt = tile_tgt[tile * TW + col];
+            if (tgt < 0) continue;
+            dst = L + (int64_t)tgt * P2pad;
+        } else {
+            dst = part + (((int64_t)ks * ntile + tile) * TW + col) * P2pad;
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
+    }
+}
+
+// Sum of the KS partial products of each target, in chunk order.
+template <class T>
+__global__ __launch_bounds__(256) void k_m2l_reduce(const T *part, int KS, int64_t ncol, int P2pad,
+                                                    const int32_t *tile_tgt, T *L)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pos = t / P2pad;
+    const int row = (int)(t % P2pad);
+    if (pos >= ncol) return;
+    const int tgt = tile_tgt[pos];
     if (tgt < 0) return;
-    T *dst = L + (int64_t)tgt * P2pad;
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[r][e];
+    T s = 0;
+    for (int k = 0; k < KS; ++k) s += part[((int64_t)k * ncol + pos) * P2pad + row];
+    L[(int64_t)tgt * P2pad + row] = s;
 }
 
 // ------------------------------------------------------- cross-level pairs
@@ -226,15 +362,21 @@ __global__ void k_mfma_probe_f64(double *out)
 }
 
 template <class T, int RT>
-void launch_tiles(fmm_plan *P, hipStream_t s)
+void launch_batched(fmm_plan *P, hipStream_t s)
 {
-    const int64_t nt = P->ntile;
-    const int64_t chunk = 1 << 20;
-    for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
-        const int64_t nb = std::min(chunk, nt - t0);
-        k_m2l_tiles<T, RT><<<(unsigned)nb, 256, 0, s>>>(P->tile_cls, P->tile_tgt, P->slots, P->st_op, P->K,
-                                                        static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
-                                                        static_cast<T *>(P->Lc), t0);
+    constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
+    constexpr int SCH = m2l_sch(RT, (int)sizeof(T));
+    const int64_t nb = P->ntile * P->KS;
+    FMM_CHECK(nb < (1ll << 31), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
+    FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
+    k_m2l_batched<T, RT, CG, SCH><<<(unsigned)nb, 256, 0, s>>>(
+        P->tile_cls, P->slots, P->st_op, P->K, P->KS, static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
+        static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
+    FMM_HIP(hipGetLastError());
+    if (P->KS > 1) {
+        const int64_t ncol = P->ntile * P->TW;
+        k_m2l_reduce<T><<<grid1(ncol * P->P2pad, 256), 256, 0, s>>>(static_cast<const T *>(P->m2l_part), P->KS, ncol,
+                                                                   P->P2pad, P->tile_tgt, static_cast<T *>(P->Lc));
         FMM_HIP(hipGetLastError());
     }
 }
@@ -243,23 +385,41 @@ template <class T>
 void dispatch_tiles(fmm_plan *P, hipStream_t s)
 {
     switch (P->P2pad / 16) {
-    case 1: launch_tiles<T, 1>(P, s); break;
-    case 2: launch_tiles<T, 2>(P, s); break;
-    case 3: launch_tiles<T, 3>(P, s); break;
-    case 4: launch_tiles<T, 4>(P, s); break;
-    case 6: launch_tiles<T, 6>(P, s); break;
-    case 7: launch_tiles<T, 7>(P, s); break;
-    case 8: launch_tiles<T, 8>(P, s); break;
-    case 9: launch_tiles<T, 9>(P, s); break;
-    case 11: launch_tiles<T, 11>(P, s); break;
-    case 13: launch_tiles<T, 13>(P, s); break;
-    case 15: launch_tiles<T, 15>(P, s); break;
-    case 16: launch_tiles<T, 16>(P, s); break;
+    case 1: launch_batched<T, 1>(P, s); break;
+    case 2: launch_batched<T, 2>(P, s); break;
+    case 3: launch_batched<T, 3>(P, s); break;
+    case 4: launch_batched<T, 4>(P, s); break;
+    case 6: launch_batched<T, 6>(P, s); break;
+    case 7: launch_batched<T, 7>(P, s); break;
+    case 8: launch_batched<T, 8>(P, s); break;
+    case 9: launch_batched<T, 9>(P, s); break;
+    case 11: launch_batched<T, 11>(P, s); break;
+    case 13: launch_batched<T, 13>(P, s); break;
+    case 15: launch_batched<T, 15>(P, s); break;
+    case 16: launch_batched<T, 16>(P, s); break;
     default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported padded coefficient count");
     }
 }
 
 }  // namespace
+
+int m2l_tile_width(int p, bool f64) { return 64 * m2l_cg(p2pad_of(p) / 16, f64); }
+
+// Stencil split: enough blocks to fill the chip (about 8 per compute unit),
+// but at least 8 stencil entries per chunk.
+void m2l_prepare(fmm_plan *P)
+{
+    P->KS = 1;
+    if (P->ntile <= 0 || P->K <= 0) return;
+    int64_t ks = (2048 + P->ntile - 1) / P->ntile;
+    ks = std::min<int64_t>(ks, 16);
+    ks = std::min<int64_t>(ks, std::max(1, P->K / 8));
+    P->KS = (int)std::max<int64_t>(1, ks);
+    if (P->KS > 1) {
+        const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
+        P->m2l_part = plan_alloc(P, esz * (size_t)P->KS * P->ntile * P->TW * P->P2pad);
+    }
+}
 
 void m2l(fmm_plan *P, hipStream_t s)
 {

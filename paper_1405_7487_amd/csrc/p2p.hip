@@ -3,10 +3,14 @@
 //
 // One wave per target leaf.  Source bodies of the leaf's P2P list are staged
 // in LDS in batches of up to 256, shifted into the target leaf's frame
-// (offsets from leaf centers keep float32 differences exact to ~1e-7 of the
-// leaf size at any depth).  When the leaf holds few bodies, G lanes share a
-// target and split the batch; a butterfly of wave shuffles sums them.  Batch
-// partial sums enter the running totals through a compensated (Kahan) add.
+// (offsets from leaf centers keep float32 differences accurate to ~1e-7 of
+// the leaf size at any depth).  When the leaf holds few bodies, G lanes share
+// a target and split each batch; a butterfly of wave shuffles sums them.
+// Batches are padded with zero-charge bodies far away so that every lane runs
+// the same unrolled loop with compile-time LDS offsets.  Only the leaf's own
+// bodies can coincide with a target, so only that batch tests r^2 > 0.
+// Batch partial sums enter the running totals through a compensated (Kahan)
+// add.
 #include "internal.hpp"
 
 namespace fmm {
@@ -14,9 +18,10 @@ namespace fmm {
 namespace {
 
 constexpr int kStage = 256;
+constexpr int kUnroll = 4;
 
 template <class T> __device__ __forceinline__ T rsqrt_t(T x);
-template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return __frsqrt_rn(x); }
+template <> __device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 
 template <class T>
@@ -28,87 +33,147 @@ __device__ __forceinline__ void kahan_add(T &sum, T &comp, T v)
     sum = t;
 }
 
+template <class T> struct Acc {
+    T p, x, y, z;
+};
+
+// Interaction of one target (ux, uy, uz) with staged sources sub, sub+G, ...
+// of a batch padded to a multiple of G * kUnroll.
+template <class T, class V4, int G, bool MASK>
+__device__ __forceinline__ void batch(const V4 *sb, int npad, int sub, T ux, T uy, T uz, Acc<T> &a)
+{
+    const V4 *p = sb + sub;
+    for (int it = 0; it < npad; it += G * kUnroll, p += G * kUnroll) {
+        V4 v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) v[u] = p[u * G];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const T dx = ux - v[u].x, dy = uy - v[u].y, dz = uz - v[u].z;
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            T ri = rsqrt_t<T>(r2);
+            if (MASK) ri = r2 > (T)0 ? ri : (T)0;
+            const T qri = v[u].w * ri;
+            const T qr3 = qri * (ri * ri);
+            a.p += qri;
+            a.x += qr3 * dx;
+            a.y += qr3 * dy;
+            a.z += qr3 * dz;
+        }
+    }
+}
+
+template <class T, class V4>
+__device__ __forceinline__ V4 far_dummy()
+{
+    V4 v;
+    v.x = (T)1e15;
+    v.y = (T)1e15;
+    v.z = (T)1e15;
+    v.w = (T)0;
+    return v;
+}
+
+template <class T, class V4, bool KAHAN, int G>
+__device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const int32_t *beg, const int32_t *end,
+                           int64_t k0, int64_t k1, const int32_t *src, const double *ctr, const V4 *ub, T *phi_s,
+                           T *E_s)
+{
+    const int lane = threadIdx.x;
+    const int ti = lane / G, sub = lane % G;
+    const bool active = ti < cnt;
+    const V4 u = ub[tb + base + (active ? ti : 0)];
+    const double cax = ctr[3 * A], cay = ctr[3 * A + 1], caz = ctr[3 * A + 2];
+    Acc<T> s{0, 0, 0, 0}, c{0, 0, 0, 0};
+    auto fold = [&](const Acc<T> &pa) {
+        if (KAHAN) {
+            kahan_add(s.p, c.p, pa.p);
+            kahan_add(s.x, c.x, pa.x);
+            kahan_add(s.y, c.y, pa.y);
+            kahan_add(s.z, c.z, pa.z);
+        } else {
+            s.p += pa.p; s.x += pa.x; s.y += pa.y; s.z += pa.z;
+        }
+    };
+    const int32_t ab = beg[A], ae = end[A];
+    // 1) the leaf's own bodies (may coincide with the target): masked
+    for (int32_t o = ab; o < ae; o += kStage) {
+        const int take = min(kStage, ae - o);
+        const int npad = (take + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
+        for (int l = lane; l < npad; l += 64) sb[l] = l < take ? ub[o + l] : far_dummy<T, V4>();
+        __syncthreads();
+        Acc<T> pa{0, 0, 0, 0};
+        batch<T, V4, G, true>(sb, npad, sub, u.x, u.y, u.z, pa);
+        fold(pa);
+        __syncthreads();
+    }
+    // 2) every other leaf of the list, batched, no test needed
+    int64_t k = k0;
+    int32_t o = 0;
+    while (k < k1) {
+        int staged = 0;
+        while (staged < kStage && k < k1) {
+            const int b = src[k];
+            if (b == A) { ++k; o = 0; continue; }
+            const int32_t bb = beg[b] + o, be = end[b];
+            const int take = min(min(be - bb, kStage - staged), 64);
+            if (lane < take) {
+                V4 v = ub[bb + lane];
+                v.x += (T)(ctr[3 * b] - cax);
+                v.y += (T)(ctr[3 * b + 1] - cay);
+                v.z += (T)(ctr[3 * b + 2] - caz);
+                sb[staged + lane] = v;
+            }
+            staged += take;
+            o += take;
+            if (bb + take == be) { ++k; o = 0; }
+        }
+        if (staged == 0) break;
+        const int npad = (staged + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
+        for (int l = staged + lane; l < npad; l += 64) sb[l] = far_dummy<T, V4>();
+        __syncthreads();
+        Acc<T> pa{0, 0, 0, 0};
+        batch<T, V4, G, false>(sb, npad, sub, u.x, u.y, u.z, pa);
+        fold(pa);
+        __syncthreads();
+    }
+    if (KAHAN) {
+        s.p -= c.p; s.x -= c.x; s.y -= c.y; s.z -= c.z;
+    }
+#pragma unroll
+    for (int w = G >> 1; w >= 1; w >>= 1) {
+        s.p += __shfl_xor(s.p, w, 64);
+        s.x += __shfl_xor(s.x, w, 64);
+        s.y += __shfl_xor(s.y, w, 64);
+        s.z += __shfl_xor(s.z, w, 64);
+    }
+    if (active && sub == 0) {
+        const int64_t i = tb + base + ti;
+        phi_s[i] = s.p;
+        E_s[3 * i] = s.x;
+        E_s[3 * i + 1] = s.y;
+        E_s[3 * i + 2] = s.z;
+    }
+}
+
 template <class T, class V4, bool KAHAN>
 __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t *beg, const int32_t *end,
                                             const int64_t *off, const int32_t *src, const double *ctr, const V4 *ub,
                                             T *phi_s, T *E_s)
 {
-    __shared__ V4 sb[kStage];
-    const int lane = threadIdx.x;
+    __shared__ V4 sb[kStage + 64 * kUnroll];
     const int A = leaves[blockIdx.x];
     const int32_t tb = beg[A], te = end[A];
     const int nt = te - tb;
-    const double cax = ctr[3 * A], cay = ctr[3 * A + 1], caz = ctr[3 * A + 2];
     const int64_t k0 = off[A], k1 = off[A + 1];
     for (int base = 0; base < nt; base += 64) {
         const int cnt = min(64, nt - base);
-        int G = 1;
-        while (G < 16 && 2 * G * cnt <= 64) G *= 2;
-        const int ti = lane / G, sub = lane % G;
-        const bool active = ti < cnt;
-        V4 u = ub[tb + base + (active ? ti : 0)];
-        T s_p = 0, s_x = 0, s_y = 0, s_z = 0, c_p = 0, c_x = 0, c_y = 0, c_z = 0;
-        int64_t k = k0;
-        int32_t o = 0;
-        while (k < k1) {
-            int staged = 0;
-            while (staged < kStage && k < k1) {
-                const int b = src[k];
-                const int32_t bb = beg[b] + o, be = end[b];
-                const int take = min(min(be - bb, kStage - staged), 64);
-                if (lane < take) {
-                    V4 v = ub[bb + lane];
-                    v.x += (T)(ctr[3 * b] - cax);
-                    v.y += (T)(ctr[3 * b + 1] - cay);
-                    v.z += (T)(ctr[3 * b + 2] - caz);
-                    sb[staged + lane] = v;
-                }
-                staged += take;
-                o += take;
-                if (bb + take == be) { ++k; o = 0; }
-            }
-            __syncthreads();
-            T p_p = 0, p_x = 0, p_y = 0, p_z = 0;
-            if (active) {
-                for (int jj = sub; jj < staged; jj += G) {
-                    const V4 v = sb[jj];
-                    const T dx = u.x - v.x, dy = u.y - v.y, dz = u.z - v.z;
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    const T ri = r2 > (T)0 ? rsqrt_t<T>(r2) : (T)0;
-                    const T qr = v.w * ri;
-                    const T qr3 = qr * ri * ri;
-                    p_p += qr;
-                    p_x += qr3 * dx;
-                    p_y += qr3 * dy;
-                    p_z += qr3 * dz;
-                }
-            }
-            if (KAHAN) {
-                kahan_add(s_p, c_p, p_p);
-                kahan_add(s_x, c_x, p_x);
-                kahan_add(s_y, c_y, p_y);
-                kahan_add(s_z, c_z, p_z);
-            } else {
-                s_p += p_p; s_x += p_x; s_y += p_y; s_z += p_z;
-            }
-            __syncthreads();
-        }
-        if (KAHAN) {
-            s_p -= c_p; s_x -= c_x; s_y -= c_y; s_z -= c_z;
-        }
-        for (int w = G >> 1; w >= 1; w >>= 1) {
-            s_p += __shfl_xor(s_p, w, 64);
-            s_x += __shfl_xor(s_x, w, 64);
-            s_y += __shfl_xor(s_y, w, 64);
-            s_z += __shfl_xor(s_z, w, 64);
-        }
-        if (active && sub == 0) {
-            const int64_t i = tb + base + ti;
-            phi_s[i] = s_p;
-            E_s[3 * i] = s_x;
-            E_s[3 * i + 1] = s_y;
-            E_s[3 * i + 2] = s_z;
-        }
+        // lanes per target: the largest power of two (<= 16) with G * cnt <= 64
+        if (cnt <= 4) leaf_chunk<T, V4, KAHAN, 16>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else if (cnt <= 8) leaf_chunk<T, V4, KAHAN, 8>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else if (cnt <= 16) leaf_chunk<T, V4, KAHAN, 4>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else if (cnt <= 32) leaf_chunk<T, V4, KAHAN, 2>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else leaf_chunk<T, V4, KAHAN, 1>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
     }
 }
 

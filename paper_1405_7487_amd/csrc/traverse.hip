@@ -50,7 +50,7 @@ struct TreeView {
     const int32_t *tile_pos;  // cell -> tile*64 + lane (or -1)
     const int32_t *kidx;      // [8][(2R+1)^3]
     int32_t *slots;
-    int K, R;
+    int K, R, TW;
     double t4;
 };
 
@@ -132,8 +132,8 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
                 if (kk < 0 || pos < 0) {
                     atomicOr(err, 1);
                 } else {
-                    const int64_t tile = pos / kTileW, lane = pos % kTileW;
-                    T.slots[(tile * T.K + kk) * kTileW + lane] = y;
+                    const int64_t tile = pos / T.TW, lane = pos % T.TW;
+                    T.slots[(tile * T.K + kk) * T.TW + lane] = y;
                 }
             } else if (k == 1) {
                 cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
@@ -149,17 +149,24 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
 __global__ __launch_bounds__(256) void k_class_keys(const int32_t *lvl, const uint64_t *key, int64_t nc, uint64_t *ck,
                                                     int32_t *idx, int32_t *cnt)
 {
+    __shared__ int32_t h[(kLevels + 1) * 8];
+    for (int t = threadIdx.x; t < (kLevels + 1) * 8; t += blockDim.x) h[t] = 0;
+    __syncthreads();
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const int g = lvl[c] * 8 + (int)(key[c] & 7u);
-    ck[c] = (uint64_t)g;
-    idx[c] = (int32_t)c;
-    atomicAdd(&cnt[g], 1);
+    if (c < nc) {
+        const int g = lvl[c] * 8 + (int)(key[c] & 7u);
+        ck[c] = (uint64_t)g;
+        idx[c] = (int32_t)c;
+        atomicAdd(&h[g], 1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (kLevels + 1) * 8; t += blockDim.x)
+        if (h[t]) atomicAdd(&cnt[t], h[t]);
 }
 
 __global__ __launch_bounds__(256) void k_fill_tiles(const uint64_t *ck, const int32_t *idx, int64_t nc,
-                                                    const int64_t *gstart, const int64_t *gtile, int32_t *tile_tgt,
-                                                    int32_t *tile_pos)
+                                                    const int64_t *gstart, const int64_t *gtile, int TW,
+                                                    int32_t *tile_tgt, int32_t *tile_pos)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nc) return;
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(256) void k_fill_tiles(const uint64_t *ck, const in
         return;
     }
     const int64_t r = j - gstart[g];
-    const int64_t p = (gtile[g] + r / kTileW) * kTileW + r % kTileW;
+    const int64_t p = (gtile[g] + r / TW) * TW + r % TW;
     tile_tgt[p] = c;
     tile_pos[c] = (int32_t)p;
 }
@@ -197,23 +204,21 @@ __global__ __launch_bounds__(256) void k_csr_offsets(const uint64_t *keys, int64
     off[c] = lo;
 }
 
-__global__ __launch_bounds__(256) void k_csr_sources(const uint64_t *keys, int64_t np, int cbits, int32_t *src,
-                                                     const int32_t *beg, const int32_t *end,
-                                                     unsigned long long *body_pairs)
+__global__ __launch_bounds__(256) void k_csr_sources(const uint64_t *keys, int64_t np, int cbits, int32_t *src)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t bp = 0;
-    if (k < np) {
-        const uint64_t key = keys[k];
-        const int32_t s = (int32_t)(key & ((1ull << cbits) - 1));
-        const int32_t t = (int32_t)(key >> cbits);
-        src[k] = s;
-        if (body_pairs) bp = (uint64_t)(end[t] - beg[t]) * (uint64_t)(end[s] - beg[s]);
-    }
-    if (body_pairs) {
-        for (int o = 32; o > 0; o >>= 1) bp += __shfl_xor(bp, o, 64);
-        if ((threadIdx.x & 63) == 0 && bp) atomicAdd(body_pairs, (unsigned long long)bp);
-    }
+    if (k < np) src[k] = (int32_t)(keys[k] & ((1ull << cbits) - 1));
+}
+
+// Body pairs of one target's list: |A| * sum_B |B| (one thread per cell).
+__global__ __launch_bounds__(256) void k_body_pairs(const int64_t *off, const int32_t *src, const int32_t *beg,
+                                                    const int32_t *end, int64_t nc, int64_t *out)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int64_t s = 0;
+    for (int64_t k = off[c]; k < off[c + 1]; ++k) s += end[src[k]] - beg[src[k]];
+    out[c] = s * (int64_t)(end[c] - beg[c]);
 }
 
 // Same-level acceptance as the traversal evaluates it (equal sides: s = 2,
@@ -284,7 +289,7 @@ static int bits_for(int64_t v)
 }
 
 static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int64_t **off, int32_t **src,
-                        unsigned long long *body_pairs, hipStream_t s)
+                        int64_t *body_pairs_dev, hipStream_t s)
 {
     radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s);
     *off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (P->ncell + 1)));
@@ -292,8 +297,17 @@ static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int6
     k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits, P->ncell, *off);
     FMM_HIP(hipGetLastError());
     if (np > 0) {
-        k_csr_sources<<<grid1(np, 256), 256, 0, s>>>(keys, np, cbits, *src, P->c_beg, P->c_end, body_pairs);
+        k_csr_sources<<<grid1(np, 256), 256, 0, s>>>(keys, np, cbits, *src);
         FMM_HIP(hipGetLastError());
+    }
+    if (body_pairs_dev) {
+        int64_t *per = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
+        int64_t *scn = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
+        k_body_pairs<<<grid1(P->ncell, 256), 256, 0, s>>>(*off, *src, P->c_beg, P->c_end, P->ncell, per);
+        FMM_HIP(hipGetLastError());
+        scan_exclusive_i64(per, scn, P->ncell, body_pairs_dev, P->al, s);
+        P->al.free(scn);
+        P->al.free(per);
     }
 }
 
@@ -326,7 +340,7 @@ void traverse(fmm_plan *P, hipStream_t s)
             continue;
         }
         gtile[g] = tiles;
-        tiles += (hcnt[g] + kTileW - 1) / kTileW;
+        tiles += (hcnt[g] + P->TW - 1) / P->TW;
     }
     for (int l = 0; l <= P->depth; ++l) {
         P->lv[l].tile0 = (l == 0) ? 0 : -1;
@@ -335,7 +349,7 @@ void traverse(fmm_plan *P, hipStream_t s)
             const int g = l * 8 + c;
             if (gtile[g] < 0) continue;
             if (P->lv[l].tile0 < 0) P->lv[l].tile0 = gtile[g];
-            P->lv[l].ntile += (hcnt[g] + kTileW - 1) / kTileW;
+            P->lv[l].ntile += (hcnt[g] + P->TW - 1) / P->TW;
         }
         if (P->lv[l].tile0 < 0) P->lv[l].tile0 = tiles;
     }
@@ -343,20 +357,20 @@ void traverse(fmm_plan *P, hipStream_t s)
     int64_t *d_gs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 2 * G));
     FMM_HIP(hipMemcpyAsync(d_gs, gstart.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, s));
     FMM_HIP(hipMemcpyAsync(d_gs + G, gtile.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, s));
-    P->tile_tgt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, tiles * kTileW)));
+    P->tile_tgt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, tiles * P->TW)));
     P->tile_cls = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, tiles)));
     int32_t *tile_pos = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc));
     if (tiles > 0) {
-        k_fill_i32<<<grid1(tiles * kTileW, 256), 256, 0, s>>>(P->tile_tgt, tiles * kTileW, -1);
+        k_fill_i32<<<grid1(tiles * P->TW, 256), 256, 0, s>>>(P->tile_tgt, tiles * P->TW, -1);
         FMM_HIP(hipGetLastError());
     }
-    k_fill_tiles<<<grid1(nc, 256), 256, 0, s>>>(ck, idx, nc, d_gs, d_gs + G, P->tile_tgt, tile_pos);
+    k_fill_tiles<<<grid1(nc, 256), 256, 0, s>>>(ck, idx, nc, d_gs, d_gs + G, P->TW, P->tile_tgt, tile_pos);
     FMM_HIP(hipGetLastError());
     {
         std::vector<int32_t> tc(std::max<int64_t>(1, tiles), 0);
         for (int g = 0; g < G; ++g)
             if (gtile[g] >= 0)
-                for (int64_t t = 0; t < (hcnt[g] + kTileW - 1) / kTileW; ++t) tc[gtile[g] + t] = g % 8;
+                for (int64_t t = 0; t < (hcnt[g] + P->TW - 1) / P->TW; ++t) tc[gtile[g] + t] = g % 8;
         FMM_HIP(hipMemcpyAsync(P->tile_cls, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice, s));
         FMM_HIP(hipStreamSynchronize(s));
     }
@@ -365,7 +379,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     al.free(idx);
     al.free(ck);
 
-    const int64_t nslots = tiles * (int64_t)P->K * kTileW;
+    const int64_t nslots = tiles * (int64_t)P->K * P->TW;
     P->slots = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nslots)));
     if (nslots > 0) {
         k_fill_i32<<<grid1(nslots, 256), 256, 0, s>>>(P->slots, nslots, -1);
@@ -383,6 +397,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     T.slots = P->slots;
     T.K = P->K;
     T.R = P->R;
+    T.TW = P->TW;
     T.t4 = P->t4;
 
     const int cbits = bits_for(nc);
@@ -465,12 +480,12 @@ void traverse(fmm_plan *P, hipStream_t s)
     };
     uint64_t *p2p_all = concat(p2p_parts, np2p);
     uint64_t *cross_all = concat(cross_parts, ncross);
-    FMM_HIP(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s));
-    sort_to_csr(P, p2p_all, np2p, cbits, &P->p2p_off, &P->p2p_src, d_cnt, s);
+    int64_t *d_bp = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+    sort_to_csr(P, p2p_all, np2p, cbits, &P->p2p_off, &P->p2p_src, d_bp, s);
     sort_to_csr(P, cross_all, ncross, cbits, &P->m2lx_off, &P->m2lx_src, nullptr, s);
-    FMM_HIP(hipMemcpyAsync(h_cnt, d_cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipMemcpyAsync(&P->p2p_body_pairs, d_bp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     FMM_HIP(hipStreamSynchronize(s));
-    P->p2p_body_pairs = (int64_t)h_cnt[0];
+    al.free(d_bp);
     for (auto &pr : p2p_parts) al.free(pr.first);
     for (auto &pr : cross_parts) al.free(pr.first);
     al.free(p2p_all);

@@ -58,18 +58,38 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const T *x, int64_t n, Box
     }
 }
 
-__global__ void k_bbox_final(BoxPart *parts, int nparts)
+__global__ __launch_bounds__(256) void k_bbox_final(BoxPart *parts, int nparts)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    BoxPart b = parts[0];
-    for (int k = 1; k < nparts; ++k) {
+    __shared__ double s_lo[3][256], s_hi[3][256];
+    __shared__ int s_bad[256];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
         for (int d = 0; d < 3; ++d) {
-            b.lo[d] = fmin(b.lo[d], parts[k].lo[d]);
-            b.hi[d] = fmax(b.hi[d], parts[k].hi[d]);
+            lo[d] = fmin(lo[d], parts[k].lo[d]);
+            hi[d] = fmax(hi[d], parts[k].hi[d]);
         }
-        b.bad |= parts[k].bad;
+        bad |= parts[k].bad;
     }
-    parts[0] = b;
+    for (int d = 0; d < 3; ++d) { s_lo[d][threadIdx.x] = lo[d]; s_hi[d][threadIdx.x] = hi[d]; }
+    s_bad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            for (int d = 0; d < 3; ++d) {
+                s_lo[d][threadIdx.x] = fmin(s_lo[d][threadIdx.x], s_lo[d][threadIdx.x + o]);
+                s_hi[d][threadIdx.x] = fmax(s_hi[d][threadIdx.x], s_hi[d][threadIdx.x + o]);
+            }
+            s_bad[threadIdx.x] |= s_bad[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        BoxPart b;
+        for (int d = 0; d < 3; ++d) { b.lo[d] = s_lo[d][0]; b.hi[d] = s_hi[d][0]; }
+        b.bad = s_bad[0];
+        parts[0] = b;
+    }
 }
 
 // Spread the low 21 bits of v so that bit b lands at bit 3b.
@@ -239,7 +259,7 @@ void launch_bbox(const void *x, int64_t n, BoxPart *parts, int nparts, hipStream
 {
     k_bbox_partial<T><<<nparts, 256, 0, s>>>(static_cast<const T *>(x), n, parts);
     FMM_HIP(hipGetLastError());
-    k_bbox_final<<<1, 64, 0, s>>>(parts, nparts);
+    k_bbox_final<<<1, 256, 0, s>>>(parts, nparts);
     FMM_HIP(hipGetLastError());
 }
 
