@@ -366,10 +366,10 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         traverse(P, s);
         allocator_flush(P->al);
         make_operators(P, s);
-        m2l_prepare(P);
+        m2l_prepare(P, s);
         const bool f64 = P->precision == FMM_PREC_FP64;
         const size_t esz = f64 ? sizeof(double) : sizeof(float);
-        const size_t ncoef = (size_t)P->ncell * P->P2pad;
+        const size_t ncoef = (size_t)(P->ncell + 1) * P->P2pad;  // + one all-zero row
         P->Mc = plan_alloc(P, esz * ncoef);
         P->Lc = plan_alloc(P, esz * ncoef);
         if (f64) {

@@ -116,6 +116,9 @@ struct fmm_plan {
     int32_t *tile_cls = nullptr;     // [ntile] octant class
     int32_t *slots = nullptr;        // [ntile*K*TW] source cell or -1
     void *m2l_part = nullptr;        // [KS][ntile*TW][P2pad] partial sums when KS > 1
+    int32_t *tile_kl = nullptr;      // [ntile][K] stencil entries with a source, per tile
+    int32_t *tile_nk = nullptr;      // [ntile] length of that list
+    int32_t *slot_none = nullptr;    // [TW] all -1 (source row of an entry past the list)
     int32_t *st_op = nullptr;        // [8*K] operator index of stencil entry
     int32_t *st_kidx = nullptr;      // [8*(2R+1)^3] stencil entry of (class, t) or -1
     std::vector<int32_t> h_st_t;     // [8*K*3] offsets (host copy)
@@ -126,7 +129,7 @@ struct fmm_plan {
     double *m2m_d = nullptr, *l2l_d = nullptr; // float64 versions
 
     // coefficients
-    void *Mc = nullptr, *Lc = nullptr;    // [ncell*P2pad] compute type
+    void *Mc = nullptr, *Lc = nullptr;    // [(ncell+1)*P2pad] compute type; row ncell stays zero
     double *M64 = nullptr, *L64 = nullptr;// [ncoarse*P2pad]
     // evaluation outputs in sorted order, compute type
     void *phi_s = nullptr, *E_s = nullptr;    // [n], [3n]
@@ -157,7 +160,7 @@ void downward_l2l(fmm_plan *P, hipStream_t s);
 void l2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
 // m2l.hip
 int m2l_tile_width(int p, bool f64);
-void m2l_prepare(fmm_plan *P);
+void m2l_prepare(fmm_plan *P, hipStream_t s);
 void m2l(fmm_plan *P, hipStream_t s);
 // p2p.hip
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);

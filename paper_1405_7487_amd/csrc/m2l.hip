@@ -70,19 +70,26 @@ __host__ __device__ constexpr int m2l_sch(int RT, int bytes)
 }
 
 // Batched same-level M2L.  Block = 4 waves = one tile of TW = 64 CG targets of
-// one octant class, restricted to the stencil chunk [k0, k1) (ks = block mod
-// KS, so that blocks on one XCD share a chunk of operators in its L2).  For
-// every stencil entry k the block stages the common operator T(t_k) in LDS;
-// each wave multiplies it by its 16 CG gathered source multipoles:
+// one octant class, restricted to chunk ks = block mod KS of the tile's list
+// of stencil entries that have at least one source (chunks, not tiles, vary
+// fastest across blocks, so blocks resident on one XCD share operators in its
+// L2).  For every listed entry k the block stages the common operator T(t_k)
+// in LDS; each wave multiplies it by its 16 CG gathered source multipoles:
 //     D[i][j] = sum_k A[i][k] B[k][j] (16x16x4 MFMA), A = operator fragment
 //     (lane l: A[l%16][l/16]), B = multipoles (lane l: B[l/16][l%16]); lane l
 //     accumulates D[acc_row(l/16, e)][l%16] in slot e.
-// The next stage of the operator and the next sources are fetched while the
-// current stage is multiplied.
+// The loop body has no divergent branch and never edits loaded data: the
+// next operator stage and the next entry's sources (slot indices two entries
+// ahead) are fetched while the current stage is multiplied; a missing source
+// reads the all-zero multipole row zero_row (= ncell).
 template <class T, int RT, int CG, int SCH>
 __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__ tile_cls,
-                                                     const int32_t *__restrict__ slots, const int32_t *__restrict__ st_op,
-                                                     int K, int KS, const T *__restrict__ Tf, const T *__restrict__ M,
+                                                     const int32_t *__restrict__ slots,
+                                                     const int32_t *__restrict__ tile_kl,
+                                                     const int32_t *__restrict__ tile_nk,
+                                                     const int32_t *__restrict__ st_op, int K, int KS,
+                                                     const int32_t *__restrict__ slot_none, int zero_row,
+                                                     const T *__restrict__ Tf, const T *__restrict__ M,
                                                      T *__restrict__ part, const int32_t *__restrict__ tile_tgt,
                                                      T *__restrict__ L, int64_t ntile)
 {
@@ -100,9 +107,12 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
     const int64_t tile = b / KS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
     const int cls = tile_cls[tile];
-    const int Kc = (K + KS - 1) / KS;
-    const int k0 = ks * Kc, k1 = min(K, k0 + Kc);
+    const int nk = tile_nk[tile];
+    const int Kc = (nk + KS - 1) / KS;
+    const int i0 = ks * Kc, i1 = min(nk, i0 + Kc);
+    const int32_t *kl = tile_kl + tile * (int64_t)K;
     const int32_t *sl = slots + tile * (int64_t)K * TW + wave * CG * 16 + j;
+    const int32_t *sl_none = slot_none + wave * CG * 16 + j;  // a row of -1
     const int32_t *opk = st_op + (int64_t)cls * K;
 
     acc_t acc[CG][RT];
@@ -111,23 +121,18 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
 #pragma unroll
         for (int r = 0; r < RT; ++r) acc[cg][r] = acc_t{0, 0, 0, 0};
 
-    if (k0 < k1) {
-        T bc[CG][Q], bn[CG][Q];
-        int srcc[CG], srcn[CG];
+    if (i0 < i1) {
         vec_t treg[PV];
-        // operator stage (k, c): rows s in [c SCH, (c+1) SCH) of the 4 groups
+        // operator stage (entry KK, chunk CC): rows s in [CC SCH, (CC+1) SCH) of the 4 groups
 #define M2L_LOAD_STAGE(KK, CC)                                                                     \
     {                                                                                              \
         int op_ = opk[KK];                                                                         \
         op_ = op_ < 0 ? 0 : op_;                                                                   \
         _Pragma("unroll") for (int u = 0; u < PV; ++u)                                             \
         {                                                                                          \
-            const int v = tid + 256 * u;                                                           \
-            if (v < NV) {                                                                          \
-                const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);        \
-                treg[u] = *reinterpret_cast<const vec_t *>(                                        \
-                    Tf + ((int64_t)(op_ * 4 + gg) * Q + (CC) * SCH) * P2pad + rem);                \
-            }                                                                                      \
+            const int v = min(tid + 256 * u, NV - 1);                                              \
+            const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);            \
+            treg[u] = *reinterpret_cast<const vec_t *>(Tf + ((int64_t)(op_ * 4 + gg) * Q + (CC) * SCH) * P2pad + rem); \
         }                                                                                          \
     }
 #define M2L_STORE_STAGE()                                                                          \
@@ -135,65 +140,76 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
         _Pragma("unroll") for (int u = 0; u < PV; ++u)                                             \
         {                                                                                          \
             const int v = tid + 256 * u;                                                           \
-            if (v < NV) *reinterpret_cast<vec_t *>(lds + v * VN) = treg[u];                         \
+            if (NV % 256 == 0 || v < NV) *reinterpret_cast<vec_t *>(lds + v * VN) = treg[u];        \
         }                                                                                          \
     }
-#define M2L_LOAD_B(KK, DST, SRC)                                                                   \
+#define M2L_SLOTS(II, DST)                                                                         \
+    {                                                                                              \
+        const int32_t *sp_ = (II) < i1 ? sl + (int64_t)kl[II] * TW : sl_none;                      \
+        _Pragma("unroll") for (int cg = 0; cg < CG; ++cg) DST[cg] = sp_[cg * 16];                  \
+    }
+#define M2L_LOAD_B(SRC, DST)                                                                       \
     {                                                                                              \
         _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                                          \
         {                                                                                          \
-            const int sv = sl[(int64_t)(KK) * TW + cg * 16];                                      \
-            SRC[cg] = sv;                                                                          \
-            const vec_t *mp = reinterpret_cast<const vec_t *>(M + (int64_t)(sv < 0 ? 0 : sv) * P2pad + g * Q); \
+            const int sv = SRC[cg];                                                                \
+            const vec_t *mp = reinterpret_cast<const vec_t *>(M + (int64_t)(sv < 0 ? zero_row : sv) * P2pad + g * Q); \
             _Pragma("unroll") for (int v = 0; v < Q / VN; ++v)                                     \
             {                                                                                      \
-                vec_t x = sv >= 0 ? mp[v] : vec_t{};                                               \
+                const vec_t x = mp[v];                                                             \
                 _Pragma("unroll") for (int w = 0; w < VN; ++w) DST[cg][v * VN + w] = x[w];         \
             }                                                                                      \
         }                                                                                          \
     }
-        M2L_LOAD_STAGE(k0, 0);
-        M2L_STORE_STAGE();
-        M2L_LOAD_B(k0, bc, srcc);
-        for (int k = k0; k < k1; ++k) {
-            bool any = false;
-#pragma unroll
-            for (int cg = 0; cg < CG; ++cg) any |= srcc[cg] >= 0;
-            const bool active = __ballot(any) != 0ull;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const bool has_next = (c + 1 < NC) || (k + 1 < k1);
-                if (c + 1 < NC) M2L_LOAD_STAGE(k, c + 1)
-                else if (k + 1 < k1) M2L_LOAD_STAGE(k + 1, 0)
-                if (c == 0 && k + 1 < k1) M2L_LOAD_B(k + 1, bn, srcn)
-                __syncthreads();
-                if (active) {
-#pragma unroll
-                    for (int ss = 0; ss < SCH; ++ss) {
-                        T a[RT];
-                        const T *ap = lds + g * (SCH * P2pad) + ss * P2pad + j * RT;
-#pragma unroll
-                        for (int r = 0; r < RT; ++r) a[r] = ap[r];
-#pragma unroll
-                        for (int cg = 0; cg < CG; ++cg)
-#pragma unroll
-                            for (int r = 0; r < RT; ++r) acc[cg][r] = Mfma<T>::run(a[r], bc[cg][c * SCH + ss], acc[cg][r]);
-                    }
-                }
-                __syncthreads();
-                if (has_next) M2L_STORE_STAGE()
-            }
-            if (k + 1 < k1) {
-#pragma unroll
-                for (int cg = 0; cg < CG; ++cg) {
-                    srcc[cg] = srcn[cg];
-#pragma unroll
-                    for (int s2 = 0; s2 < Q; ++s2) bc[cg][s2] = bn[cg][s2];
-                }
-            }
+        T bA[CG][Q], bB[CG][Q];
+        int sA[CG], sB[CG];
+        {
+            int s0[CG];
+            M2L_SLOTS(i0, s0);
+            M2L_SLOTS(i0 + 1, sA);
+            M2L_LOAD_STAGE(kl[i0], 0);
+            M2L_LOAD_B(s0, bA);
+            M2L_STORE_STAGE();
         }
+        // One stencil entry: multiply with BCUR while the next entry's sources
+        // (slot indices SREAD) go to BNEXT and the slot indices two entries
+        // ahead go to SWRITE.  Two entries per trip with swapped roles, so no
+        // loaded register is ever copied; an odd tail runs one entry whose
+        // sources are all missing (it adds exact zeros).
+#define M2L_ENTRY(IT, BCUR, BNEXT, SREAD, SWRITE)                                                  \
+    {                                                                                              \
+        const int k_ = kl[min(IT, i1 - 1)];                                                        \
+        const int kn_ = kl[min((IT) + 1, i1 - 1)];                                                 \
+        _Pragma("unroll") for (int c = 0; c < NC; ++c)                                             \
+        {                                                                                          \
+            if (c + 1 < NC) M2L_LOAD_STAGE(k_, c + 1)                                              \
+            else M2L_LOAD_STAGE(kn_, 0)                                                            \
+            if (c == 0) {                                                                          \
+                M2L_SLOTS((IT) + 2, SWRITE);                                                       \
+                M2L_LOAD_B(SREAD, BNEXT);                                                          \
+            }                                                                                      \
+            __syncthreads();                                                                       \
+            _Pragma("unroll") for (int ss = 0; ss < SCH; ++ss)                                     \
+            {                                                                                      \
+                T a[RT];                                                                           \
+                const T *ap = lds + g * (SCH * P2pad) + ss * P2pad + j * RT;                       \
+                _Pragma("unroll") for (int r = 0; r < RT; ++r) a[r] = ap[r];                       \
+                _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                                  \
+                    _Pragma("unroll") for (int r = 0; r < RT; ++r)                                 \
+                        acc[cg][r] = Mfma<T>::run(a[r], BCUR[cg][c * SCH + ss], acc[cg][r]);       \
+            }                                                                                      \
+            __syncthreads();                                                                       \
+            M2L_STORE_STAGE();                                                                     \
+        }                                                                                          \
+    }
+        for (int it = i0; it < i1; it += 2) {
+            M2L_ENTRY(it, bA, bB, sA, sB);
+            M2L_ENTRY(it + 1, bB, bA, sB, sA);
+        }
+#undef M2L_ENTRY
 #undef M2L_LOAD_STAGE
 #undef M2L_STORE_STAGE
+#undef M2L_SLOTS
 #undef M2L_LOAD_B
     }
 #pragma unroll
@@ -212,6 +228,39 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
 #pragma unroll
             for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
     }
+}
+
+__global__ void k_fill_none(int32_t *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = -1;
+}
+
+// Per tile, the stencil entries with at least one source, in stencil order.
+__global__ __launch_bounds__(256) void k_tile_klist(const int32_t *slots, int K, int TW, int32_t *kl, int32_t *nk)
+{
+    const int64_t tile = blockIdx.x;
+    const int32_t *sl = slots + tile * (int64_t)K * TW;
+    __shared__ int32_t s_cnt[4];
+    __shared__ int32_t s_base;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < K; k0 += 256) {
+        const int k = k0 + threadIdx.x;
+        bool any = false;
+        if (k < K)
+            for (int c = 0; c < TW; ++c) any |= sl[(int64_t)k * TW + c] >= 0;
+        const uint64_t m = __ballot(any);
+        if (lane == 0) s_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = s_base;
+        for (int w = 0; w < wave; ++w) off += s_cnt[w];
+        if (any) kl[tile * (int64_t)K + off + __popcll(m & ((1ull << lane) - 1))] = k;
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nk[tile] = s_base;
 }
 
 // Sum of the KS partial products of each target, in chunk order.
@@ -370,8 +419,9 @@ void launch_batched(fmm_plan *P, hipStream_t s)
     FMM_CHECK(nb < (1ll << 31), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
     FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
     k_m2l_batched<T, RT, CG, SCH><<<(unsigned)nb, 256, 0, s>>>(
-        P->tile_cls, P->slots, P->st_op, P->K, P->KS, static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
-        static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
+        P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->KS, P->slot_none, (int)P->ncell,
+        static_cast<const T *>(P->ops),
+        static_cast<const T *>(P->Mc), static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
     FMM_HIP(hipGetLastError());
     if (P->KS > 1) {
         const int64_t ncol = P->ntile * P->TW;
@@ -407,14 +457,20 @@ int m2l_tile_width(int p, bool f64) { return 64 * m2l_cg(p2pad_of(p) / 16, f64);
 
 // Stencil split: enough blocks to fill the chip (about 8 per compute unit),
 // but at least 8 stencil entries per chunk.
-void m2l_prepare(fmm_plan *P)
+void m2l_prepare(fmm_plan *P, hipStream_t s)
 {
     P->KS = 1;
     if (P->ntile <= 0 || P->K <= 0) return;
-    int64_t ks = (2048 + P->ntile - 1) / P->ntile;
-    ks = std::min<int64_t>(ks, 16);
-    ks = std::min<int64_t>(ks, std::max(1, P->K / 8));
-    P->KS = (int)std::max<int64_t>(1, ks);
+    P->tile_kl = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->ntile * P->K));
+    P->slot_none = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->TW));
+    k_fill_none<<<1, 256, 0, s>>>(P->slot_none, P->TW);
+    P->tile_nk = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->ntile));
+    k_tile_klist<<<(unsigned)P->ntile, 256, 0, s>>>(P->slots, P->K, P->TW, P->tile_kl, P->tile_nk);
+    FMM_HIP(hipGetLastError());
+    // a power of two (a divisor or multiple of the 8 XCDs), at least 8 entries per chunk
+    int64_t ks = 1;
+    while (ks < 16 && P->ntile * ks < 2048 && P->K / (2 * ks) >= 8) ks *= 2;
+    P->KS = (int)ks;
     if (P->KS > 1) {
         const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
         P->m2l_part = plan_alloc(P, esz * (size_t)P->KS * P->ntile * P->TW * P->P2pad);
