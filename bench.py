@@ -36,6 +36,7 @@ def main():
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--cpu-sample", type=int, default=256, help="oracle targets for cpu_baseline (0 = skip)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 GPU forward runs for the speedup (0 = skip)")
+    ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build evaluates one rank's share on one GPU; --gpus must be 1 "
@@ -61,7 +62,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(timed_events=None):
-        plan = F.Plan(x, prm, timing=timed_events is not None)
+        plan = F.Plan(x, prm, timing=timed_events is not None, torch_allocator=not args.pool)
         if timed_events is not None:
             timed_events[1].record(stream)
         phi, E = plan.evaluate(q)
@@ -128,7 +129,10 @@ def main():
              "p2m_ms": float(np.mean([s["ms_p2m"] for s in kern])),
              "l2l_ms": float(np.mean([s["ms_l2l"] for s in kern])),
              "l2p_ms": float(np.mean([s["ms_l2p"] for s in kern])),
-             "build_ms": float(np.mean([s["ms_build"] for s in kern]))}
+             "build_ms": float(np.mean([s["ms_build"] for s in kern])),
+             "build_tree_ms": float(np.mean([s["ms_tree"] for s in kern])),
+             "build_traverse_ms": float(np.mean([s["ms_traverse"] for s in kern])),
+             "build_ops_ms": float(np.mean([s["ms_ops"] for s in kern]))}
 
     # FP64 GPU baseline (same build + forward)
     fp64_ms = None

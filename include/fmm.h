@@ -109,8 +109,11 @@ typedef struct {
     int64_t m2l_offsets;     /* distinct same-level offsets (operators)        */
     int64_t m2l_slots;       /* slot entries scanned by the batched M2L         */
     int64_t device_bytes;    /* bytes held by the plan                          */
-    /* milliseconds of the last call, per phase (HIP events on the stream) */
-    double ms_build, ms_sort, ms_traverse;
+    /* build: host wall clock of fmm_build and of its parts (tree = box, keys,
+     * sort, cells, geometry; traverse = stencils, tiles, dual traversal, lists;
+     * ops = operator tables and M2L schedule) */
+    double ms_build, ms_tree, ms_traverse, ms_ops;
+    /* milliseconds of the last evaluation, per phase (HIP events on the stream) */
     double ms_p2m, ms_m2m, ms_m2l, ms_l2l, ms_l2p, ms_p2p, ms_evaluate, ms_adjoint;
 } fmm_stats;
 

@@ -52,7 +52,8 @@ class _Stats(C.Structure):
                 ("p", C.c_int32), ("n_m2l", C.c_int64), ("n_m2l_same", C.c_int64), ("n_m2l_cross", C.c_int64),
                 ("n_p2p", C.c_int64), ("p2p_body_pairs", C.c_int64), ("m2l_stencil", C.c_int64),
                 ("m2l_offsets", C.c_int64), ("m2l_slots", C.c_int64), ("device_bytes", C.c_int64),
-                ("ms_build", C.c_double), ("ms_sort", C.c_double), ("ms_traverse", C.c_double),
+                ("ms_build", C.c_double), ("ms_tree", C.c_double), ("ms_traverse", C.c_double),
+                ("ms_ops", C.c_double),
                 ("ms_p2m", C.c_double), ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
                 ("ms_l2p", C.c_double), ("ms_p2p", C.c_double), ("ms_evaluate", C.c_double),
                 ("ms_adjoint", C.c_double)]

@@ -361,12 +361,23 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
             return FMM_OK;
         }
         auto t0 = std::chrono::steady_clock::now();
+        auto ms_since = [](std::chrono::steady_clock::time_point a) {
+            return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+        };
         tree_build(P, x, s);
+        FMM_HIP(hipStreamSynchronize(s));
         allocator_flush(P->al);
+        P->st.ms_tree = ms_since(t0);
+        auto t1a = std::chrono::steady_clock::now();
         traverse(P, s);
+        FMM_HIP(hipStreamSynchronize(s));
         allocator_flush(P->al);
+        P->st.ms_traverse = ms_since(t1a);
+        auto t2a = std::chrono::steady_clock::now();
         make_operators(P, s);
         m2l_prepare(P, s);
+        FMM_HIP(hipStreamSynchronize(s));
+        P->st.ms_ops = ms_since(t2a);
         const bool f64 = P->precision == FMM_PREC_FP64;
         const size_t esz = f64 ? sizeof(double) : sizeof(float);
         const size_t ncoef = (size_t)(P->ncell + 1) * P->P2pad;  // + one all-zero row

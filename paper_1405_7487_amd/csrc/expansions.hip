@@ -21,6 +21,10 @@
 #include "internal.hpp"
 
 #include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace fmm {
 
@@ -190,8 +194,10 @@ __global__ __launch_bounds__(256) void k_make_shift_ops(int p, int P2pad, double
                 vl = (rim ? d.im : d.re) * sc;
             }
         }
-        m2m[((size_t)oct * P2pad + row) * P2pad + col] = vm;
-        l2l[((size_t)oct * P2pad + row) * P2pad + col] = vl;
+        // stored transposed ([oct][col][row]) so that threads of consecutive
+        // rows read consecutive addresses
+        m2m[((size_t)oct * P2pad + col) * P2pad + row] = vm;
+        l2l[((size_t)oct * P2pad + col) * P2pad + row] = vl;
     }
 }
 
@@ -202,62 +208,72 @@ __global__ __launch_bounds__(256) void k_d2f(const double *a, float *b, int64_t 
 }
 
 // ------------------------------------------------------------------ P2M
-// One thread per (leaf, order m); rolling recurrence in the degree.
+// One wave per leaf.  Each lane takes one body of a chunk (<= 64), writes the
+// p^2 real components of q conj(R(u / h)) to its LDS row (rolling Cartesian
+// recurrence), then each lane sums coefficient columns over the chunk in body
+// order.  Deterministic; no atomics.
 template <class T, class V4>
-__global__ __launch_bounds__(256) void k_p2m(const int32_t *leaves, int64_t nleaf, const int32_t *beg,
-                                             const int32_t *end, const int32_t *lvl, const V4 *ub, double S, int p,
-                                             int P2pad, T *Mc, double *M64, int64_t ncoarse)
+__global__ __launch_bounds__(64) void k_p2m(const int32_t *leaves, const int32_t *beg, const int32_t *end,
+                                            const int32_t *lvl, const V4 *ub, double S, int p, int P2pad, int chunk,
+                                            T *Mc, double *M64, int64_t ncoarse)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t li = t / p;
-    const int m = (int)(t % p);
-    if (li >= nleaf) return;
-    const int c = leaves[li];
+    extern __shared__ __align__(16) unsigned char p2m_smem[];
+    T *rows = reinterpret_cast<T *>(p2m_smem);  // [chunk][P2 + 1], chunk <= 64
+    const int lane = threadIdx.x;
+    const int c = leaves[blockIdx.x];
+    const int P2 = p * p, stride = P2 + 1;
     const T ih = (T)ldexp(1.0 / S, lvl[c]);
-    T are[kMaxP], aim[kMaxP];
-#pragma unroll
-    for (int n = 0; n < kMaxP; ++n) { are[n] = 0; aim[n] = 0; }
-    for (int32_t b = beg[c]; b < end[c]; ++b) {
-        const V4 u = ub[b];
-        const T x = u.x * ih, y = u.y * ih, z = u.z * ih, q = u.w;
-        const T r2 = x * x + y * y + z * z;
-        T mre = 1, mim = 0;
-        for (int k = 1; k <= m; ++k) {
-            const T f = (T)(-0.5) / (T)k;
-            const T nr = (mre * x - mim * y) * f;
-            const T ni = (mre * y + mim * x) * f;
-            mre = nr;
-            mim = ni;
-        }
-        T p2r = 0, p2i = 0, p1r = mre, p1i = mim;
-#pragma unroll
-        for (int n = 0; n < kMaxP; ++n) {
-            if (n < m || n >= p) continue;
-            T cr, ci;
-            if (n == m) { cr = mre; ci = mim; }
-            else if (n == m + 1) { cr = z * mre; ci = z * mim; p2r = 0; p2i = 0; }
-            else {
-                const T a = (T)(2 * n - 1), inv = (T)1 / (T)(n * n - m * m);
-                cr = (a * z * p1r - r2 * p2r) * inv;
-                ci = (a * z * p1i - r2 * p2i) * inv;
+    T acc[4] = {0, 0, 0, 0};  // coefficients lane + 64 q, q < 4 (p <= 16)
+    for (int32_t b0 = beg[c]; b0 < end[c]; b0 += chunk) {
+        const int nb = min(chunk, end[c] - b0);
+        if (lane < nb) {
+            const V4 u = ub[b0 + lane];
+            const T x = u.x * ih, y = u.y * ih, z = u.z * ih, q = u.w;
+            const T r2 = x * x + y * y + z * z;
+            T *row = rows + lane * stride;
+            T mre = q, mim = 0;  // q R_m^m
+            for (int m = 0; m < p; ++m) {
+                if (m > 0) {
+                    const T f = (T)(-0.5) / (T)m;
+                    const T nr = (mre * x - mim * y) * f;
+                    const T ni = (mre * y + mim * x) * f;
+                    mre = nr;
+                    mim = ni;
+                }
+                T p2r = 0, p2i = 0, p1r = mre, p1i = mim;
+                for (int n = m; n < p; ++n) {
+                    T cr, ci;
+                    if (n == m) { cr = mre; ci = mim; }
+                    else if (n == m + 1) { cr = z * mre; ci = z * mim; }
+                    else {
+                        const T a = (T)(2 * n - 1), inv = (T)1 / (T)(n * n - m * m);
+                        cr = (a * z * p1r - r2 * p2r) * inv;
+                        ci = (a * z * p1i - r2 * p2i) * inv;
+                    }
+                    if (n > m) { p2r = p1r; p2i = p1i; }
+                    p1r = cr;
+                    p1i = ci;
+                    const int r = ridx_re(n, m);
+                    row[r] = cr;                 // Re of q conj(R) = q Re R
+                    if (m > 0) row[r + 1] = -ci; // Im of q conj(R) = -q Im R
+                }
             }
-            if (n > m) { p2r = p1r; p2i = p1i; }
-            p1r = cr;
-            p1i = ci;
-            are[n] += q * cr;
-            aim[n] -= q * ci;
         }
-    }
-    T *dst = Mc + (int64_t)c * P2pad;
+        __syncthreads();
 #pragma unroll
-    for (int n = 0; n < kMaxP; ++n) {
-        if (n < m || n >= p) continue;
-        const int r = ridx_re(n, m);
-        dst[r] = are[n];
-        if (m > 0) dst[r + 1] = aim[n];
-        if (c < ncoarse && M64) {
-            M64[(int64_t)c * P2pad + r] = (double)are[n];
-            if (m > 0) M64[(int64_t)c * P2pad + r + 1] = (double)aim[n];
+        for (int qd = 0; qd < 4; ++qd) {
+            const int col = lane + 64 * qd;
+            if (col < P2)
+                for (int j = 0; j < nb; ++j) acc[qd] += rows[j * stride + col];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+        const int col = lane + 64 * qd;
+        if (col < P2) {
+            Mc[(int64_t)c * P2pad + col] = acc[qd];
+            if (c < ncoarse && M64) M64[(int64_t)c * P2pad + col] = (double)acc[qd];
         }
     }
 }
@@ -281,9 +297,9 @@ __global__ __launch_bounds__(256) void k_m2m(int64_t pstart, int64_t pcount, con
     for (int k = 0; k < nc; ++k) {
         const int64_t ch = cbeg[c] + k;
         const int oct = (int)(key[ch] & 7u);
-        const TC *w = W + ((int64_t)oct * P2pad + row) * P2pad;
+        const TC *w = W + (int64_t)oct * P2pad * P2pad + row;
         const TI *mc = src + ch * P2pad;
-        for (int col = 0; col < P2; ++col) acc += w[col] * (TC)mc[col];
+        for (int col = 0; col < P2; ++col) acc += w[(int64_t)col * P2pad] * (TC)mc[col];
     }
     dst[c * P2pad + row] = acc;
     if (dst32) dst32[c * P2pad + row] = (float)acc;
@@ -303,11 +319,11 @@ __global__ __launch_bounds__(256) void k_l2l(int64_t cstart, int64_t ccount, con
     const int64_t c = cstart + cc;
     const int64_t pa = par[c];
     const int oct = (int)(key[c] & 7u);
-    const TC *v = V + ((int64_t)oct * P2pad + row) * P2pad;
+    const TC *v = V + (int64_t)oct * P2pad * P2pad + row;
     const TP *lp = lpar + pa * P2pad;
     TC acc = m2l_is_double ? (TC) static_cast<const double *>(m2l_in)[c * P2pad + row]
                            : (TC) static_cast<const float *>(m2l_in)[c * P2pad + row];
-    for (int col = 0; col < P2; ++col) acc += v[col] * (TC)lp[col];
+    for (int col = 0; col < P2; ++col) acc += v[(int64_t)col * P2pad] * (TC)lp[col];
     dst[c * P2pad + row] = (TO)acc;
 }
 
@@ -411,43 +427,70 @@ __global__ __launch_bounds__(256) void k_l2p(int64_t n, const int32_t *leaf_of, 
 
 }  // namespace
 
+// Operator tables depend only on (p, theta, precision); they are generated
+// once per device and kept for the life of the process.
+namespace {
+struct OpCache {
+    void *ops = nullptr, *m2m_c = nullptr, *l2l_c = nullptr;
+    double *m2m_d = nullptr, *l2l_d = nullptr;
+};
+std::mutex g_ops_mu;
+std::map<std::tuple<int, int, uint64_t, int>, OpCache> g_ops;
+}  // namespace
+
 void make_operators(fmm_plan *P, hipStream_t s)
 {
     const int P2pad = P->P2pad;
     const bool f64 = P->precision == FMM_PREC_FP64;
-    const size_t opn = (size_t)std::max(1, P->nops) * P2pad * P2pad;
-    int32_t *d_ot = static_cast<int32_t *>(P->al.alloc(sizeof(int32_t) * std::max<size_t>(3, P->h_ops_t.size())));
-    if (!P->h_ops_t.empty())
-        FMM_HIP(hipMemcpyAsync(d_ot, P->h_ops_t.data(), sizeof(int32_t) * P->h_ops_t.size(), hipMemcpyHostToDevice, s));
-    if (f64) {
-        P->ops = plan_alloc(P, sizeof(double) * opn);
-        if (P->nops > 0)
-            k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<double *>(P->ops),
-                                                            nullptr);
-    } else {
-        P->ops = plan_alloc(P, sizeof(float) * opn);
-        if (P->nops > 0)
-            k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<float *>(P->ops),
-                                                           nullptr);
-    }
-    FMM_HIP(hipGetLastError());
-    const size_t shn = (size_t)8 * P2pad * P2pad;
-    P->m2m_d = static_cast<double *>(plan_alloc(P, sizeof(double) * shn));
-    P->l2l_d = static_cast<double *>(plan_alloc(P, sizeof(double) * shn));
-    k_make_shift_ops<<<8, 256, 0, s>>>(P->p, P2pad, P->m2m_d, P->l2l_d);
-    FMM_HIP(hipGetLastError());
-    if (f64) {
-        P->m2m_c = P->m2m_d;
-        P->l2l_c = P->l2l_d;
-    } else {
-        P->m2m_c = plan_alloc(P, sizeof(float) * shn);
-        P->l2l_c = plan_alloc(P, sizeof(float) * shn);
-        k_d2f<<<grid1(shn, 256), 256, 0, s>>>(P->m2m_d, static_cast<float *>(P->m2m_c), shn);
-        k_d2f<<<grid1(shn, 256), 256, 0, s>>>(P->l2l_d, static_cast<float *>(P->l2l_c), shn);
+    int dev = 0;
+    FMM_HIP(hipGetDevice(&dev));
+    uint64_t bits;
+    std::memcpy(&bits, &P->t4, sizeof(bits));
+    std::lock_guard<std::mutex> lk(g_ops_mu);
+    const auto key = std::make_tuple(dev, P->p, bits, f64 ? 1 : 0);
+    auto it = g_ops.find(key);
+    if (it == g_ops.end()) {
+        OpCache C;
+        const size_t opn = (size_t)std::max(1, P->nops) * P2pad * P2pad;
+        int32_t *d_ot = nullptr;
+        FMM_HIP(hipMalloc(&d_ot, sizeof(int32_t) * std::max<size_t>(3, P->h_ops_t.size())));
+        if (!P->h_ops_t.empty())
+            FMM_HIP(hipMemcpy(d_ot, P->h_ops_t.data(), sizeof(int32_t) * P->h_ops_t.size(), hipMemcpyHostToDevice));
+        FMM_HIP(hipMalloc(&C.ops, (f64 ? sizeof(double) : sizeof(float)) * opn));
+        if (P->nops > 0) {
+            if (f64)
+                k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<double *>(C.ops),
+                                                                nullptr);
+            else
+                k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<float *>(C.ops),
+                                                               nullptr);
+            FMM_HIP(hipGetLastError());
+        }
+        const size_t shn = (size_t)8 * P2pad * P2pad;
+        FMM_HIP(hipMalloc(&C.m2m_d, sizeof(double) * shn));
+        FMM_HIP(hipMalloc(&C.l2l_d, sizeof(double) * shn));
+        k_make_shift_ops<<<8, 256, 0, s>>>(P->p, P2pad, C.m2m_d, C.l2l_d);
         FMM_HIP(hipGetLastError());
+        if (f64) {
+            C.m2m_c = C.m2m_d;
+            C.l2l_c = C.l2l_d;
+        } else {
+            FMM_HIP(hipMalloc(&C.m2m_c, sizeof(float) * shn));
+            FMM_HIP(hipMalloc(&C.l2l_c, sizeof(float) * shn));
+            k_d2f<<<grid1(shn, 256), 256, 0, s>>>(C.m2m_d, static_cast<float *>(C.m2m_c), shn);
+            k_d2f<<<grid1(shn, 256), 256, 0, s>>>(C.l2l_d, static_cast<float *>(C.l2l_c), shn);
+            FMM_HIP(hipGetLastError());
+        }
+        FMM_HIP(hipStreamSynchronize(s));
+        FMM_HIP(hipFree(d_ot));
+        it = g_ops.emplace(key, C).first;
     }
-    FMM_HIP(hipStreamSynchronize(s));
-    P->al.free(d_ot);
+    const OpCache &C = it->second;
+    P->ops = C.ops;
+    P->m2m_c = C.m2m_c;
+    P->l2l_c = C.l2l_c;
+    P->m2m_d = C.m2m_d;
+    P->l2l_d = C.l2l_d;
 }
 
 // P2M at every leaf, then M2M from the finest level up.
@@ -456,15 +499,18 @@ void upward(fmm_plan *P, const void *ub, hipStream_t s)
     const int p = P->p, P2 = P->P2, P2pad = P->P2pad;
     const bool f64 = P->precision == FMM_PREC_FP64;
     if (P->nleaf > 0) {
-        const int64_t nt = P->nleaf * p;
+        const unsigned nb = (unsigned)P->nleaf;
+        const size_t esz = f64 ? sizeof(double) : sizeof(float);
+        const int chunk = (int)std::min<size_t>(64, (60 * 1024) / ((P2 + 1) * esz));
+        const size_t smem = (size_t)chunk * (P2 + 1) * esz;
         if (f64)
-            k_p2m<double, double4><<<grid1(nt, 256), 256, 0, s>>>(P->leaves, P->nleaf, P->c_beg, P->c_end, P->c_lvl,
-                                                                   static_cast<const double4 *>(ub), P->S, p, P2pad,
-                                                                   static_cast<double *>(P->Mc), nullptr, 0);
+            k_p2m<double, double4><<<nb, 64, smem, s>>>(P->leaves, P->c_beg, P->c_end, P->c_lvl,
+                                                        static_cast<const double4 *>(ub), P->S, p, P2pad, chunk,
+                                                        static_cast<double *>(P->Mc), nullptr, 0);
         else
-            k_p2m<float, float4><<<grid1(nt, 256), 256, 0, s>>>(P->leaves, P->nleaf, P->c_beg, P->c_end, P->c_lvl,
-                                                                 static_cast<const float4 *>(ub), P->S, p, P2pad,
-                                                                 static_cast<float *>(P->Mc), P->M64, P->ncoarse);
+            k_p2m<float, float4><<<nb, 64, smem, s>>>(P->leaves, P->c_beg, P->c_end, P->c_lvl,
+                                                      static_cast<const float4 *>(ub), P->S, p, P2pad, chunk,
+                                                      static_cast<float *>(P->Mc), P->M64, P->ncoarse);
         FMM_HIP(hipGetLastError());
     }
     const int cfl = f64 ? P->depth + 1 : std::min(P->cfl, P->depth + 1);

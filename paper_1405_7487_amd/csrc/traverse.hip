@@ -22,7 +22,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <array>
 #include <map>
+#include <mutex>
 
 namespace fmm {
 
@@ -229,10 +231,20 @@ int ceil_div2(int v) { return (v >= 0) ? (v + 1) / 2 : -((-v) / 2); }
 
 }  // namespace
 
-// Host: the stencils S_c and the operator table.
-static void build_stencils(fmm_plan *P)
+// The stencils S_c depend only on theta; they are computed once per device
+// and kept for the life of the process.
+namespace {
+struct StencilCache {
+    int K = 0, R = 0, nops = 0;
+    std::vector<int32_t> ops_t, st_t;
+    int32_t *d_op = nullptr, *d_kidx = nullptr;
+};
+std::mutex g_stencil_mu;
+std::map<std::pair<int, uint64_t>, StencilCache> g_stencils;
+
+StencilCache make_stencils(double t4)
 {
-    const double t4 = P->t4;
+    StencilCache C;
     // parent offsets that fail the criterion satisfy |T|^2 <= 12 / t4
     const int rT = (int)std::floor(std::sqrt(12.0 / t4)) + 1;
     const int R = 2 * rT + 1;
@@ -251,34 +263,55 @@ static void build_stencils(fmm_plan *P)
                 }
     }
     int id = 0;
-    P->h_ops_t.clear();
     for (auto &kv : uni) {
         kv.second = id++;
-        P->h_ops_t.insert(P->h_ops_t.end(), kv.first.begin(), kv.first.end());
+        C.ops_t.insert(C.ops_t.end(), kv.first.begin(), kv.first.end());
     }
     size_t K = 0;
     for (int c = 0; c < 8; ++c) K = std::max(K, S[c].size());
-    P->K = (int)K;
-    P->R = R;
-    P->nops = id;
-    // stencil entries ordered by operator index so that all classes sweep the
-    // operator table in the same order
-    std::vector<int32_t> op(8 * K, -1), kidx((size_t)8 * (2 * R + 1) * (2 * R + 1) * (2 * R + 1), -1);
-    P->h_st_t.assign(8 * K * 3, 0);
+    C.K = (int)K;
+    C.R = R;
+    C.nops = id;
+    // stencil entries in lexicographic offset order (= operator order), so
+    // that all classes sweep the operator table alike
+    std::vector<int32_t> op(std::max<size_t>(1, 8 * K), -1), kidx((size_t)8 * (2 * R + 1) * (2 * R + 1) * (2 * R + 1), -1);
+    C.st_t.assign(8 * K * 3, 0);
     const int W = 2 * R + 1;
     for (int c = 0; c < 8; ++c) {
         std::sort(S[c].begin(), S[c].end());
         for (size_t k = 0; k < S[c].size(); ++k) {
             const auto &t = S[c][k];
             op[c * K + k] = uni[t];
-            for (int d = 0; d < 3; ++d) P->h_st_t[(c * K + k) * 3 + d] = t[d];
+            for (int d = 0; d < 3; ++d) C.st_t[(c * K + k) * 3 + d] = t[d];
             kidx[(size_t)c * W * W * W + ((t[0] + R) * W + (t[1] + R)) * W + (t[2] + R)] = (int32_t)k;
         }
     }
-    P->st_op = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<size_t>(1, op.size())));
-    P->st_kidx = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * kidx.size()));
-    FMM_HIP(hipMemcpy(P->st_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice));
-    FMM_HIP(hipMemcpy(P->st_kidx, kidx.data(), sizeof(int32_t) * kidx.size(), hipMemcpyHostToDevice));
+    FMM_HIP(hipMalloc(&C.d_op, sizeof(int32_t) * op.size()));
+    FMM_HIP(hipMalloc(&C.d_kidx, sizeof(int32_t) * kidx.size()));
+    FMM_HIP(hipMemcpy(C.d_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice));
+    FMM_HIP(hipMemcpy(C.d_kidx, kidx.data(), sizeof(int32_t) * kidx.size(), hipMemcpyHostToDevice));
+    return C;
+}
+}  // namespace
+
+static void build_stencils(fmm_plan *P)
+{
+    int dev = 0;
+    FMM_HIP(hipGetDevice(&dev));
+    uint64_t bits;
+    std::memcpy(&bits, &P->t4, sizeof(bits));
+    std::lock_guard<std::mutex> lk(g_stencil_mu);
+    auto key = std::make_pair(dev, bits);
+    auto it = g_stencils.find(key);
+    if (it == g_stencils.end()) it = g_stencils.emplace(key, make_stencils(P->t4)).first;
+    const StencilCache &C = it->second;
+    P->K = C.K;
+    P->R = C.R;
+    P->nops = C.nops;
+    P->h_ops_t = C.ops_t;
+    P->h_st_t = C.st_t;
+    P->st_op = C.d_op;
+    P->st_kidx = C.d_kidx;
 }
 
 static int bits_for(int64_t v)
