@@ -393,6 +393,8 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         // padded coefficient slots stay zero forever
         FMM_HIP(hipMemsetAsync(P->Mc, 0, esz * ncoef, s));
         if (!f64 && P->M64) FMM_HIP(hipMemsetAsync(P->M64, 0, sizeof(double) * P->ncoarse * P->P2pad, s));
+        if (!f64 && P->L64) FMM_HIP(hipMemsetAsync(P->L64, 0, sizeof(double) * P->ncoarse * P->P2pad, s));
+        FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * ncoef, s));
         P->phi_s = plan_alloc(P, esz * n);
         P->E_s = plan_alloc(P, esz * 3 * n);
         FMM_HIP(hipStreamSynchronize(s));
@@ -559,7 +561,11 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
     st.n_m2l_cross = P->n_m2l_cross;
     st.n_m2l = P->n_m2l_same + P->n_m2l_cross;
     st.n_p2p = P->n_p2p;
-    st.p2p_body_pairs = P->p2p_body_pairs;
+    try {
+        st.p2p_body_pairs = P->n > 0 ? p2p_body_pairs(P, P->al.stream) : 0;
+    } catch (const Error &e) {
+        return fail(e);
+    }
     st.m2l_stencil = P->K;
     st.m2l_offsets = P->nops;
     st.m2l_slots = P->ntile * (int64_t)P->K * P->TW;

@@ -299,7 +299,12 @@ __global__ __launch_bounds__(256) void k_m2m(int64_t pstart, int64_t pcount, con
         const int oct = (int)(key[ch] & 7u);
         const TC *w = W + (int64_t)oct * P2pad * P2pad + row;
         const TI *mc = src + ch * P2pad;
-        for (int col = 0; col < P2; ++col) acc += w[(int64_t)col * P2pad] * (TC)mc[col];
+        TC a4[4] = {0, 0, 0, 0};  // independent chains; P2pad is a multiple of 16
+        for (int col = 0; col < P2pad; col += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a4[u & 3] += w[(int64_t)(col + u) * P2pad] * (TC)mc[col + u];
+        }
+        acc += (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
     dst[c * P2pad + row] = acc;
     if (dst32) dst32[c * P2pad + row] = (float)acc;
@@ -323,7 +328,12 @@ __global__ __launch_bounds__(256) void k_l2l(int64_t cstart, int64_t ccount, con
     const TP *lp = lpar + pa * P2pad;
     TC acc = m2l_is_double ? (TC) static_cast<const double *>(m2l_in)[c * P2pad + row]
                            : (TC) static_cast<const float *>(m2l_in)[c * P2pad + row];
-    for (int col = 0; col < P2; ++col) acc += v[(int64_t)col * P2pad] * (TC)lp[col];
+    TC a4[4] = {0, 0, 0, 0};  // independent chains; P2pad is a multiple of 16
+    for (int col = 0; col < P2pad; col += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a4[u & 3] += v[(int64_t)(col + u) * P2pad] * (TC)lp[col + u];
+    }
+    acc += (a4[0] + a4[1]) + (a4[2] + a4[3]);
     dst[c * P2pad + row] = (TO)acc;
 }
 

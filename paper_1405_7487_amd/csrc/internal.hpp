@@ -119,6 +119,7 @@ struct fmm_plan {
     int32_t *tile_kl = nullptr;      // [ntile][K] stencil entries with a source, per tile
     int32_t *tile_nk = nullptr;      // [ntile] length of that list
     int32_t *slot_none = nullptr;    // [TW] all -1 (source row of an entry past the list)
+    uint8_t *tile_kflag = nullptr;   // [ntile][K] 1 where the entry has a source in the tile
     int32_t *st_op = nullptr;        // [8*K] operator index of stencil entry
     int32_t *st_kidx = nullptr;      // [8*(2R+1)^3] stencil entry of (class, t) or -1
     std::vector<int32_t> h_st_t;     // [8*K*3] offsets (host copy)
@@ -153,6 +154,7 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocato
 void tree_build(fmm_plan *P, const void *x, hipStream_t s);
 // traverse.hip
 void traverse(fmm_plan *P, hipStream_t s);
+int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s);
 // expansions.hip
 void make_operators(fmm_plan *P, hipStream_t s);
 void upward(fmm_plan *P, const void *ub, hipStream_t s);

@@ -235,11 +235,12 @@ __global__ void k_fill_none(int32_t *p, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = -1;
 }
 
-// Per tile, the stencil entries with at least one source, in stencil order.
-__global__ __launch_bounds__(256) void k_tile_klist(const int32_t *slots, int K, int TW, int32_t *kl, int32_t *nk)
+// Per tile, the stencil entries with at least one source (flags set by the
+// traversal), in stencil order.
+__global__ __launch_bounds__(256) void k_tile_klist(const uint8_t *kflag, int K, int32_t *kl, int32_t *nk)
 {
     const int64_t tile = blockIdx.x;
-    const int32_t *sl = slots + tile * (int64_t)K * TW;
+    const uint8_t *fl = kflag + tile * (int64_t)K;
     __shared__ int32_t s_cnt[4];
     __shared__ int32_t s_base;
     if (threadIdx.x == 0) s_base = 0;
@@ -247,9 +248,7 @@ __global__ __launch_bounds__(256) void k_tile_klist(const int32_t *slots, int K,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int k0 = 0; k0 < K; k0 += 256) {
         const int k = k0 + threadIdx.x;
-        bool any = false;
-        if (k < K)
-            for (int c = 0; c < TW; ++c) any |= sl[(int64_t)k * TW + c] >= 0;
+        const bool any = k < K && fl[k] != 0;
         const uint64_t m = __ballot(any);
         if (lane == 0) s_cnt[wave] = __popcll(m);
         __syncthreads();
@@ -465,7 +464,7 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     P->slot_none = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->TW));
     k_fill_none<<<1, 256, 0, s>>>(P->slot_none, P->TW);
     P->tile_nk = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->ntile));
-    k_tile_klist<<<(unsigned)P->ntile, 256, 0, s>>>(P->slots, P->K, P->TW, P->tile_kl, P->tile_nk);
+    k_tile_klist<<<(unsigned)P->ntile, 256, 0, s>>>(P->tile_kflag, P->K, P->tile_kl, P->tile_nk);
     FMM_HIP(hipGetLastError());
     // a power of two (a divisor or multiple of the 8 XCDs), at least 8 entries per chunk
     int64_t ks = 1;

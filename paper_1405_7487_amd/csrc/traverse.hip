@@ -52,6 +52,7 @@ struct TreeView {
     const int32_t *tile_pos;  // cell -> tile*64 + lane (or -1)
     const int32_t *kidx;      // [8][(2R+1)^3]
     int32_t *slots;
+    uint8_t *kflag;  // [ntile][K]: entry has a source in the tile
     int K, R, TW;
     double t4;
 };
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
                 } else {
                     const int64_t tile = pos / T.TW, lane = pos % T.TW;
                     T.slots[(tile * T.K + kk) * T.TW + lane] = y;
+                    T.kflag[tile * T.K + kk] = 1;
                 }
             } else if (k == 1) {
                 cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
@@ -344,6 +346,26 @@ static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int6
     }
 }
 
+// Sum over P2P pairs of |A| |B| (a statistic; computed when asked for).
+int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s)
+{
+    if (P->p2p_body_pairs >= 0 || P->ncell == 0) return std::max<int64_t>(0, P->p2p_body_pairs);
+    int64_t *per = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
+    int64_t *scn = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
+    int64_t *tot = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t)));
+    k_body_pairs<<<grid1(P->ncell, 256), 256, 0, s>>>(P->p2p_off, P->p2p_src, P->c_beg, P->c_end, P->ncell, per);
+    FMM_HIP(hipGetLastError());
+    scan_exclusive_i64(per, scn, P->ncell, tot, P->al, s);
+    int64_t h = 0;
+    FMM_HIP(hipMemcpyAsync(&h, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    P->al.free(tot);
+    P->al.free(scn);
+    P->al.free(per);
+    P->p2p_body_pairs = h;
+    return h;
+}
+
 void traverse(fmm_plan *P, hipStream_t s)
 {
     Allocator &al = P->al;
@@ -412,6 +434,8 @@ void traverse(fmm_plan *P, hipStream_t s)
     al.free(idx);
     al.free(ck);
 
+    P->tile_kflag = static_cast<uint8_t *>(plan_alloc(P, std::max<int64_t>(1, tiles * (int64_t)P->K)));
+    if (tiles > 0) FMM_HIP(hipMemsetAsync(P->tile_kflag, 0, tiles * (int64_t)P->K, s));
     const int64_t nslots = tiles * (int64_t)P->K * P->TW;
     P->slots = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nslots)));
     if (nslots > 0) {
@@ -428,6 +452,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     T.tile_pos = tile_pos;
     T.kidx = P->st_kidx;
     T.slots = P->slots;
+    T.kflag = P->tile_kflag;
     T.K = P->K;
     T.R = P->R;
     T.TW = P->TW;
@@ -513,12 +538,9 @@ void traverse(fmm_plan *P, hipStream_t s)
     };
     uint64_t *p2p_all = concat(p2p_parts, np2p);
     uint64_t *cross_all = concat(cross_parts, ncross);
-    int64_t *d_bp = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
-    sort_to_csr(P, p2p_all, np2p, cbits, &P->p2p_off, &P->p2p_src, d_bp, s);
+    sort_to_csr(P, p2p_all, np2p, cbits, &P->p2p_off, &P->p2p_src, nullptr, s);
     sort_to_csr(P, cross_all, ncross, cbits, &P->m2lx_off, &P->m2lx_src, nullptr, s);
-    FMM_HIP(hipMemcpyAsync(&P->p2p_body_pairs, d_bp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    FMM_HIP(hipStreamSynchronize(s));
-    al.free(d_bp);
+    P->p2p_body_pairs = -1;  // counted on demand by p2p_body_pairs()
     for (auto &pr : p2p_parts) al.free(pr.first);
     for (auto &pr : cross_parts) al.free(pr.first);
     al.free(p2p_all);
