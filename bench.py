@@ -126,6 +126,7 @@ def main():
                 "frac": achieved / peak, "traffic": None, "launch_ms": p2p_ms, "flops_per_launch": p2p_flops}
     other = {"m2l_ms": m2l_ms, "m2l_tflops": m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms else None,
              "p2p_ms": p2p_ms, "p2p_tflops": p2p_flops / (p2p_ms * 1e-3) / 1e12 if p2p_ms else None,
+             "m2l_cross_ms": float(np.mean([s["ms_m2l_cross"] for s in kern])),
              "p2m_ms": float(np.mean([s["ms_p2m"] for s in kern])),
              "l2l_ms": float(np.mean([s["ms_l2l"] for s in kern])),
              "l2p_ms": float(np.mean([s["ms_l2p"] for s in kern])),
@@ -167,7 +168,7 @@ def main():
         import oracle
         tg = W.sample_targets(n, args.cpu_sample)
         c0 = time.perf_counter()
-        T = oracle.Tree(x_np, cfg["ncrit"], cfg["theta"], targets=tg)
+        T = oracle.Tree(x_np, cfg["ncrit"], cfg["theta"], targets=tg, prune=True)
         po, Eo = T.fmm(q_np, cfg["p"], targets=tg)
         c1 = time.perf_counter()
         err["vs_oracle_sampled"] = {"phi": rel(phi_h[tg], po), "E": rel(E_h[tg], Eo), "targets": int(tg.size)}

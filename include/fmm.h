@@ -115,6 +115,7 @@ typedef struct {
     double ms_build, ms_tree, ms_traverse, ms_ops;
     /* milliseconds of the last evaluation, per phase (HIP events on the stream) */
     double ms_p2m, ms_m2m, ms_m2l, ms_l2l, ms_l2p, ms_p2p, ms_evaluate, ms_adjoint;
+    double ms_m2l_cross;     /* cross-level M2L (ms_m2l: same-level, batched) */
 } fmm_stats;
 
 /* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are

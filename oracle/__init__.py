@@ -40,6 +40,8 @@ def lib():
         L.oracle_op_l2p.argtypes = [_dp, _dp, C.c_int, C.c_int64, _dp, _dp, _dp]
         L.oracle_tree_new.argtypes = [C.c_int64, _dp, C.c_int32, C.c_double, C.c_int64, _i64p]
         L.oracle_tree_new.restype = C.c_void_p
+        L.oracle_tree_new2.argtypes = [C.c_int64, _dp, C.c_int32, C.c_double, C.c_int64, _i64p, C.c_int]
+        L.oracle_tree_new2.restype = C.c_void_p
         L.oracle_tree_free.argtypes = [C.c_void_p]
         L.oracle_tree_info.argtypes = [C.c_void_p, _i64p, _dp]
         L.oracle_tree_export.argtypes = [C.c_void_p, _u64p, _i32p, _i32p, _u64p, _i32p, _i32p,
@@ -143,9 +145,11 @@ class Tree:
 
     targets=None keeps every list; an index array keeps only what those
     targets need; count_only=True keeps no list (counts are always full).
+    prune=True (with targets) walks only the pairs the targets need, so the
+    counts then cover only the kept lists (for very large trees).
     """
 
-    def __init__(self, x, ncrit, theta, targets=None, count_only=False):
+    def __init__(self, x, ncrit, theta, targets=None, count_only=False, prune=False):
         self.x = _f64(x).reshape(-1, 3)
         self.n = self.x.shape[0]
         self.ncrit, self.theta = int(ncrit), float(theta)
@@ -158,7 +162,7 @@ class Tree:
         else:
             self.targets = np.ascontiguousarray(targets, dtype=np.int64)
             nt, tp = self.targets.size, self.targets.ctypes.data_as(_i64p)
-        h = lib().oracle_tree_new(self.n, _d(self.x), self.ncrit, self.theta, nt, tp)
+        h = lib().oracle_tree_new2(self.n, _d(self.x), self.ncrit, self.theta, nt, tp, 1 if prune else 0)
         if not h:
             raise ValueError("oracle_tree_new: invalid input")
         self._h = h

@@ -425,13 +425,16 @@ static void pb_push(pbuf *b, uint64_t x)
     b->v[b->n++] = x;
 }
 
-typedef struct { otree *t; pbuf m2l, p2p; } tctx;
+typedef struct { otree *t; pbuf m2l, p2p; int prune; } tctx;
 
 /* Dual tree traversal (step T7, Section II.C).  Pairs are packed as
  * target << 32 | source.                                                    */
 static void interact(tctx *c, int a, int b)
 {
     otree *t = c->t;
+    /* pruned walk: a pair whose target is not kept has no kept descendant
+     * (the kept set is closed under ancestors) */
+    if (c->prune && !t->need[a]) return;
     if (mac(t, a, b)) {
         t->n_m2l++;
         if (t->need[a]) pb_push(&c->m2l, ((uint64_t)a << 32) | (uint32_t)b);
@@ -476,9 +479,11 @@ static void csr_from_pairs(pbuf *b, int64_t ncell, int64_t **off, int32_t **src)
 /* Build the tree and the lists.  targets (nt indices into the input order)
  * restrict which target cells keep their lists: leaves holding a target and
  * their ancestors.  targets == NULL keeps everything; nt < 0 keeps nothing
- * (count only).  Returns NULL on invalid input.                            */
-void *oracle_tree_new(int64_t n, const double *x, int32_t ncrit, double theta,
-                      int64_t nt, const int64_t *targets)
+ * (count only).  prune != 0 (with targets) walks only pairs whose target is
+ * kept; the counts then cover the kept lists only.  Returns NULL on invalid
+ * input.                                                                    */
+void *oracle_tree_new2(int64_t n, const double *x, int32_t ncrit, double theta,
+                       int64_t nt, const int64_t *targets, int prune)
 {
     if (n <= 0 || !x || ncrit < 1 || !(theta > 0.0 && theta < 1.0)) return NULL;
     otree *t = (otree *)calloc(1, sizeof(otree));
@@ -593,13 +598,19 @@ void *oracle_tree_new(int64_t n, const double *x, int32_t ncrit, double theta,
     }
 
     /* T7: lists. */
-    tctx cx = {t, {0}, {0}};
+    tctx cx = {t, {0}, {0}, (prune && targets) ? 1 : 0};
     interact(&cx, 0, 0);
     t->n_m2l_stored = cx.m2l.n;
     t->n_p2p_stored = cx.p2p.n;
     csr_from_pairs(&cx.m2l, nc, &t->m2l_off, &t->m2l_src);
     csr_from_pairs(&cx.p2p, nc, &t->p2p_off, &t->p2p_src);
     return t;
+}
+
+void *oracle_tree_new(int64_t n, const double *x, int32_t ncrit, double theta,
+                      int64_t nt, const int64_t *targets)
+{
+    return oracle_tree_new2(n, x, ncrit, theta, nt, targets, 0);
 }
 
 void oracle_tree_free(void *h)

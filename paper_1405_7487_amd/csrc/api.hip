@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_adjoint_out(const TC *psi_s, const TC *
 }
 
 // ------------------------------------------------------------ timing
-enum Phase { PH_P2M, PH_M2L, PH_L2L, PH_P2P, PH_L2P, PH_EVAL, PH_ADJ, PH_N };
+enum Phase { PH_P2M, PH_M2L, PH_L2L, PH_P2P, PH_L2P, PH_EVAL, PH_ADJ, PH_M2LX, PH_N };
 
 struct Events {
     hipEvent_t a[PH_N], b[PH_N];
@@ -241,8 +241,11 @@ void run_pipeline(fmm_plan *P, const void *q, void *ub, void *phi_s, void *E_s, 
     upward(P, ub, s);
     ev_rec(P, PH_P2M, false, s);
     ev_rec(P, PH_M2L, true, s);
-    m2l(P, s);
+    m2l_same(P, s);
     ev_rec(P, PH_M2L, false, s);
+    ev_rec(P, PH_M2LX, true, s);
+    m2l_cross(P, s);
+    ev_rec(P, PH_M2LX, false, s);
     ev_rec(P, PH_L2L, true, s);
     downward_l2l(P, s);
     ev_rec(P, PH_L2L, false, s);
@@ -575,7 +578,7 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
         auto it = g_ev.find(P);
         if (it != g_ev.end()) {
             double *dst[PH_N] = {&st.ms_p2m, &st.ms_m2l, &st.ms_l2l, &st.ms_p2p, &st.ms_l2p, &st.ms_evaluate,
-                                 &st.ms_adjoint};
+                                 &st.ms_adjoint, &st.ms_m2l_cross};
             for (int k = 0; k < PH_N; ++k) {
                 if (!it->second.used[k]) continue;
                 float ms = 0.f;

@@ -163,7 +163,8 @@ void l2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
 // m2l.hip
 int m2l_tile_width(int p, bool f64);
 void m2l_prepare(fmm_plan *P, hipStream_t s);
-void m2l(fmm_plan *P, hipStream_t s);
+void m2l_same(fmm_plan *P, hipStream_t s);
+void m2l_cross(fmm_plan *P, hipStream_t s);
 // p2p.hip
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
 // api.hip helpers

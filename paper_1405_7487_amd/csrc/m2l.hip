@@ -300,11 +300,13 @@ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
     else { m = (o + 1) / 2; im = (o & 1) ? 0 : 1; }
 }
 
-// One wave per target cell; float64 arithmetic.  For a source of level l_B
-// and a target of level l_A, with tau = (c_A - c_B)/h_A and rho = h_B/h_A:
-//     Lt_j^s += (-1)^j sum_{n,m} rho^n Mt_n^m I_{n+j}^{m+s}(tau).
-// One 64-thread block (one wave) per target cell, so every barrier below is
-// reached by the whole block.
+// Cross-level pairs, one 64-thread block (one wave) per target cell, float64
+// arithmetic in the complex form.  For a source of level l_B and a target of
+// level l_A, with tau = (c_A - c_B)/h_A and rho = h_B/h_A:
+//     Lt_j^s += (-1)^j sum_{n<p} rho^n sum_{m=-n..n} Mt_n^m I_{n+j}^{m+s}(tau),
+// M^{-m} = (-1)^m conj(M^m), I^{-l} = (-1)^l conj(I^l).  Lane t owns the
+// outputs (j, s >= 0) numbered t and t + 64 and sums over the target's pairs
+// in list order; the block's barriers are reached by the whole block.
 template <class TM>
 __global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *off, const int32_t *src,
                                                   const int32_t *lvl, const double *ctr, double S, int p, int P2pad,
@@ -316,15 +318,24 @@ __global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *
     const int64_t k0 = off[c], k1 = off[c + 1];
     if (k0 == k1) return;
     __shared__ cd H[(2 * kMaxP) * (2 * kMaxP + 1) / 2];
-    const int nI = 2 * p - 1, P2 = p * p;
+    __shared__ cd Ms[kMaxP * (kMaxP + 1) / 2];
+    const int nI = 2 * p - 1, P2 = p * p, NO = p * (p + 1) / 2;
     const double hA = ldexp(S, -lvl[c]);
-    double acc[4] = {0, 0, 0, 0};  // rows lane, lane+64, lane+128, lane+192
+    // output (j, s) of each of this lane's two slots
+    int oj[2], os[2];
+    for (int q = 0; q < 2; ++q) {
+        const int t = lane + 64 * q;
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= t) ++j;
+        oj[q] = t < NO ? j : -1;
+        os[q] = t - j * (j + 1) / 2;
+    }
+    double are[2] = {0, 0}, aim[2] = {0, 0};
     for (int64_t k = k0; k < k1; ++k) {
         const int b = src[k];
         const double tx = (ctr[3 * c] - ctr[3 * b]) / hA, ty = (ctr[3 * c + 1] - ctr[3 * b + 1]) / hA,
                      tz = (ctr[3 * c + 2] - ctr[3 * b + 2]) / hA;
-        const double rho = ldexp(1.0, lvl[c] - lvl[b]);
-        // irregular table: diagonal by lane 0, columns by lanes < nI
+        const int dl = lvl[c] - lvl[b];
         const double r2 = tx * tx + ty * ty + tz * tz, ir2 = 1.0 / r2;
         if (lane == 0) {
             cd mm = {1.0 / sqrt(r2), 0.0};
@@ -334,6 +345,18 @@ __global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *
                     mm = cd{(mm.re * tx - mm.im * ty) * f, (mm.re * ty + mm.im * tx) * f};
                 }
                 H[m * (m + 1) / 2 + m] = mm;
+            }
+        }
+        // source multipole as complex coefficients, scaled by rho^n
+        const TM *mb = M + (int64_t)b * P2pad;
+        for (int r = lane; r < P2; r += 64) {
+            const int n = (int)sqrtf((float)r + 0.5f);
+            const int o = r - n * n;
+            const double sc = ldexp(1.0, n * dl);
+            if (o == 0) Ms[n * (n + 1) / 2] = cd{sc * (double)mb[r], 0.0};
+            else if (o & 1) {
+                const int m = (o + 1) / 2;
+                Ms[n * (n + 1) / 2 + m] = cd{sc * (double)mb[r], sc * (double)mb[r + 1]};
             }
         }
         __syncthreads();
@@ -353,38 +376,40 @@ __global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *
             }
         }
         __syncthreads();
-        const TM *mb = M + (int64_t)b * P2pad;
-        for (int q = 0; q < 4; ++q) {
-            const int row = lane + 64 * q;
-            if (row >= P2) break;
-            int j, s, rim;
-            rdecode(row, j, s, rim);
-            double sum = 0.0;
-            double rn = 1.0;
-            int ncur = 0;
-            for (int colx = 0; colx < P2; ++colx) {
-                int n, m, cim;
-                rdecode(colx, n, m, cim);
-                while (ncur < n) { rn *= rho; ++ncur; }
-                cd d;
-                if (m == 0) d = hget(H, nI, n + j, s);
-                else {
-                    cd a = hget(H, nI, n + j, m + s), bq = hget(H, nI, n + j, s - m);
-                    const double sg = (m & 1) ? -1.0 : 1.0;
-                    if (!cim) d = {a.re + sg * bq.re, a.im + sg * bq.im};
-                    else d = {-(a.im - sg * bq.im), a.re - sg * bq.re};
+        for (int q = 0; q < 2; ++q) {
+            const int j = oj[q], sO = os[q];
+            if (j < 0) continue;
+            double sr = 0.0, si = 0.0;
+            for (int n = 0; n < p; ++n) {
+                const int kk = n + j;
+                const cd *Hk = H + kk * (kk + 1) / 2;
+                const cd *Mn = Ms + n * (n + 1) / 2;
+                for (int m = -n; m <= n; ++m) {
+                    cd mv = Mn[m < 0 ? -m : m];
+                    if (m < 0) mv = (m & 1) ? cd{-mv.re, mv.im} : cd{mv.re, -mv.im};
+                    const int l = m + sO;  // |l| <= kk always
+                    cd iv = Hk[l < 0 ? -l : l];
+                    if (l < 0) iv = (l & 1) ? cd{-iv.re, iv.im} : cd{iv.re, -iv.im};
+                    sr += mv.re * iv.re - mv.im * iv.im;
+                    si += mv.re * iv.im + mv.im * iv.re;
                 }
-                const double v = rim ? d.im : d.re;
-                sum += v * rn * (double)mb[colx];
             }
-            acc[q] += (j & 1) ? -sum : sum;
+            are[q] += sr;
+            aim[q] += si;
         }
         __syncthreads();
     }
     TM *dl = L + c * P2pad;
-    for (int q = 0; q < 4; ++q) {
-        const int row = lane + 64 * q;
-        if (row < P2) dl[row] = (TM)((double)dl[row] + acc[q]);
+    for (int q = 0; q < 2; ++q) {
+        const int j = oj[q], sO = os[q];
+        if (j < 0) continue;
+        const double sg = (j & 1) ? -1.0 : 1.0;
+        if (sO == 0) dl[j * j] = (TM)((double)dl[j * j] + sg * are[q]);
+        else {
+            const int r = j * j + 2 * sO - 1;
+            dl[r] = (TM)((double)dl[r] + sg * are[q]);
+            dl[r + 1] = (TM)((double)dl[r + 1] + sg * aim[q]);
+        }
     }
 }
 
@@ -476,7 +501,7 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     }
 }
 
-void m2l(fmm_plan *P, hipStream_t s)
+void m2l_same(fmm_plan *P, hipStream_t s)
 {
     const bool f64 = P->precision == FMM_PREC_FP64;
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
@@ -488,6 +513,11 @@ void m2l(fmm_plan *P, hipStream_t s)
     } else {
         FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * P->P2pad * P->ncell, s));
     }
+}
+
+void m2l_cross(fmm_plan *P, hipStream_t s)
+{
+    const bool f64 = P->precision == FMM_PREC_FP64;
     if (P->n_m2l_cross > 0) {
         const unsigned nb = (unsigned)P->ncell;
         if (f64)

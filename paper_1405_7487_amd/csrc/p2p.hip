@@ -74,7 +74,7 @@ __device__ __forceinline__ V4 far_dummy()
     return v;
 }
 
-template <class T, class V4, bool KAHAN, int G>
+template <class T, class V4, bool KAHAN, bool GATHER, int G>
 __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const int32_t *beg, const int32_t *end,
                            int64_t k0, int64_t k1, const int32_t *src, const double *ctr, const V4 *ub, T *phi_s,
                            T *E_s)
@@ -107,34 +107,122 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
         fold(pa);
         __syncthreads();
     }
-    // 2) every other leaf of the list, batched, no test needed
-    int64_t k = k0;
-    int32_t o = 0;
-    while (k < k1) {
-        int staged = 0;
-        while (staged < kStage && k < k1) {
-            const int b = src[k];
-            if (b == A) { ++k; o = 0; continue; }
-            const int32_t bb = beg[b] + o, be = end[b];
-            const int take = min(min(be - bb, kStage - staged), 64);
-            if (lane < take) {
-                V4 v = ub[bb + lane];
-                v.x += (T)(ctr[3 * b] - cax);
-                v.y += (T)(ctr[3 * b + 1] - cay);
-                v.z += (T)(ctr[3 * b + 2] - caz);
-                sb[staged + lane] = v;
+    if constexpr (!GATHER) {
+        // 2) every other leaf of the list, staged leaf by leaf (lanes load the
+        //    bodies of one source leaf per step; good for well-filled leaves)
+        int64_t k = k0;
+        int32_t o = 0;
+        while (k < k1) {
+            int staged = 0;
+            while (staged < kStage && k < k1) {
+                const int b = src[k];
+                if (b == A) { ++k; o = 0; continue; }
+                const int32_t bb = beg[b] + o, be = end[b];
+                const int take = min(min(be - bb, kStage - staged), 64);
+                if (lane < take) {
+                    V4 v = ub[bb + lane];
+                    v.x += (T)(ctr[3 * b] - cax);
+                    v.y += (T)(ctr[3 * b + 1] - cay);
+                    v.z += (T)(ctr[3 * b + 2] - caz);
+                    sb[staged + lane] = v;
+                }
+                staged += take;
+                o += take;
+                if (bb + take == be) { ++k; o = 0; }
             }
-            staged += take;
-            o += take;
-            if (bb + take == be) { ++k; o = 0; }
+            if (staged == 0) break;
+            const int npad = (staged + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
+            for (int l = staged + lane; l < npad; l += 64) sb[l] = far_dummy<T, V4>();
+            __syncthreads();
+            Acc<T> pa{0, 0, 0, 0};
+            batch<T, V4, G, false>(sb, npad, sub, u.x, u.y, u.z, pa);
+            fold(pa);
+            __syncthreads();
         }
-        if (staged == 0) break;
-        const int npad = (staged + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
-        for (int l = staged + lane; l < npad; l += 64) sb[l] = far_dummy<T, V4>();
-        __syncthreads();
-        Acc<T> pa{0, 0, 0, 0};
-        batch<T, V4, G, false>(sb, npad, sub, u.x, u.y, u.z, pa);
-        fold(pa);
+    } else {
+        // 2) every other leaf of the list, batched, no test needed.  A batch is
+        //    gathered from the next (up to) 64 list entries at once: lane l takes
+        //    entry k + l, a wave prefix sum of the leaf sizes places the bodies,
+        //    and every LDS slot finds its leaf by a branchless binary search of
+        //    that sum.  The loads of batch i+1 are in flight while batch i is
+        //    multiplied (two LDS buffers); slots past the batch hold zero-charge
+        //    dummies, which also pad the batch for the unrolled loop.
+        __shared__ int32_t s_excl[64], s_incl[64], s_base[64];
+        __shared__ T s_sh[64][3];
+        int64_t k = k0;
+        int32_t o = 0;  // bodies of entry k already consumed
+        V4 regs[kStage / 64];
+        int st_next = 0;
+        auto gather = [&]() {
+            const int64_t kk = k + lane;
+            const int b = kk < k1 ? src[kk] : A;
+            const int32_t skip = lane == 0 ? o : 0;
+            const int32_t sz = (kk < k1 && b != A) ? end[b] - beg[b] - skip : 0;
+            int32_t pre = sz;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int32_t v = __shfl_up(pre, d, 64);
+                if (lane >= d) pre += v;
+            }
+            const int staged = min(__shfl(pre, 63, 64), kStage);
+            s_incl[lane] = pre;
+            s_excl[lane] = pre - sz;
+            s_base[lane] = beg[b] + skip;
+            s_sh[lane][0] = (T)(ctr[3 * b] - cax);
+            s_sh[lane][1] = (T)(ctr[3 * b + 1] - cay);
+            s_sh[lane][2] = (T)(ctr[3 * b + 2] - caz);
+            __syncthreads();
+            int lo[kStage / 64];
+#pragma unroll
+            for (int r = 0; r < kStage / 64; ++r) lo[r] = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+#pragma unroll
+                for (int r = 0; r < kStage / 64; ++r)
+                    if (s_incl[lo[r] + step - 1] <= lane + 64 * r) lo[r] += step;
+#pragma unroll
+            for (int r = 0; r < kStage / 64; ++r) {
+                const int t = lane + 64 * r;
+                if (t < staged) {
+                    V4 v = ub[s_base[lo[r]] + (t - s_excl[lo[r]])];
+                    v.x += s_sh[lo[r]][0];
+                    v.y += s_sh[lo[r]][1];
+                    v.z += s_sh[lo[r]][2];
+                    regs[r] = v;
+                } else {
+                    regs[r] = far_dummy<T, V4>();
+                }
+            }
+            // advance the cursor past the consumed entries
+            const int nf = __popcll(__ballot(pre <= staged));
+            if (nf == 64) {
+                k += 64;
+                o = 0;
+            } else {
+                const int32_t consumed = staged - __shfl(pre - sz, nf, 64);
+                o = (nf == 0 ? o : 0) + consumed;
+                k += nf;
+            }
+            st_next = staged;
+        };
+        if (k < k1) gather();
+        int buf = 0;
+        while (st_next > 0 || k < k1) {
+            V4 *cur = sb + buf * kStage;
+#pragma unroll
+            for (int r = 0; r < kStage / 64; ++r) cur[lane + 64 * r] = regs[r];
+            const int st_cur = st_next;
+            __syncthreads();
+            if (k < k1) gather();
+            else st_next = 0;
+            if (st_cur > 0) {
+                const int npad = (st_cur + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
+                Acc<T> pa{0, 0, 0, 0};
+                batch<T, V4, G, false>(cur, npad, sub, u.x, u.y, u.z, pa);
+                fold(pa);
+            }
+            buf ^= 1;
+        }
         __syncthreads();
     }
     if (KAHAN) {
@@ -156,12 +244,12 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
     }
 }
 
-template <class T, class V4, bool KAHAN>
+template <class T, class V4, bool KAHAN, bool GATHER>
 __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t *beg, const int32_t *end,
                                             const int64_t *off, const int32_t *src, const double *ctr, const V4 *ub,
                                             T *phi_s, T *E_s)
 {
-    __shared__ V4 sb[kStage + 64 * kUnroll];
+    __shared__ V4 sb[2 * kStage];
     const int A = leaves[blockIdx.x];
     const int32_t tb = beg[A], te = end[A];
     const int nt = te - tb;
@@ -169,33 +257,42 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     for (int base = 0; base < nt; base += 64) {
         const int cnt = min(64, nt - base);
         // lanes per target: the largest power of two (<= 16) with G * cnt <= 64
-        if (cnt <= 4) leaf_chunk<T, V4, KAHAN, 16>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else if (cnt <= 8) leaf_chunk<T, V4, KAHAN, 8>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else if (cnt <= 16) leaf_chunk<T, V4, KAHAN, 4>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else if (cnt <= 32) leaf_chunk<T, V4, KAHAN, 2>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else leaf_chunk<T, V4, KAHAN, 1>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        if (cnt <= 4) leaf_chunk<T, V4, KAHAN, GATHER, 16>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else if (cnt <= 8) leaf_chunk<T, V4, KAHAN, GATHER, 8>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else if (cnt <= 16) leaf_chunk<T, V4, KAHAN, GATHER, 4>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else if (cnt <= 32) leaf_chunk<T, V4, KAHAN, GATHER, 2>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        else leaf_chunk<T, V4, KAHAN, GATHER, 1>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
     }
+}
+
+template <bool GATHER>
+void launch_p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
+{
+    const unsigned nb = (unsigned)P->nleaf;
+    if (P->precision == FMM_PREC_FP64)
+        k_p2p<double, double4, false, GATHER><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off,
+                                                                P->p2p_src, P->c_ctr, static_cast<const double4 *>(ub),
+                                                                static_cast<double *>(phi_s), static_cast<double *>(E_s));
+    else if (P->kahan)
+        k_p2p<float, float4, true, GATHER><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
+                                                             P->c_ctr, static_cast<const float4 *>(ub),
+                                                             static_cast<float *>(phi_s), static_cast<float *>(E_s));
+    else
+        k_p2p<float, float4, false, GATHER><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
+                                                              P->c_ctr, static_cast<const float4 *>(ub),
+                                                              static_cast<float *>(phi_s), static_cast<float *>(E_s));
+    FMM_HIP(hipGetLastError());
 }
 
 }  // namespace
 
+// Staging by leaf when leaves are well filled (mean >= 16 bodies), otherwise
+// the cooperative gather that packs many small leaves per batch.
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
     if (P->nleaf == 0) return;
-    const unsigned nb = (unsigned)P->nleaf;
-    if (P->precision == FMM_PREC_FP64)
-        k_p2p<double, double4, false><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
-                                                        P->c_ctr, static_cast<const double4 *>(ub),
-                                                        static_cast<double *>(phi_s), static_cast<double *>(E_s));
-    else if (P->kahan)
-        k_p2p<float, float4, true><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
-                                                     P->c_ctr, static_cast<const float4 *>(ub),
-                                                     static_cast<float *>(phi_s), static_cast<float *>(E_s));
-    else
-        k_p2p<float, float4, false><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
-                                                      P->c_ctr, static_cast<const float4 *>(ub),
-                                                      static_cast<float *>(phi_s), static_cast<float *>(E_s));
-    FMM_HIP(hipGetLastError());
+    if (P->n >= 16 * P->nleaf) launch_p2p<false>(P, ub, phi_s, E_s, s);
+    else launch_p2p<true>(P, ub, phi_s, E_s, s);
 }
 
 }  // namespace fmm
