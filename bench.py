@@ -27,6 +27,27 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = {"k_m2l_batched": "m2l.hip", "k_p2p": "p2p.hip"}
+
+
+def recorded_traffic(kernel, config, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", f"hbm_traffic_{config}.md")
+    src = os.path.join(HERE, "paper_1405_7487_amd", "csrc", KERNEL_SOURCE[kernel])
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        cols = [c.strip() for c in line.strip().strip("|").split("|")]
+        # | kernel | precision | source sha256 | FETCH KiB | WRITE KiB | bytes per launch |
+        if len(cols) == 6 and cols[0] == kernel and cols[1] == precision and cols[2] == sha:
+            return float(cols[5])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,13 +116,21 @@ def main():
         fwd.append(e[0].elapsed_time(e[2]))
         adj.append(e[2].elapsed_time(e[3]))
     ms_step = (t1 - t0) * 1e3 / args.steps
-    t_fwd = float(np.mean(fwd))
-    t_adj = float(np.mean(adj))
+    t_fwd = float(np.median(fwd))
+    t_adj = float(np.median(adj))
     log(f"bench: {args.steps} timed steps: forward {t_fwd:.3f} ms, adjoint {t_adj:.3f} ms, step {ms_step:.3f} ms")
 
-    # keep one plan's outputs for the accuracy check
+    # evaluation alone on a reused plan; keep its outputs for the accuracy check
     plan = F.Plan(x, prm)
-    phi, E = plan.evaluate(q)
+    ev_ms = []
+    for k in range(max(3, min(args.steps, 10))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        phi, E = plan.evaluate(q)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ev_ms.append(e0.elapsed_time(e1))
+    t_eval = float(np.median(ev_ms))
     stats = plan.stats()
     phi_h = phi.cpu().numpy()
     E_h = E.cpu().numpy()
@@ -116,14 +145,16 @@ def main():
     if m2l_ms >= p2p_ms:
         achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
         peak = PEAK["mfma_f32"] if args.precision == "mixed" else PEAK["mfma_f64"]
-        roof = {"kernel": "k_m2l_tiles (batched same-level M2L)", "bound": "mfma", "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+        roof = {"kernel": "k_m2l_batched (same-level M2L)", "bound": "mfma", "achieved": achieved,
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": recorded_traffic("k_m2l_batched", args.config, args.precision),
                 "launch_ms": m2l_ms, "flops_per_launch": m2l_flops}
     else:
         achieved = p2p_flops / (p2p_ms * 1e-3) / 1e12
         peak = PEAK["valu_f32"] if args.precision == "mixed" else PEAK["valu_f64"]
         roof = {"kernel": "k_p2p", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "launch_ms": p2p_ms, "flops_per_launch": p2p_flops}
+                "frac": achieved / peak, "traffic": recorded_traffic("k_p2p", args.config, args.precision),
+                "launch_ms": p2p_ms, "flops_per_launch": p2p_flops}
     other = {"m2l_ms": m2l_ms, "m2l_tflops": m2l_flops / (m2l_ms * 1e-3) / 1e12 if m2l_ms else None,
              "p2p_ms": p2p_ms, "p2p_tflops": p2p_flops / (p2p_ms * 1e-3) / 1e12 if p2p_ms else None,
              "m2l_cross_ms": float(np.mean([s["ms_m2l_cross"] for s in kern])),
@@ -196,6 +227,8 @@ def main():
                                f"ncrit={cfg['ncrit']}, forward+adjoint", "n": n, "p": cfg["p"],
                    "theta": cfg["theta"], "ncrit": cfg["ncrit"], "precision": args.precision},
         "forward_ms": t_fwd,
+        "forward_ms_mean": float(np.mean(fwd)),
+        "evaluate_only_ms": t_eval,
         "adjoint_ms": t_adj,
         "adjoint_over_forward": t_adj / t_fwd,
         "fp64_forward_ms": fp64_ms,

@@ -178,6 +178,16 @@ FMM_API fmm_status fmm_plan_stats(const fmm_plan *plan, fmm_stats *out);
  * plan's stream). */
 FMM_API fmm_status fmm_export_tree(const fmm_plan *plan, const fmm_tree_export *out);
 
+/* Order-independent digests of the plan's two lists (dual tree traversal,
+ * Section II.C): out_host[0] for the M2L pairs (same- and cross-level),
+ * out_host[1] for the P2P pairs, each the sum mod 2^64 over the pairs
+ * (A <- B) of mix64(A << 32 | B), with A and B cell indices in (level, key)
+ * order and mix64 the output finaliser of SplitMix64 (Steele, Lea & Flood
+ * 2014).  Equal digests mean equal lists without copying them to the host.
+ * out_host is a HOST array of 2 uint64.  Synchronises the plan's stream.
+ * Errors: FMM_ERR_INVALID (NULL argument), FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_list_digest(const fmm_plan *plan, uint64_t *out_host);
+
 /* Per-phase event timing on (1) or off (0, default).  Timing adds one event
  * pair per phase to the stream. */
 FMM_API fmm_status fmm_set_timing(fmm_plan *plan, int32_t on);

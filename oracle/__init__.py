@@ -44,6 +44,7 @@ def lib():
         L.oracle_tree_new2.restype = C.c_void_p
         L.oracle_tree_free.argtypes = [C.c_void_p]
         L.oracle_tree_info.argtypes = [C.c_void_p, _i64p, _dp]
+        L.oracle_tree_digest.argtypes = [C.c_void_p, _u64p]
         L.oracle_tree_export.argtypes = [C.c_void_p, _u64p, _i32p, _i32p, _u64p, _i32p, _i32p,
                                          _i32p, _i32p, _i32p, _dp, _i32p, _i32p]
         L.oracle_fmm_at.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp]
@@ -171,6 +172,9 @@ class Tree:
         lib().oracle_tree_info(h, info.ctypes.data_as(_i64p), _d(box))
         (self.ncell, self.nleaf, self.depth, self.n_m2l, self.n_p2p,
          self.n_m2l_stored, self.n_p2p_stored) = (int(v) for v in info)
+        dg = np.zeros(2, dtype=np.uint64)
+        lib().oracle_tree_digest(h, dg.ctypes.data_as(_u64p))
+        self.digest_m2l, self.digest_p2p = int(dg[0]), int(dg[1])
         self.lo = box[:3].copy()
         self.S = float(box[3])
         self.scale = float(box[4])

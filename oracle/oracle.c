@@ -353,6 +353,7 @@ typedef struct {
     /* lists (CSR by target cell; source ascending).  With a target subset only
      * the target cells that matter are stored; the counts are always full.  */
     int64_t n_m2l, n_p2p, n_m2l_stored, n_p2p_stored;
+    uint64_t h_m2l, h_p2p; /* list digests (mix64 sums) */
     int64_t *m2l_off, *p2p_off;
     int32_t *m2l_src, *p2p_src;
     uint8_t *need;    /* target cell is an ancestor of (or is) a sampled leaf */
@@ -425,33 +426,70 @@ static void pb_push(pbuf *b, uint64_t x)
     b->v[b->n++] = x;
 }
 
-typedef struct { otree *t; pbuf m2l, p2p; int prune; } tctx;
+/* Order-independent list digest: the sum, mod 2^64, of mix64(target << 32 |
+ * source) over the pairs, with mix64 the output finaliser of SplitMix64
+ * (Steele, Lea & Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014).  Two lists have equal digests when they hold the same pairs
+ * (up to a 2^-64 accident), whatever order they were produced in.          */
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
 
-/* Dual tree traversal (step T7, Section II.C).  Pairs are packed as
- * target << 32 | source.                                                    */
+typedef struct {
+    otree *t;
+    pbuf m2l, p2p;
+    int prune;
+    int64_t n_m2l, n_p2p;
+    uint64_t h_m2l, h_p2p;
+} tctx;
+
+/* One step of the dual tree traversal (step T7, Section II.C): 0 = the pair
+ * is an M2L pair, 1 = a P2P pair, 2 = split A and/or B (symmetric rule: the
+ * coarser cell, both on equal levels, never a leaf).                       */
+static int classify(const otree *t, int a, int b, int *split_a, int *split_b)
+{
+    if (mac(t, a, b)) return 0;
+    int la = is_leaf(t, a), lb = is_leaf(t, b);
+    if (la && lb) return 1;
+    if (la) { *split_a = 0; *split_b = 1; }
+    else if (lb) { *split_a = 1; *split_b = 0; }
+    else if (t->lvl[a] < t->lvl[b]) { *split_a = 1; *split_b = 0; }
+    else if (t->lvl[b] < t->lvl[a]) { *split_a = 0; *split_b = 1; }
+    else { *split_a = 1; *split_b = 1; }
+    return 2;
+}
+
+/* Records a terminal pair (packed target << 32 | source); returns 1 when the
+ * pair was split instead, with the split flags set. */
+static int visit(tctx *c, int a, int b, int *split_a, int *split_b)
+{
+    otree *t = c->t;
+    int kind = classify(t, a, b, split_a, split_b);
+    if (kind == 2) return 1;
+    const uint64_t pr = ((uint64_t)a << 32) | (uint32_t)b;
+    if (kind == 0) {
+        c->n_m2l++;
+        c->h_m2l += mix64(pr);
+        if (t->need[a]) pb_push(&c->m2l, pr);
+    } else {
+        c->n_p2p++;
+        c->h_p2p += mix64(pr);
+        if (t->need[a]) pb_push(&c->p2p, pr);
+    }
+    return 0;
+}
+
 static void interact(tctx *c, int a, int b)
 {
     otree *t = c->t;
     /* pruned walk: a pair whose target is not kept has no kept descendant
      * (the kept set is closed under ancestors) */
     if (c->prune && !t->need[a]) return;
-    if (mac(t, a, b)) {
-        t->n_m2l++;
-        if (t->need[a]) pb_push(&c->m2l, ((uint64_t)a << 32) | (uint32_t)b);
-        return;
-    }
-    int la = is_leaf(t, a), lb = is_leaf(t, b);
-    if (la && lb) {
-        t->n_p2p++;
-        if (t->need[a]) pb_push(&c->p2p, ((uint64_t)a << 32) | (uint32_t)b);
-        return;
-    }
-    int split_a, split_b;
-    if (la) { split_a = 0; split_b = 1; }
-    else if (lb) { split_a = 1; split_b = 0; }
-    else if (t->lvl[a] < t->lvl[b]) { split_a = 1; split_b = 0; }
-    else if (t->lvl[b] < t->lvl[a]) { split_a = 0; split_b = 1; }
-    else { split_a = 1; split_b = 1; }
+    int split_a = 0, split_b = 0;
+    if (!visit(c, a, b, &split_a, &split_b)) return;
     if (split_a && split_b) {
         for (int i = 0; i < t->nch[a]; ++i)
             for (int j = 0; j < t->nch[b]; ++j) interact(c, t->cbeg[a] + i, t->cbeg[b] + j);
@@ -460,6 +498,60 @@ static void interact(tctx *c, int a, int b)
     } else {
         for (int j = 0; j < t->nch[b]; ++j) interact(c, a, t->cbeg[b] + j);
     }
+}
+
+static void pb_append(pbuf *dst, const pbuf *src)
+{
+    for (int64_t k = 0; k < src->n; ++k) pb_push(dst, src->v[k]);
+}
+
+/* The whole walk from (root, root).  The first generations are expanded
+ * breadth-first until the frontier holds enough pairs; the frontier's pairs
+ * are then walked depth-first by independent threads.  Each pair is visited
+ * exactly once either way, so the lists (sorted afterwards), counts and
+ * digests do not depend on the thread count.                                */
+static void traverse_all(tctx *cx)
+{
+    otree *t = cx->t;
+    pbuf front = {0}, next = {0};
+    pb_push(&front, 0);
+    for (int gen = 0; gen < 6 && front.n > 0 && front.n < 4096; ++gen) {
+        next.n = 0;
+        for (int64_t k = 0; k < front.n; ++k) {
+            int a = (int)(front.v[k] >> 32), b = (int)(front.v[k] & 0xffffffffu);
+            if (cx->prune && !t->need[a]) continue;
+            int split_a = 0, split_b = 0;
+            if (!visit(cx, a, b, &split_a, &split_b)) continue;
+            int na = split_a ? t->nch[a] : 1, nb = split_b ? t->nch[b] : 1;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    uint64_t ca = split_a ? (uint64_t)(t->cbeg[a] + i) : (uint64_t)a;
+                    uint64_t cb = split_b ? (uint64_t)(t->cbeg[b] + j) : (uint64_t)b;
+                    pb_push(&next, (ca << 32) | cb);
+                }
+        }
+        pbuf tmp = front; front = next; next = tmp;
+    }
+#pragma omp parallel
+    {
+        tctx lc = {t, {0}, {0}, cx->prune, 0, 0, 0, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < front.n; ++k)
+            interact(&lc, (int)(front.v[k] >> 32), (int)(front.v[k] & 0xffffffffu));
+#pragma omp critical
+        {
+            cx->n_m2l += lc.n_m2l;
+            cx->n_p2p += lc.n_p2p;
+            cx->h_m2l += lc.h_m2l;
+            cx->h_p2p += lc.h_p2p;
+            pb_append(&cx->m2l, &lc.m2l);
+            pb_append(&cx->p2p, &lc.p2p);
+        }
+        free(lc.m2l.v);
+        free(lc.p2p.v);
+    }
+    free(front.v);
+    free(next.v);
 }
 
 static void csr_from_pairs(pbuf *b, int64_t ncell, int64_t **off, int32_t **src)
@@ -598,8 +690,12 @@ void *oracle_tree_new2(int64_t n, const double *x, int32_t ncrit, double theta,
     }
 
     /* T7: lists. */
-    tctx cx = {t, {0}, {0}, (prune && targets) ? 1 : 0};
-    interact(&cx, 0, 0);
+    tctx cx = {t, {0}, {0}, (prune && targets) ? 1 : 0, 0, 0, 0, 0};
+    traverse_all(&cx);
+    t->n_m2l = cx.n_m2l;
+    t->n_p2p = cx.n_p2p;
+    t->h_m2l = cx.h_m2l;
+    t->h_p2p = cx.h_p2p;
     t->n_m2l_stored = cx.m2l.n;
     t->n_p2p_stored = cx.p2p.n;
     csr_from_pairs(&cx.m2l, nc, &t->m2l_off, &t->m2l_src);
@@ -622,6 +718,15 @@ void oracle_tree_free(void *h)
     free(t->ix); free(t->ctr); free(t->need);
     free(t->m2l_off); free(t->m2l_src); free(t->p2p_off); free(t->p2p_src);
     free(t);
+}
+
+/* out: [digest of the M2L list, digest of the P2P list] over every pair the
+ * walk visited (the full lists unless the walk was pruned).               */
+void oracle_tree_digest(const void *h, uint64_t *out)
+{
+    const otree *t = (const otree *)h;
+    out[0] = t->h_m2l;
+    out[1] = t->h_p2p;
 }
 
 /* info: [ncell, nleaf, depth, n_m2l, n_p2p, n_m2l_stored, n_p2p_stored]

@@ -24,7 +24,7 @@ PREC = {"fp64": 0, "mixed": 1}
 EXPORTS = (
     "fmm_params_default", "fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_adjoint",
     "fmm_plan_stats", "fmm_export_tree", "fmm_set_timing", "fmm_destroy", "fmm_last_error",
-    "fmm_debug_mfma_layout",
+    "fmm_debug_mfma_layout", "fmm_list_digest",
 )
 
 
@@ -90,8 +90,9 @@ def load():
     L.fmm_destroy.restype = None
     L.fmm_last_error.restype = C.c_char_p
     L.fmm_debug_mfma_layout.argtypes = [C.c_int32, vp]
+    L.fmm_list_digest.argtypes = [vp, C.POINTER(C.c_uint64)]
     for name in ("fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_adjoint", "fmm_plan_stats",
-                 "fmm_export_tree", "fmm_set_timing", "fmm_debug_mfma_layout"):
+                 "fmm_export_tree", "fmm_set_timing", "fmm_debug_mfma_layout", "fmm_list_digest"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L
@@ -230,6 +231,13 @@ class Plan:
         st = _Stats()
         _check(load().fmm_plan_stats(self._h, C.byref(st)))
         return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+    def list_digest(self) -> tuple:
+        """(M2L digest, P2P digest) of the plan's lists (fmm_list_digest)."""
+        out = (C.c_uint64 * 2)()
+        with torch.cuda.device(self.device):
+            _check(load().fmm_list_digest(self._h, out))
+        return int(out[0]), int(out[1])
 
     def export_tree(self, lists: bool = True) -> dict:
         """Host copies of keys, permutation, cells and (optionally) lists."""

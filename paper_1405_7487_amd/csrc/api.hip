@@ -592,6 +592,22 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
     return FMM_OK;
 }
 
+fmm_status fmm_list_digest(const fmm_plan *Pc, uint64_t *out)
+{
+    g_err.clear();
+    try {
+        FMM_CHECK(Pc && out, FMM_ERR_INVALID, "NULL argument");
+        fmm_plan *P = const_cast<fmm_plan *>(Pc);
+        uint64_t h[2] = {0, 0};
+        list_digest(P, h, P->al.stream);
+        out[0] = h[0];
+        out[1] = h[1];
+    } catch (const Error &e) {
+        return fail(e);
+    }
+    return FMM_OK;
+}
+
 fmm_status fmm_export_tree(const fmm_plan *Pc, const fmm_tree_export *o)
 {
     g_err.clear();

@@ -125,7 +125,6 @@ struct fmm_plan {
     std::vector<int32_t> h_st_t;     // [8*K*3] offsets (host copy)
     std::vector<int32_t> h_ops_t;    // [nops*3]
     void *ops = nullptr;             // M2L operators, fragment layout, compute type
-    double *ops64 = nullptr;         // (mixed) float64 operators, for coarse targets? unused
     void *m2m_c = nullptr, *l2l_c = nullptr;   // [8][P2pad][P2pad] compute type
     double *m2m_d = nullptr, *l2l_d = nullptr; // float64 versions
 
@@ -155,6 +154,7 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s);
 // traverse.hip
 void traverse(fmm_plan *P, hipStream_t s);
 int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s);
+void list_digest(fmm_plan *P, uint64_t out[2], hipStream_t s);
 // expansions.hip
 void make_operators(fmm_plan *P, hipStream_t s);
 void upward(fmm_plan *P, const void *ub, hipStream_t s);

@@ -225,6 +225,41 @@ __global__ __launch_bounds__(256) void k_body_pairs(const int64_t *off, const in
     out[c] = s * (int64_t)(end[c] - beg[c]);
 }
 
+// List digests: the sum, mod 2^64, of mix64(target << 32 | source) over the
+// pairs, mix64 being the output finaliser of SplitMix64 (Steele, Lea & Flood
+// 2014).  Integer addition commutes, so the result is the same for any order
+// of the pairs or of the atomic adds.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_digest_slots(const int32_t *slots, const int32_t *tile_tgt, int64_t nslot,
+                                                      int K, int TW, unsigned long long *out)
+{
+    uint64_t h = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t sv = slots[i];
+        if (sv < 0) continue;
+        const int64_t tile = i / ((int64_t)K * TW);
+        const int32_t tg = tile_tgt[tile * TW + (int)(i % TW)];
+        if (tg >= 0) h += mix64(((uint64_t)(uint32_t)tg << 32) | (uint32_t)sv);
+    }
+    atomicAdd(out, (unsigned long long)h);
+}
+
+__global__ __launch_bounds__(256) void k_digest_csr(const int64_t *off, const int32_t *src, int64_t nc,
+                                                    unsigned long long *out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    uint64_t h = 0;
+    for (int64_t k = off[c]; k < off[c + 1]; ++k) h += mix64(((uint64_t)(uint32_t)c << 32) | (uint32_t)src[k]);
+    atomicAdd(out, (unsigned long long)h);
+}
+
 // Same-level acceptance as the traversal evaluates it (equal sides: s = 2,
 // D = 2 |t| in half-units).
 bool mac_same_level(int64_t t2, double t4) { return 48.0 < t4 * (double)(4 * t2); }
@@ -364,6 +399,35 @@ int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s)
     P->al.free(per);
     P->p2p_body_pairs = h;
     return h;
+}
+
+// Digests of the M2L list (same-level slots and cross-level CSR) and of the
+// P2P list; synchronises the stream.
+void list_digest(fmm_plan *P, uint64_t out[2], hipStream_t s)
+{
+    out[0] = out[1] = 0;
+    if (P->ncell == 0) return;
+    unsigned long long *d = static_cast<unsigned long long *>(P->al.alloc(2 * sizeof(unsigned long long)));
+    FMM_HIP(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), s));
+    const int64_t nslot = P->ntile * (int64_t)P->K * P->TW;
+    if (nslot > 0) {
+        k_digest_slots<<<2048, 256, 0, s>>>(P->slots, P->tile_tgt, nslot, P->K, P->TW, d);
+        FMM_HIP(hipGetLastError());
+    }
+    if (P->m2lx_off) {
+        k_digest_csr<<<grid1(P->ncell, 256), 256, 0, s>>>(P->m2lx_off, P->m2lx_src, P->ncell, d);
+        FMM_HIP(hipGetLastError());
+    }
+    if (P->p2p_off) {
+        k_digest_csr<<<grid1(P->ncell, 256), 256, 0, s>>>(P->p2p_off, P->p2p_src, P->ncell, d + 1);
+        FMM_HIP(hipGetLastError());
+    }
+    unsigned long long h[2] = {0, 0};
+    FMM_HIP(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    P->al.free(d);
+    out[0] = h[0];
+    out[1] = h[1];
 }
 
 void traverse(fmm_plan *P, hipStream_t s)

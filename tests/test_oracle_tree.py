@@ -259,3 +259,26 @@ def test_list_invariants(case):
         if lv[a] != lv[b]:
             coarse = a if lv[a] < lv[b] else b
             assert e["nchild"][coarse] == 0
+
+
+def _mix64(z):
+    # SplitMix64 output finaliser, written out in Python integers
+    m = (1 << 64) - 1
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_list_digest_is_the_sum_over_exported_pairs():
+    # the digests are a pure function of the pair sets, whatever thread
+    # count or frontier the walk used
+    x, _, _ = W.plummer(6000, seed=5)
+    T = oracle.Tree(x, 16, 0.4)
+    o = T.export()
+    m = (1 << 64) - 1
+    dm = sum(_mix64((int(a) << 32) | int(b)) for a, b in o["m2l"]) & m
+    dp = sum(_mix64((int(a) << 32) | int(b)) for a, b in o["p2p"]) & m
+    assert (T.digest_m2l, T.digest_p2p) == (dm, dp)
+    # SplitMix64's first output from seed 0 is mix64(0x9E3779B97F4A7C15)
+    assert _mix64(0x9E3779B97F4A7C15) == 0xE220A8397B1DCDAF
+    assert oracle.Tree(x, 16, 0.4, count_only=True).digest_m2l == dm
