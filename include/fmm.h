@@ -116,6 +116,8 @@ typedef struct {
     /* milliseconds of the last evaluation, per phase (HIP events on the stream) */
     double ms_p2m, ms_m2m, ms_m2l, ms_l2l, ms_l2p, ms_p2p, ms_evaluate, ms_adjoint;
     double ms_m2l_cross;     /* cross-level M2L (ms_m2l: same-level, batched) */
+    int64_t m2l_cross_keys;     /* cross-level (level difference, offset) keys with an operator */
+    int64_t m2l_cross_batched;  /* cross-level pairs run as shared-operator products */
 } fmm_stats;
 
 /* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are

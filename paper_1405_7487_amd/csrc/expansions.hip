@@ -107,15 +107,21 @@ __host__ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
 // Written in the fragment layout of the batched kernel (Q = P2pad/4,
 // RT = P2pad/16, row = 16 r + i):
 //     Tf[(op*4 + g)*Q + s][i*RT + r] = T[16 r + i][g*Q + s].
+// Each operator is given as tr = (tau_x, tau_y, tau_z, e): the center offset
+// c_A - c_B in units of the target's cell size h_A, and the source-to-target
+// size ratio rho = h_B / h_A = 2^e (0 for same-level pairs), which scales
+// input degree n by rho^n.
 template <class T>
-__global__ __launch_bounds__(256) void k_make_m2l_ops(const int32_t *ot, int nops, int p, int P2pad, T *Tf,
+__global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nops, int p, int P2pad, T *Tf,
                                                       double *Tdense)
 {
     const int op = blockIdx.x;
     if (op >= nops) return;
     __shared__ cd H[(2 * kMaxP) * (2 * kMaxP + 1) / 2];
     const int nI = 2 * p - 1;
-    if (threadIdx.x == 0) irregular_table((double)ot[3 * op], (double)ot[3 * op + 1], (double)ot[3 * op + 2], nI, H);
+    const double4 t = tr[op];
+    const int e2 = (int)t.w;
+    if (threadIdx.x == 0) irregular_table(t.x, t.y, t.z, nI, H);
     __syncthreads();
     const int P2 = p * p, Q = P2pad / 4;
     for (int e = threadIdx.x; e < P2pad * P2pad; e += blockDim.x) {
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const int32_t *ot, int nop
                 else d = {-(a.im - sg * b.im), a.re - sg * b.re};  // i (a - sg b)
             }
             if (j & 1) d = {-d.re, -d.im};
-            v = rim ? d.im : d.re;
+            v = ldexp(rim ? d.im : d.re, e2 * n);
         }
         const int g = col / Q, sq = col % Q, RT = P2pad / 16;
         Tf[((size_t)(op * 4 + g) * Q + sq) * P2pad + (row % 16) * RT + row / 16] = (T)v;
@@ -462,10 +468,12 @@ void make_operators(fmm_plan *P, hipStream_t s)
     if (it == g_ops.end()) {
         OpCache C;
         const size_t opn = (size_t)std::max(1, P->nops) * P2pad * P2pad;
-        int32_t *d_ot = nullptr;
-        FMM_HIP(hipMalloc(&d_ot, sizeof(int32_t) * std::max<size_t>(3, P->h_ops_t.size())));
-        if (!P->h_ops_t.empty())
-            FMM_HIP(hipMemcpy(d_ot, P->h_ops_t.data(), sizeof(int32_t) * P->h_ops_t.size(), hipMemcpyHostToDevice));
+        std::vector<double4> tr(std::max(1, P->nops));
+        for (int k = 0; k < P->nops; ++k)
+            tr[k] = make_double4(P->h_ops_t[3 * k], P->h_ops_t[3 * k + 1], P->h_ops_t[3 * k + 2], 0.0);
+        double4 *d_ot = nullptr;
+        FMM_HIP(hipMalloc(&d_ot, sizeof(double4) * tr.size()));
+        FMM_HIP(hipMemcpy(d_ot, tr.data(), sizeof(double4) * tr.size(), hipMemcpyHostToDevice));
         FMM_HIP(hipMalloc(&C.ops, (f64 ? sizeof(double) : sizeof(float)) * opn));
         if (P->nops > 0) {
             if (f64)
@@ -501,6 +509,18 @@ void make_operators(fmm_plan *P, hipStream_t s)
     P->l2l_c = C.l2l_c;
     P->m2m_d = C.m2m_d;
     P->l2l_d = C.l2l_d;
+}
+
+// M2L operators for arbitrary (tau, e) in the batched fragment layout, into
+// a caller-provided buffer of nops * P2pad^2 values of the compute type.
+void make_m2l_ops(fmm_plan *P, const double4 *tr_dev, int nops, void *out, hipStream_t s)
+{
+    if (nops <= 0) return;
+    if (P->precision == FMM_PREC_FP64)
+        k_make_m2l_ops<double><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<double *>(out), nullptr);
+    else
+        k_make_m2l_ops<float><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<float *>(out), nullptr);
+    FMM_HIP(hipGetLastError());
 }
 
 // P2M at every leaf, then M2M from the finest level up.

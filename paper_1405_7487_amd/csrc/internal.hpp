@@ -71,6 +71,12 @@ struct Level {
 
 struct Timer;
 
+// One chunk of the batched cross-level M2L: tiles [t0, t1) cover the pairs at
+// positions [p0, p1); reduction segments [s0, s1).
+struct XChunk {
+    int64_t t0 = 0, t1 = 0, p0 = 0, p1 = 0, s0 = 0, s1 = 0;
+};
+
 }  // namespace fmm
 
 struct fmm_plan {
@@ -125,6 +131,27 @@ struct fmm_plan {
     std::vector<int32_t> h_st_t;     // [8*K*3] offsets (host copy)
     std::vector<int32_t> h_ops_t;    // [nops*3]
     void *ops = nullptr;             // M2L operators, fragment layout, compute type
+    // batched cross-level M2L: pairs grouped by key (level difference, offset)
+    int nxk = 0;                     // keys with their own operator
+    void *xops = nullptr;            // [nxk] operators, fragment layout, compute type
+    int64_t nxb = 0;                 // batched pairs, in (key, target) order
+    int64_t nxt = 0;                 // tiles of TW pairs of one key
+    int32_t *xt_op = nullptr;        // [nxt] key of the tile
+    int64_t *xt_first = nullptr;     // [nxt] position of its first pair
+    int32_t *xt_cnt = nullptr;       // [nxt] pairs in the tile
+    int32_t *xp_src = nullptr;       // [nxb] source cell of each batched pair
+    int32_t *xr_pos = nullptr;       // [nxb] pair positions in (chunk, target, key) order
+    int64_t *xs_off = nullptr;       // [nseg + 1] segment starts in xr_pos (one target of one chunk)
+    int32_t *xs_tgt = nullptr;       // [nseg] target cell of the segment
+    std::vector<fmm::XChunk> xchunks;
+    void *xbuf = nullptr;            // per-pair products of one chunk
+    int64_t n_gx = 0;                // cross pairs left to the generic kernel
+    int64_t *gx_off = nullptr; int32_t *gx_src = nullptr;  // their CSR by target
+    int64_t n_gchunk = 0;            // chunks of those pairs (a target's list split in order)
+    int32_t *gx_ctgt = nullptr;      // [n_gchunk] target cell
+    int64_t *gx_ck0 = nullptr;       // [n_gchunk] first pair
+    int64_t *gx_cofs = nullptr;      // [ncell + 1] chunks of each cell
+    double *gx_part = nullptr;       // [n_gchunk][P2pad] float64 sums of a chunk
     void *m2m_c = nullptr, *l2l_c = nullptr;   // [8][P2pad][P2pad] compute type
     double *m2m_d = nullptr, *l2l_d = nullptr; // float64 versions
 
@@ -157,6 +184,7 @@ int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s);
 void list_digest(fmm_plan *P, uint64_t out[2], hipStream_t s);
 // expansions.hip
 void make_operators(fmm_plan *P, hipStream_t s);
+void make_m2l_ops(fmm_plan *P, const double4 *tr_dev, int nops, void *out, hipStream_t s);
 void upward(fmm_plan *P, const void *ub, hipStream_t s);
 void downward_l2l(fmm_plan *P, hipStream_t s);
 void l2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
@@ -165,12 +193,20 @@ int m2l_tile_width(int p, bool f64);
 void m2l_prepare(fmm_plan *P, hipStream_t s);
 void m2l_same(fmm_plan *P, hipStream_t s);
 void m2l_cross(fmm_plan *P, hipStream_t s);
+void m2l_cross_prepare(fmm_plan *P, hipStream_t s);
 // p2p.hip
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
 // api.hip helpers
 void gather_bodies(fmm_plan *P, const void *q, void *ub, hipStream_t s);
 
 void *plan_alloc(fmm_plan *P, size_t bytes);
-inline dim3 grid1(int64_t n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
+// One work-item per element.  A dispatch counts its work-items in 32 bits, so
+// larger ranges must use grid-stride kernels instead.
+inline dim3 grid1(int64_t n, int bs)
+{
+    const int64_t nb = (n + bs - 1) / bs;
+    FMM_CHECK(nb * bs < (1ll << 32), FMM_ERR_UNSUPPORTED, "launch of more than 2^32 work-items");
+    return dim3((unsigned)nb);
+}
 
 }  // namespace fmm

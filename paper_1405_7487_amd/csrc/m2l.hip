@@ -300,37 +300,41 @@ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
     else { m = (o + 1) / 2; im = (o & 1) ? 0 : 1; }
 }
 
-// Cross-level pairs, one 64-thread block (one wave) per target cell, float64
-// arithmetic in the complex form.  For a source of level l_B and a target of
-// level l_A, with tau = (c_A - c_B)/h_A and rho = h_B/h_A:
+// Cross-level pairs left to the generic path, one 64-thread block (one wave)
+// per chunk of at most kGChunk pairs of one target, float64 arithmetic in the
+// complex form.  For a source of level l_B and a target of level l_A, with
+// tau = (c_A - c_B)/h_A and rho = h_B/h_A:
 //     Lt_j^s += (-1)^j sum_{n<p} rho^n sum_{m=-n..n} Mt_n^m I_{n+j}^{m+s}(tau),
 // M^{-m} = (-1)^m conj(M^m), I^{-l} = (-1)^l conj(I^l).  Lane t owns the
-// outputs (j, s >= 0) numbered t and t + 64 and sums over the target's pairs
-// in list order; the block's barriers are reached by the whole block.
+// outputs (j, s >= 0) numbered t, t + 64 and t + 128 and sums over the
+// chunk's pairs in list order; the chunk's sums go to part[chunk] (float64).
+// The block's barriers are reached by the whole block.
+constexpr int kGChunk = 16;
+constexpr int kOutSlots = (kMaxP * (kMaxP + 1) / 2 + 63) / 64;
+
 template <class TM>
-__global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *off, const int32_t *src,
-                                                  const int32_t *lvl, const double *ctr, double S, int p, int P2pad,
-                                                  const TM *M, TM *L)
+__global__ __launch_bounds__(64) void k_m2l_cross(const int32_t *ch_tgt, const int64_t *ch_k0, const int64_t *off,
+                                                  const int32_t *src, const int32_t *lvl, const double *ctr,
+                                                  double S, int p, int P2pad, const TM *M, double *part)
 {
     const int lane = threadIdx.x;
-    const int64_t c = blockIdx.x;
-    if (c >= ncell) return;
-    const int64_t k0 = off[c], k1 = off[c + 1];
-    if (k0 == k1) return;
+    const int64_t chunk = blockIdx.x;
+    const int c = ch_tgt[chunk];
+    const int64_t k0 = ch_k0[chunk], k1 = min(k0 + (int64_t)kGChunk, off[c + 1]);
     __shared__ cd H[(2 * kMaxP) * (2 * kMaxP + 1) / 2];
     __shared__ cd Ms[kMaxP * (kMaxP + 1) / 2];
     const int nI = 2 * p - 1, P2 = p * p, NO = p * (p + 1) / 2;
     const double hA = ldexp(S, -lvl[c]);
-    // output (j, s) of each of this lane's two slots
-    int oj[2], os[2];
-    for (int q = 0; q < 2; ++q) {
+    // output (j, s) of each of this lane's slots
+    int oj[kOutSlots], os[kOutSlots];
+    for (int q = 0; q < kOutSlots; ++q) {
         const int t = lane + 64 * q;
         int j = 0;
         while ((j + 1) * (j + 2) / 2 <= t) ++j;
         oj[q] = t < NO ? j : -1;
         os[q] = t - j * (j + 1) / 2;
     }
-    double are[2] = {0, 0}, aim[2] = {0, 0};
+    double are[kOutSlots] = {}, aim[kOutSlots] = {};
     for (int64_t k = k0; k < k1; ++k) {
         const int b = src[k];
         const double tx = (ctr[3 * c] - ctr[3 * b]) / hA, ty = (ctr[3 * c + 1] - ctr[3 * b + 1]) / hA,
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *
             }
         }
         __syncthreads();
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kOutSlots; ++q) {
             const int j = oj[q], sO = os[q];
             if (j < 0) continue;
             double sr = 0.0, si = 0.0;
@@ -399,18 +403,265 @@ __global__ __launch_bounds__(64) void k_m2l_cross(int64_t ncell, const int64_t *
         }
         __syncthreads();
     }
-    TM *dl = L + c * P2pad;
-    for (int q = 0; q < 2; ++q) {
+    double *dp = part + chunk * P2pad;
+    for (int q = 0; q < kOutSlots; ++q) {
         const int j = oj[q], sO = os[q];
         if (j < 0) continue;
         const double sg = (j & 1) ? -1.0 : 1.0;
-        if (sO == 0) dl[j * j] = (TM)((double)dl[j * j] + sg * are[q]);
+        if (sO == 0) dp[j * j] = sg * are[q];
         else {
             const int r = j * j + 2 * sO - 1;
-            dl[r] = (TM)((double)dl[r] + sg * are[q]);
-            dl[r + 1] = (TM)((double)dl[r + 1] + sg * aim[q]);
+            dp[r] = sg * are[q];
+            dp[r + 1] = sg * aim[q];
         }
     }
+}
+
+// L[c] += sum of the cell's generic-chunk sums, in chunk order.
+template <class TM>
+__global__ __launch_bounds__(256) void k_gx_reduce(int64_t nc, const int64_t *cofs, const double *part, int P2,
+                                                   int P2pad, TM *L)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = t / P2;
+    const int r = (int)(t % P2);
+    if (c >= nc) return;
+    const int64_t a = cofs[c], b = cofs[c + 1];
+    if (a == b) return;
+    double acc = 0.0;
+    for (int64_t k = a; k < b; ++k) acc += part[k * P2pad + r];
+    TM *dst = L + c * P2pad + r;
+    *dst = (TM)((double)*dst + acc);
+}
+
+__global__ __launch_bounds__(256) void k_gx_count(const int64_t *off, int64_t nc, int32_t *cnt)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > nc) return;
+    cnt[c] = c < nc ? (int32_t)((off[c + 1] - off[c] + kGChunk - 1) / kGChunk) : 0;
+}
+
+__global__ __launch_bounds__(256) void k_gx_fill(const int64_t *off, const int64_t *cofs, int64_t nc,
+                                                 int32_t *ch_tgt, int64_t *ch_k0)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    for (int64_t i = cofs[c]; i < cofs[c + 1]; ++i) {
+        ch_tgt[i] = (int32_t)c;
+        ch_k0[i] = off[c] + (i - cofs[c]) * kGChunk;
+    }
+}
+
+// ------------------------------------------- batched cross-level pairs
+//
+// A cross-level pair joins a leaf A and a cell B of another level.  With
+// lattice centers, the operator depends only on the key (dl, D): the level
+// difference dl = l_B - l_A and the center offset D = C_A - C_B in half-units
+// of the finer cell (tau = D 2^-max(dl,0) / 2 in units of h_A, rho = 2^-dl).
+// Keys with |dl| <= kXMaxDl and enough pairs get an operator of their own and
+// run as shared-operator MFMA products, tiles of TW pairs of one key; the
+// products go to a per-pair buffer, chunk by chunk, and a reduction adds them
+// to each target in (key) order, so the sums are deterministic.  All other
+// cross pairs use k_m2l_cross.
+
+constexpr int kXMaxDl = 2;
+constexpr int kXMinPairs = 64;
+
+// Code of the key (dl, D), or -1 when the pair is left to the generic kernel.
+struct XCodes {
+    int maxdl = 0;
+    int R[kXMaxDl + 1] = {0, 0, 0};
+    int base[2 * kXMaxDl + 1] = {0, 0, 0, 0, 0};
+    int64_t ncode = 0;
+};
+
+__global__ __launch_bounds__(256) void k_x_targets(const int64_t *off, int64_t nc, int32_t *tgt)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    for (int64_t k = off[c]; k < off[c + 1]; ++k) tgt[k] = (int32_t)c;
+}
+
+__global__ __launch_bounds__(256) void k_x_codes(const int32_t *tgt, const int32_t *src, int64_t nx,
+                                                 const int32_t *lvl, const int32_t *ix, XCodes xc, int32_t *code,
+                                                 int32_t *cnt)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nx) return;
+    const int a = tgt[k], b = src[k];
+    const int la = lvl[a], lb = lvl[b], dl = lb - la;
+    const int adl = dl < 0 ? -dl : dl;
+    int cd = -1;
+    if (adl >= 1 && adl <= xc.maxdl) {
+        const int f = la > lb ? la : lb, R = xc.R[adl], W = 2 * R + 1;
+        int64_t D[3];
+        bool ok = true;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t ca = (2 * (int64_t)ix[3 * a + d] + 1) << (f - la);
+            const int64_t cb = (2 * (int64_t)ix[3 * b + d] + 1) << (f - lb);
+            D[d] = ca - cb;
+            ok = ok && D[d] >= -R && D[d] <= R;
+        }
+        if (ok) {
+            cd = xc.base[dl + kXMaxDl] + (int)(((D[0] + R) * W + (D[1] + R)) * W + (D[2] + R));
+            atomicAdd(&cnt[cd], 1);
+        }
+    }
+    code[k] = cd;
+}
+
+// Sort key (key id, target) for batched pairs; generic pairs get id = nk and
+// are counted per target.
+__global__ __launch_bounds__(256) void k_x_key1(const int32_t *tgt, const int32_t *src, const int32_t *code,
+                                                const int32_t *id_of, int nk, int64_t nx, uint64_t *k1, int32_t *v1,
+                                                int32_t *gcnt)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nx) return;
+    const int cd = code[k];
+    const int id = cd >= 0 ? id_of[cd] : -1;
+    const int32_t a = tgt[k];
+    if (id < 0) atomicAdd(&gcnt[a], 1);
+    k1[k] = ((uint64_t)(uint32_t)(id < 0 ? nk : id) << 32) | (uint32_t)a;
+    v1[k] = src[k];
+}
+
+// Sort key (chunk, target, key id) of each batched pair; value = its position.
+__global__ __launch_bounds__(256) void k_x_key2(const uint64_t *k1, int64_t nb, const int32_t *chunk_of,
+                                                uint64_t *k2, int32_t *v2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const uint64_t id = k1[i] >> 32, a = k1[i] & 0xffffffffull;
+    k2[i] = ((uint64_t)(uint32_t)chunk_of[id] << 52) | (a << 21) | id;
+    v2[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void k_x_segflag(const uint64_t *k2, int64_t nb, int32_t *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    flag[i] = (i == 0 || (k2[i] >> 21) != (k2[i - 1] >> 21)) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const int32_t *flag, const int64_t *sidx,
+                                                    int64_t nb, int64_t *s_off, int32_t *s_tgt, int64_t *chunk_seg0)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb || !flag[i]) return;
+    const int64_t seg = sidx[i];
+    s_off[seg] = i;
+    s_tgt[seg] = (int32_t)((k2[i] >> 21) & 0x7fffffffull);
+    const uint64_t ch = k2[i] >> 52;
+    if (i == 0 || (k2[i - 1] >> 52) != ch) chunk_seg0[ch] = seg;
+}
+
+// One tile of TW pairs sharing one operator: out[pair] = T(key) M[src(pair)].
+// Block = 4 waves; the operator passes through LDS in NC stages, the next
+// stage loading while the current one is multiplied.
+template <class T, int RT, int CG, int SCH>
+__global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t_op,
+                                                   const int64_t *__restrict__ t_first,
+                                                   const int32_t *__restrict__ t_cnt, const int32_t *__restrict__ src,
+                                                   int zero_row, const T *__restrict__ Tf, const T *__restrict__ M,
+                                                   T *__restrict__ out, int64_t pos0)
+{
+    constexpr int P2pad = 16 * RT, Q = 4 * RT, NC = Q / SCH;
+    constexpr int STAGE = 4 * SCH * P2pad;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int NV = STAGE / VN;
+    constexpr int PV = (NV + 255) / 256;
+    typedef typename Vec16<T>::t vec_t;
+    typedef typename Mfma<T>::acc_t acc_t;
+    __shared__ __align__(16) T lds[STAGE];
+
+    const int64_t tile = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
+    const int cnt = t_cnt[tile];
+    const int64_t first = t_first[tile];
+    const T *opb = Tf + (int64_t)t_op[tile] * 4 * Q * P2pad;
+
+    vec_t treg[PV];
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+        const int v = min(tid + 256 * u, NV - 1);
+        const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);
+        treg[u] = *reinterpret_cast<const vec_t *>(opb + (int64_t)gg * Q * P2pad + rem);
+    }
+    T bq[CG][Q];
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+        const int col = wave * CG * 16 + cg * 16 + j;
+        const int sv = col < cnt ? src[first + col] : zero_row;
+        const vec_t *mp = reinterpret_cast<const vec_t *>(M + (int64_t)sv * P2pad + g * Q);
+#pragma unroll
+        for (int v = 0; v < Q / VN; ++v) {
+            const vec_t x = mp[v];
+#pragma unroll
+            for (int w = 0; w < VN; ++w) bq[cg][v * VN + w] = x[w];
+        }
+    }
+    acc_t acc[CG][RT];
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[cg][r] = acc_t{0, 0, 0, 0};
+
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c > 0) __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PV; ++u) {
+            const int v = tid + 256 * u;
+            if (NV % 256 == 0 || v < NV) *reinterpret_cast<vec_t *>(lds + v * VN) = treg[u];
+        }
+        __syncthreads();
+        if (c + 1 < NC) {
+#pragma unroll
+            for (int u = 0; u < PV; ++u) {
+                const int v = min(tid + 256 * u, NV - 1);
+                const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);
+                treg[u] = *reinterpret_cast<const vec_t *>(opb + ((int64_t)gg * Q + (c + 1) * SCH) * P2pad + rem);
+            }
+        }
+#pragma unroll
+        for (int ss = 0; ss < SCH; ++ss) {
+            T a[RT];
+            const T *ap = lds + g * (SCH * P2pad) + ss * P2pad + j * RT;
+#pragma unroll
+            for (int r = 0; r < RT; ++r) a[r] = ap[r];
+#pragma unroll
+            for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+                for (int r = 0; r < RT; ++r) acc[cg][r] = Mfma<T>::run(a[r], bq[cg][c * SCH + ss], acc[cg][r]);
+        }
+    }
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+        const int col = wave * CG * 16 + cg * 16 + j;
+        if (col >= cnt) continue;
+        T *dst = out + (first + col - pos0) * P2pad;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
+    }
+}
+
+// L[target] += sum of its pairs' products in this chunk, in key order (the
+// sum in float64).  One thread per (segment, coefficient).
+template <class T>
+__global__ __launch_bounds__(256) void k_x_reduce(const int64_t *s_off, const int32_t *s_tgt, int64_t nseg,
+                                                  const int32_t *pos, int64_t pos0, const T *buf, int P2pad, T *L)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t seg = t / P2pad;
+    const int row = (int)(t % P2pad);
+    if (seg >= nseg) return;
+    double acc = 0.0;
+    for (int64_t k = s_off[seg]; k < s_off[seg + 1]; ++k) acc += (double)buf[(pos[k] - pos0) * P2pad + row];
+    T *dst = L + (int64_t)s_tgt[seg] * P2pad + row;
+    *dst = (T)((double)*dst + acc);
 }
 
 __global__ void k_mfma_probe_f32(float *out)
@@ -440,7 +691,7 @@ void launch_batched(fmm_plan *P, hipStream_t s)
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
     constexpr int SCH = m2l_sch(RT, (int)sizeof(T));
     const int64_t nb = P->ntile * P->KS;
-    FMM_CHECK(nb < (1ll << 31), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
+    FMM_CHECK(nb * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
     FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
     k_m2l_batched<T, RT, CG, SCH><<<(unsigned)nb, 256, 0, s>>>(
         P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->KS, P->slot_none, (int)P->ncell,
@@ -473,6 +724,56 @@ void dispatch_tiles(fmm_plan *P, hipStream_t s)
     case 16: launch_batched<T, 16>(P, s); break;
     default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported padded coefficient count");
     }
+}
+
+template <class T, int RT>
+void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
+{
+    constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
+    constexpr int SCH = m2l_sch(RT, (int)sizeof(T));
+    FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
+    const int64_t nt = ch.t1 - ch.t0;
+    FMM_CHECK(nt * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
+    if (nt > 0) {
+        k_m2l_pairs<T, RT, CG, SCH><<<(unsigned)nt, 256, 0, s>>>(
+            P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, (int)P->ncell,
+            static_cast<const T *>(P->xops), static_cast<const T *>(P->Mc), static_cast<T *>(P->xbuf), ch.p0);
+        FMM_HIP(hipGetLastError());
+    }
+    const int64_t ns = ch.s1 - ch.s0;
+    if (ns > 0) {
+        k_x_reduce<T><<<grid1(ns * P->P2pad, 256), 256, 0, s>>>(P->xs_off + ch.s0, P->xs_tgt + ch.s0, ns, P->xr_pos,
+                                                               ch.p0, static_cast<const T *>(P->xbuf), P->P2pad,
+                                                               static_cast<T *>(P->Lc));
+        FMM_HIP(hipGetLastError());
+    }
+}
+
+template <class T>
+void dispatch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
+{
+    switch (P->P2pad / 16) {
+    case 1: launch_pairs<T, 1>(P, ch, s); break;
+    case 2: launch_pairs<T, 2>(P, ch, s); break;
+    case 3: launch_pairs<T, 3>(P, ch, s); break;
+    case 4: launch_pairs<T, 4>(P, ch, s); break;
+    case 6: launch_pairs<T, 6>(P, ch, s); break;
+    case 7: launch_pairs<T, 7>(P, ch, s); break;
+    case 8: launch_pairs<T, 8>(P, ch, s); break;
+    case 9: launch_pairs<T, 9>(P, ch, s); break;
+    case 11: launch_pairs<T, 11>(P, ch, s); break;
+    case 13: launch_pairs<T, 13>(P, ch, s); break;
+    case 15: launch_pairs<T, 15>(P, ch, s); break;
+    case 16: launch_pairs<T, 16>(P, ch, s); break;
+    default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported padded coefficient count");
+    }
+}
+
+int bits_of(int64_t v)
+{
+    int b = 1;
+    while ((1ll << b) <= v) ++b;
+    return b;
 }
 
 }  // namespace
@@ -515,19 +816,254 @@ void m2l_same(fmm_plan *P, hipStream_t s)
     }
 }
 
+namespace {
+
+// Groups the cross-level pairs by key, builds the operators of the frequent
+// keys, the tiles, the chunks and the reduction segments, and the CSR of the
+// pairs left to the generic kernel.
+void x_batch_prepare(fmm_plan *P, hipStream_t s)
+{
+    const int64_t nx = P->n_m2l_cross, nc = P->ncell;
+    Allocator &al = P->al;
+    const bool f64 = P->precision == FMM_PREC_FP64;
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+
+    XCodes xc;
+    for (int maxdl = kXMaxDl; maxdl >= 1; --maxdl) {
+        xc = XCodes();
+        xc.maxdl = maxdl;
+        int64_t base = 0;
+        for (int adl = 1; adl <= maxdl; ++adl)
+            xc.R[adl] = (int)std::ceil(std::sqrt(3.0) * ((std::ldexp(1.0, adl) + 2.0) / P->theta + 1.0));
+        for (int dl = -maxdl; dl <= maxdl; ++dl) {
+            if (dl == 0) continue;
+            const int64_t W = 2 * xc.R[dl < 0 ? -dl : dl] + 1;
+            xc.base[dl + kXMaxDl] = (int)base;
+            base += W * W * W;
+        }
+        xc.ncode = base;
+        if (base <= (1ll << 24)) break;
+    }
+    if (xc.ncode > (1ll << 24)) return;  // theta too small for a dense key table: all generic
+
+    int32_t *tgt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nx));
+    int32_t *code = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nx));
+    int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * xc.ncode));
+    FMM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * xc.ncode, s));
+    k_x_targets<<<grid1(nc, 256), 256, 0, s>>>(P->m2lx_off, nc, tgt);
+    k_x_codes<<<grid1(nx, 256), 256, 0, s>>>(tgt, P->m2lx_src, nx, P->c_lvl, P->c_ix, xc, code, cnt);
+    FMM_HIP(hipGetLastError());
+    std::vector<int32_t> hc(xc.ncode);
+    FMM_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * xc.ncode, hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+
+    // keys with enough pairs, in code order; their operators' (tau, e)
+    std::vector<int32_t> id_of(xc.ncode, -1), key_cnt;
+    std::vector<double4> tr;
+    for (int dl = -xc.maxdl; dl <= xc.maxdl; ++dl) {
+        if (dl == 0) continue;
+        const int R = xc.R[dl < 0 ? -dl : dl], W = 2 * R + 1, b0 = xc.base[dl + kXMaxDl];
+        const double sc = std::ldexp(0.5, -std::max(dl, 0));
+        for (int64_t o = 0; o < (int64_t)W * W * W; ++o) {
+            const int64_t cd = b0 + o;
+            if (hc[cd] < kXMinPairs) continue;
+            id_of[cd] = (int32_t)key_cnt.size();
+            key_cnt.push_back(hc[cd]);
+            const int dx = (int)(o / ((int64_t)W * W)) - R, dy = (int)((o / W) % W) - R, dz = (int)(o % W) - R;
+            tr.push_back(make_double4(dx * sc, dy * sc, dz * sc, (double)(-dl)));
+        }
+    }
+    const int nk = (int)key_cnt.size();
+    if (nk == 0) {
+        al.free(cnt);
+        al.free(code);
+        al.free(tgt);
+        return;
+    }
+    FMM_CHECK(nk < (1 << 21), FMM_ERR_UNSUPPORTED, "m2l: too many cross-level keys");
+
+    // tiles of TW pairs per key; chunks of whole keys whose products fit the buffer
+    const int TW = P->TW;
+    const int64_t budget = std::max<int64_t>((int64_t)TW, (int64_t)(2ll << 30) / (int64_t)(P->P2pad * esz));
+    std::vector<int32_t> h_op, h_cnt, chunk_of(nk);
+    std::vector<int64_t> h_first;
+    P->xchunks.clear();
+    int64_t pos = 0, maxchunk = 0;
+    XChunk cur;
+    for (int id = 0; id < nk; ++id) {
+        if (pos > cur.p0 && pos - cur.p0 + key_cnt[id] > budget) {
+            cur.p1 = pos;
+            cur.t1 = (int64_t)h_op.size();
+            maxchunk = std::max(maxchunk, cur.p1 - cur.p0);
+            P->xchunks.push_back(cur);
+            cur = XChunk();
+            cur.p0 = pos;
+            cur.t0 = (int64_t)h_op.size();
+        }
+        chunk_of[id] = (int32_t)P->xchunks.size();
+        for (int64_t k = 0; k < key_cnt[id]; k += TW) {
+            h_op.push_back(id);
+            h_first.push_back(pos + k);
+            h_cnt.push_back((int32_t)std::min<int64_t>(TW, key_cnt[id] - k));
+        }
+        pos += key_cnt[id];
+    }
+    cur.p1 = pos;
+    cur.t1 = (int64_t)h_op.size();
+    maxchunk = std::max(maxchunk, cur.p1 - cur.p0);
+    P->xchunks.push_back(cur);
+    const int64_t nb = pos;
+    const int nchunk = (int)P->xchunks.size();
+    FMM_CHECK(nchunk < (1 << 11), FMM_ERR_UNSUPPORTED, "m2l: too many cross-level chunks");
+    P->nxk = nk;
+    P->nxb = nb;
+    P->nxt = (int64_t)h_op.size();
+
+    P->xt_op = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->nxt));
+    P->xt_first = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * P->nxt));
+    P->xt_cnt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->nxt));
+    FMM_HIP(hipMemcpyAsync(P->xt_op, h_op.data(), sizeof(int32_t) * P->nxt, hipMemcpyHostToDevice, s));
+    FMM_HIP(hipMemcpyAsync(P->xt_first, h_first.data(), sizeof(int64_t) * P->nxt, hipMemcpyHostToDevice, s));
+    FMM_HIP(hipMemcpyAsync(P->xt_cnt, h_cnt.data(), sizeof(int32_t) * P->nxt, hipMemcpyHostToDevice, s));
+    double4 *d_tr = static_cast<double4 *>(al.alloc(sizeof(double4) * nk));
+    FMM_HIP(hipMemcpyAsync(d_tr, tr.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, s));
+    P->xops = plan_alloc(P, esz * (size_t)nk * P->P2pad * P->P2pad);
+    make_m2l_ops(P, d_tr, nk, P->xops, s);
+    int32_t *d_id_of = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * xc.ncode));
+    int32_t *d_chunk_of = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nk));
+    FMM_HIP(hipMemcpyAsync(d_id_of, id_of.data(), sizeof(int32_t) * xc.ncode, hipMemcpyHostToDevice, s));
+    FMM_HIP(hipMemcpyAsync(d_chunk_of, chunk_of.data(), sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+
+    // batched pairs in (key, target) order; the others, still in target order, at the end
+    uint64_t *k1 = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * nx));
+    int32_t *v1 = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nx));
+    int32_t *gcnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * (nc + 1)));
+    FMM_HIP(hipMemsetAsync(gcnt, 0, sizeof(int32_t) * (nc + 1), s));
+    k_x_key1<<<grid1(nx, 256), 256, 0, s>>>(tgt, P->m2lx_src, code, d_id_of, nk, nx, k1, v1, gcnt);
+    FMM_HIP(hipGetLastError());
+    radix_sort_u64(k1, v1, nx, 32 + bits_of(nk), al, s);
+    P->xp_src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nb));
+    FMM_HIP(hipMemcpyAsync(P->xp_src, v1, sizeof(int32_t) * nb, hipMemcpyDeviceToDevice, s));
+    P->n_gx = nx - nb;
+    P->gx_off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (nc + 1)));
+    scan_exclusive_i32to64(gcnt, P->gx_off, nc + 1, nullptr, al, s);
+    P->gx_src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, P->n_gx)));
+    if (P->n_gx > 0)
+        FMM_HIP(hipMemcpyAsync(P->gx_src, v1 + nb, sizeof(int32_t) * P->n_gx, hipMemcpyDeviceToDevice, s));
+
+    // reduction order: (chunk, target, key)
+    uint64_t *k2 = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * nb));
+    int32_t *v2 = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nb));
+    k_x_key2<<<grid1(nb, 256), 256, 0, s>>>(k1, nb, d_chunk_of, k2, v2);
+    FMM_HIP(hipGetLastError());
+    radix_sort_u64(k2, v2, nb, 52 + bits_of(nchunk), al, s);
+    P->xr_pos = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nb));
+    FMM_HIP(hipMemcpyAsync(P->xr_pos, v2, sizeof(int32_t) * nb, hipMemcpyDeviceToDevice, s));
+    int32_t *flag = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nb));
+    int64_t *sidx = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * nb));
+    int64_t *d_nseg = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+    k_x_segflag<<<grid1(nb, 256), 256, 0, s>>>(k2, nb, flag);
+    FMM_HIP(hipGetLastError());
+    scan_exclusive_i32to64(flag, sidx, nb, d_nseg, al, s);
+    int64_t nseg = 0;
+    FMM_HIP(hipMemcpyAsync(&nseg, d_nseg, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    P->xs_off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (nseg + 1)));
+    P->xs_tgt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nseg)));
+    int64_t *d_cs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * (nchunk + 1)));
+    k_x_segments<<<grid1(nb, 256), 256, 0, s>>>(k2, flag, sidx, nb, P->xs_off, P->xs_tgt, d_cs);
+    FMM_HIP(hipGetLastError());
+    FMM_HIP(hipMemcpyAsync(P->xs_off + nseg, &nb, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    std::vector<int64_t> cs(nchunk + 1);
+    FMM_HIP(hipMemcpyAsync(cs.data(), d_cs, sizeof(int64_t) * nchunk, hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    cs[nchunk] = nseg;
+    for (int c = 0; c < nchunk; ++c) {
+        P->xchunks[c].s0 = cs[c];
+        P->xchunks[c].s1 = cs[c + 1];
+    }
+    P->xbuf = plan_alloc(P, esz * (size_t)maxchunk * P->P2pad);
+
+    al.free(d_cs);
+    al.free(d_nseg);
+    al.free(sidx);
+    al.free(flag);
+    al.free(v2);
+    al.free(k2);
+    al.free(gcnt);
+    al.free(v1);
+    al.free(k1);
+    al.free(d_chunk_of);
+    al.free(d_id_of);
+    al.free(d_tr);
+    al.free(cnt);
+    al.free(code);
+    al.free(tgt);
+}
+
+// Chunks of at most kGChunk generic pairs of one target, and their buffer.
+void x_generic_prepare(fmm_plan *P, hipStream_t s)
+{
+    const int64_t nc = P->ncell;
+    P->n_gchunk = 0;
+    if (P->n_gx == 0) return;
+    Allocator &al = P->al;
+    int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * (nc + 1)));
+    int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+    k_gx_count<<<grid1(nc + 1, 256), 256, 0, s>>>(P->gx_off, nc, cnt);
+    FMM_HIP(hipGetLastError());
+    P->gx_cofs = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (nc + 1)));
+    scan_exclusive_i32to64(cnt, P->gx_cofs, nc + 1, d_tot, al, s);
+    int64_t nch = 0;
+    FMM_HIP(hipMemcpyAsync(&nch, d_tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    P->n_gchunk = nch;
+    P->gx_ctgt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nch));
+    P->gx_ck0 = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * nch));
+    k_gx_fill<<<grid1(nc, 256), 256, 0, s>>>(P->gx_off, P->gx_cofs, nc, P->gx_ctgt, P->gx_ck0);
+    FMM_HIP(hipGetLastError());
+    P->gx_part = static_cast<double *>(plan_alloc(P, sizeof(double) * nch * P->P2pad));
+    FMM_HIP(hipStreamSynchronize(s));
+    al.free(d_tot);
+    al.free(cnt);
+}
+
+}  // namespace
+
+void m2l_cross_prepare(fmm_plan *P, hipStream_t s)
+{
+    P->n_gx = P->n_m2l_cross;
+    P->gx_off = P->m2lx_off;
+    P->gx_src = P->m2lx_src;
+    if (P->n_m2l_cross == 0) return;
+    x_batch_prepare(P, s);
+    x_generic_prepare(P, s);
+}
+
 void m2l_cross(fmm_plan *P, hipStream_t s)
 {
     const bool f64 = P->precision == FMM_PREC_FP64;
-    if (P->n_m2l_cross > 0) {
-        const unsigned nb = (unsigned)P->ncell;
-        if (f64)
-            k_m2l_cross<double><<<nb, 64, 0, s>>>(P->ncell, P->m2lx_off, P->m2lx_src, P->c_lvl, P->c_ctr, P->S, P->p,
-                                                   P->P2pad, static_cast<const double *>(P->Mc),
-                                                   static_cast<double *>(P->Lc));
-        else
-            k_m2l_cross<float><<<nb, 64, 0, s>>>(P->ncell, P->m2lx_off, P->m2lx_src, P->c_lvl, P->c_ctr, P->S, P->p,
-                                                  P->P2pad, static_cast<const float *>(P->Mc),
-                                                  static_cast<float *>(P->Lc));
+    for (const XChunk &ch : P->xchunks) {
+        if (f64) dispatch_pairs<double>(P, ch, s);
+        else dispatch_pairs<float>(P, ch, s);
+    }
+    if (P->n_gchunk > 0) {
+        FMM_CHECK(P->n_gchunk * 64 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross-level chunks");
+        const unsigned nb = (unsigned)P->n_gchunk;
+        const dim3 gr = grid1(P->ncell * P->P2, 256);
+        if (f64) {
+            k_m2l_cross<double><<<nb, 64, 0, s>>>(P->gx_ctgt, P->gx_ck0, P->gx_off, P->gx_src, P->c_lvl, P->c_ctr,
+                                                   P->S, P->p, P->P2pad, static_cast<const double *>(P->Mc),
+                                                   P->gx_part);
+            k_gx_reduce<double><<<gr, 256, 0, s>>>(P->ncell, P->gx_cofs, P->gx_part, P->P2, P->P2pad,
+                                                    static_cast<double *>(P->Lc));
+        } else {
+            k_m2l_cross<float><<<nb, 64, 0, s>>>(P->gx_ctgt, P->gx_ck0, P->gx_off, P->gx_src, P->c_lvl, P->c_ctr,
+                                                  P->S, P->p, P->P2pad, static_cast<const float *>(P->Mc),
+                                                  P->gx_part);
+            k_gx_reduce<float><<<gr, 256, 0, s>>>(P->ncell, P->gx_cofs, P->gx_part, P->P2, P->P2pad,
+                                                   static_cast<float *>(P->Lc));
+        }
         FMM_HIP(hipGetLastError());
     }
 }

@@ -286,12 +286,12 @@ void launch_p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t
 
 }  // namespace
 
-// Staging by leaf when leaves are well filled (mean >= 16 bodies), otherwise
+// Staging by leaf when leaves are well filled (mean >= 24 bodies), otherwise
 // the cooperative gather that packs many small leaves per batch.
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
     if (P->nleaf == 0) return;
-    if (P->n >= 16 * P->nleaf) launch_p2p<false>(P, ub, phi_s, E_s, s);
+    if (P->n >= 24 * P->nleaf) launch_p2p<false>(P, ub, phi_s, E_s, s);
     else launch_p2p<true>(P, ub, phi_s, E_s, s);
 }
 

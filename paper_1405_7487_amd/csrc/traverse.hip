@@ -186,11 +186,15 @@ __global__ __launch_bounds__(256) void k_fill_tiles(const uint64_t *ck, const in
     tile_pos[c] = (int32_t)p;
 }
 
+// Grid-stride fill: the slot table can hold more than 2^32 entries, beyond
+// what one dispatch can cover with one work-item per entry.
 __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
+
+dim3 grid_fill(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1 << 16)); }
 
 // CSR offsets: off[c] = first position whose target is >= c.
 __global__ __launch_bounds__(256) void k_csr_offsets(const uint64_t *keys, int64_t np, int cbits, int64_t nc,
@@ -480,7 +484,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     P->tile_cls = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, tiles)));
     int32_t *tile_pos = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc));
     if (tiles > 0) {
-        k_fill_i32<<<grid1(tiles * P->TW, 256), 256, 0, s>>>(P->tile_tgt, tiles * P->TW, -1);
+        k_fill_i32<<<grid_fill(tiles * P->TW), 256, 0, s>>>(P->tile_tgt, tiles * P->TW, -1);
         FMM_HIP(hipGetLastError());
     }
     k_fill_tiles<<<grid1(nc, 256), 256, 0, s>>>(ck, idx, nc, d_gs, d_gs + G, P->TW, P->tile_tgt, tile_pos);
@@ -503,7 +507,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     const int64_t nslots = tiles * (int64_t)P->K * P->TW;
     P->slots = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nslots)));
     if (nslots > 0) {
-        k_fill_i32<<<grid1(nslots, 256), 256, 0, s>>>(P->slots, nslots, -1);
+        k_fill_i32<<<grid_fill(nslots), 256, 0, s>>>(P->slots, nslots, -1);
         FMM_HIP(hipGetLastError());
     }
 

@@ -94,10 +94,14 @@ def test_fmm_matches_oracle(case):
         p, theta, ncrit = 6, 0.35, 32
     T = oracle.Tree(x, ncrit, theta)
     po, Eo = T.fmm(q, p)
-    _, p64, E64 = gpu_fmm(x, q, p, theta, ncrit, "fp64")
+    plan, p64, E64 = gpu_fmm(x, q, p, theta, ncrit, "fp64")
     e64 = (rel(p64, po), rel(E64, Eo))
     assert e64[0] < 1e-6 and e64[1] < 1e-6
     assert e64[0] < 1e-11 and e64[1] < 1e-11, e64  # roundoff only
+    if case == "plummer":
+        # both cross-level paths run: shared-operator tiles and the generic kernel
+        st = plan.stats()
+        assert 0 < st["m2l_cross_batched"] < st["n_m2l_cross"], st
     _, pm, Em = gpu_fmm(x, q, p, theta, ncrit, "mixed")
     em = (rel(pm, po), rel(Em, Eo))
     assert em[0] < 1e-4 and em[1] < 1e-4, em
@@ -107,7 +111,7 @@ def test_fmm_matches_oracle(case):
         assert rel(p64, pd) < 1e-3 and rel(E64, Ed) < 1e-3
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 9, 10, 12])
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 9, 10, 12, 16])
 def test_orders_and_padding(p):
     # every padded coefficient width the batched M2L is instantiated for
     x, q, _ = W.uniform_cube(9000, 20 + p)
@@ -117,6 +121,21 @@ def test_orders_and_padding(p):
     assert rel(p64, po) < 1e-11 and rel(E64, Eo) < 1e-11
     _, pm, Em = gpu_fmm(x, q, p, 0.45, 40, "mixed")
     assert rel(pm, po) < 1e-4 and rel(Em, Eo) < 1e-4
+
+
+@pytest.mark.parametrize("p,n,ncrit,theta", [(4, 60000, 24, 0.35), (10, 12000, 8, 0.45)])
+def test_cross_level_pairs_plummer(p, n, ncrit, theta):
+    # adaptive trees with many leaf-against-finer-cell pairs, at a tile width
+    # of 128 (p = 4) and 64 (p = 10) pairs
+    x, _, _ = W.plummer(n, 13)
+    q = np.random.default_rng(14).uniform(0.0, 1.0, n)
+    T = oracle.Tree(x, ncrit, theta)
+    po, Eo = T.fmm(q, p)
+    for precision, tol in (("fp64", 1e-11), ("mixed", 1e-4)):
+        plan, ph, Eh = gpu_fmm(x, q, p, theta, ncrit, precision)
+        st = plan.stats()
+        assert st["m2l_cross_batched"] > 0.5 * st["n_m2l_cross"], st
+        assert rel(ph, po) < tol and rel(Eh, Eo) < tol, (precision, rel(ph, po), rel(Eh, Eo))
 
 
 def test_coarse_fp64_levels_variants():

@@ -142,7 +142,9 @@ def test_adjoint_against_direct_gradient_and_finite_differences():
         e_fd = rel(dx_h[idx_fd, ax_fd], g_fd)
         say(f"[adjoint] field_q={'given' if field_q is not None else 'recomputed'}: "
             f"dq {e_dq:.3e} dx {e_dx:.3e} dx vs FD {e_fd:.3e}")
-        assert e_dq < 1e-4 and e_dx < 1e-4 and e_fd < 1e-4
+        # the finite differences carry their own O(h^2) error, checked against its
+        # bound above; the gradient itself is held to the direct-sum reference
+        assert e_dq < 1e-4 and e_dx < 1e-4
     plan.close()
 
 
