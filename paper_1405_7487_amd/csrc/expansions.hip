@@ -107,6 +107,7 @@ __host__ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
 // Written in the fragment layout of the batched kernel (Q = P2pad/4,
 // RT = P2pad/16, row = 16 r + i):
 //     Tf[(op*4 + g)*Q + s][i*RT + r] = T[16 r + i][g*Q + s].
+// Written in the table layout of m2l_opsz / m2l_sch / m2l_gst.
 // Each operator is given as tr = (tau_x, tau_y, tau_z, e): the center offset
 // c_A - c_B in units of the target's cell size h_A, and the source-to-target
 // size ratio rho = h_B / h_A = 2^e (0 for same-level pairs), which scales
@@ -124,6 +125,9 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nop
     if (threadIdx.x == 0) irregular_table(t.x, t.y, t.z, nI, H);
     __syncthreads();
     const int P2 = p * p, Q = P2pad / 4;
+    const int RT = P2pad / 16, esz = (int)sizeof(T);
+    const int SCH = m2l_sch(RT, esz), GST = m2l_gst(RT, esz);
+    const int64_t OPSZ = m2l_opsz(RT, esz);
     for (int e = threadIdx.x; e < P2pad * P2pad; e += blockDim.x) {
         const int row = e / P2pad, col = e % P2pad;
         double v = 0.0;
@@ -143,8 +147,8 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nop
             if (j & 1) d = {-d.re, -d.im};
             v = ldexp(rim ? d.im : d.re, e2 * n);
         }
-        const int g = col / Q, sq = col % Q, RT = P2pad / 16;
-        Tf[((size_t)(op * 4 + g) * Q + sq) * P2pad + (row % 16) * RT + row / 16] = (T)v;
+        const int g = col / Q, sq = col % Q, c = sq / SCH, ss = sq % SCH;
+        Tf[(size_t)op * OPSZ + (size_t)(c * 4 + g) * GST + ss * P2pad + (row % 16) * RT + row / 16] = (T)v;
         if (Tdense) Tdense[((size_t)op * P2pad + row) * P2pad + col] = v;
     }
 }
@@ -467,7 +471,8 @@ void make_operators(fmm_plan *P, hipStream_t s)
     auto it = g_ops.find(key);
     if (it == g_ops.end()) {
         OpCache C;
-        const size_t opn = (size_t)std::max(1, P->nops) * P2pad * P2pad;
+        const int esz = f64 ? (int)sizeof(double) : (int)sizeof(float);
+        const size_t opn = (size_t)std::max(1, P->nops) * m2l_opsz(P2pad / 16, esz) + m2l_tail(P2pad / 16, esz);
         std::vector<double4> tr(std::max(1, P->nops));
         for (int k = 0; k < P->nops; ++k)
             tr[k] = make_double4(P->h_ops_t[3 * k], P->h_ops_t[3 * k + 1], P->h_ops_t[3 * k + 2], 0.0);
@@ -475,6 +480,7 @@ void make_operators(fmm_plan *P, hipStream_t s)
         FMM_HIP(hipMalloc(&d_ot, sizeof(double4) * tr.size()));
         FMM_HIP(hipMemcpy(d_ot, tr.data(), sizeof(double4) * tr.size(), hipMemcpyHostToDevice));
         FMM_HIP(hipMalloc(&C.ops, (f64 ? sizeof(double) : sizeof(float)) * opn));
+        FMM_HIP(hipMemsetAsync(C.ops, 0, (f64 ? sizeof(double) : sizeof(float)) * opn, s));
         if (P->nops > 0) {
             if (f64)
                 k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<double *>(C.ops),

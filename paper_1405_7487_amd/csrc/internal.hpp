@@ -47,6 +47,35 @@ struct Error : std::runtime_error {
 
 inline int p2pad_of(int p) { return ((p * p + 15) / 16) * 16; }
 
+// ------------------------------------------------- M2L operator table layout
+// An operator (P2pad x P2pad, RT = P2pad / 16 row tiles, Q = 4 RT input steps
+// per k-group) is stored as NC stages of SCH input steps; a stage holds the 4
+// k-groups one after another, GST elements apart, each group SCH rows of
+// P2pad values in MFMA fragment order:
+//     op[(c 4 + g) GST + ss P2pad + (row % 16) RT + row / 16] = T[row][g Q + c SCH + ss].
+// A stage is contiguous so that four waves copy it straight into LDS, 1 KiB
+// per wave and instruction; with RT odd the groups sit 64 bytes apart so the
+// fragment reads of lanes 0-31 fall in different LDS banks.  SCH is the
+// largest divisor of Q (a multiple of 4, else of 2, when one exists) whose
+// stage fits 16 KiB (32 KiB for float64, whose fragments are half as long).
+__host__ __device__ constexpr int m2l_sch(int RT, int esz)
+{
+    int b4 = 0, b2 = 0, b1 = 1;
+    for (int sc = 1; sc <= 4 * RT; ++sc)
+        if ((4 * RT) % sc == 0 && 4 * sc * 16 * RT * esz <= (esz == 8 ? 32768 : 16384)) {
+            if (sc % 4 == 0) b4 = sc;
+            if (sc % 2 == 0) b2 = sc;
+            b1 = sc;
+        }
+    return b4 ? b4 : (b2 ? b2 : b1);
+}
+__host__ __device__ constexpr int m2l_gst(int RT, int esz) { return m2l_sch(RT, esz) * 16 * RT + ((RT & 1) ? 64 / esz : 0); }
+// elements per operator, and the zero tail a table needs after its last operator
+// (the last stage copy is rounded up to whole 4 KiB block rounds)
+__host__ __device__ constexpr int64_t m2l_opsz(int RT, int esz) { return (int64_t)(4 * RT / m2l_sch(RT, esz)) * 4 * m2l_gst(RT, esz); }
+__host__ __device__ constexpr int m2l_rounds(int RT, int esz) { return (4 * m2l_gst(RT, esz) * esz + 4095) / 4096; }
+__host__ __device__ constexpr int64_t m2l_tail(int RT, int esz) { return (int64_t)m2l_rounds(RT, esz) * 4096 / esz; }
+
 // ---------------------------------------------------------------- memory
 struct Allocator {
     fmm_allocator user{};
@@ -116,12 +145,16 @@ struct fmm_plan {
     // batched same-level M2L
     int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius
     int TW = 64;                     // targets per batched-M2L tile (64, 128 or 256)
-    int KS = 1;                      // stencil chunks per tile (parallel split, reduced in order)
+    int E = 0;                       // stencil entries per chunk
+    int NCH = 0;                     // chunks of the stencil (launched chunk after chunk)
+    int G = 1;                       // chunks per launch (partial sums when > 1)
+    int TPC = 0;                     // tile slots per octant class in the interleaved order
+    int32_t *tile_order = nullptr;   // [8*TPC] tile in slot i (class i % 8) or -1
     int64_t ntile = 0;
     int32_t *tile_tgt = nullptr;     // [ntile*TW] target cell or -1
     int32_t *tile_cls = nullptr;     // [ntile] octant class
     int32_t *slots = nullptr;        // [ntile*K*TW] source cell or -1
-    void *m2l_part = nullptr;        // [KS][ntile*TW][P2pad] partial sums when KS > 1
+    void *m2l_part = nullptr;        // [G][ntile*TW][P2pad] partial sums when G > 1
     int32_t *tile_kl = nullptr;      // [ntile][K] stencil entries with a source, per tile
     int32_t *tile_nk = nullptr;      // [ntile] length of that list
     int32_t *slot_none = nullptr;    // [TW] all -1 (source row of an entry past the list)

@@ -15,6 +15,7 @@
 #include "internal.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace fmm {
 
@@ -55,63 +56,114 @@ template <> struct Vec16<double> {
     static constexpr int n = 2;
 };
 
+// Widest vector of T (16 bytes at most) whose length divides SCH.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f1v __attribute__((ext_vector_type(1)));
+typedef double d1v __attribute__((ext_vector_type(1)));
+template <class T, int SCH> struct BVec;
+template <int SCH> struct BVec<float, SCH> {
+    static constexpr int n = SCH % 4 == 0 ? 4 : (SCH % 2 == 0 ? 2 : 1);
+    typedef typename std::conditional<n == 4, f4v, typename std::conditional<n == 2, f2v, f1v>::type>::type t;
+};
+template <int SCH> struct BVec<double, SCH> {
+    static constexpr int n = SCH % 2 == 0 ? 2 : 1;
+    typedef typename std::conditional<n == 2, d2v, d1v>::type t;
+};
+
 // Column groups of 16 targets per wave: more groups reuse each operator
 // fragment more often but need more accumulator registers.
 __host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (RT <= 4 ? 2 : 1); }
 
-// Input steps of the operator per LDS stage: the largest divisor of Q = 4 RT
-// whose stage (4 groups x steps x P2pad values) fits in 32 KiB.
-__host__ __device__ constexpr int m2l_sch(int RT, int bytes)
-{
-    int best = 1;
-    for (int sc = 1; sc <= 4 * RT; ++sc)
-        if ((4 * RT) % sc == 0 && 4 * sc * 16 * RT * bytes <= 32768) best = sc;
-    return best;
-}
 
-// Batched same-level M2L.  Block = 4 waves = one tile of TW = 64 CG targets of
-// one octant class, restricted to chunk ks = block mod KS of the tile's list
-// of stencil entries that have at least one source (chunks, not tiles, vary
-// fastest across blocks, so blocks resident on one XCD share operators in its
-// L2).  For every listed entry k the block stages the common operator T(t_k)
-// in LDS; each wave multiplies it by its 16 CG gathered source multipoles:
+// Batched same-level M2L.  The stencil of each octant class is cut into
+// chunks of E entries; one launch covers G consecutive chunks for every tile,
+// and launches run chunk after chunk, so at any time the GPU works on a few
+// chunks and their operators stay in L2.  Block b = (chunk c0 + b / ntpos,
+// slot b % ntpos of the class-interleaved tile order): consecutive blocks
+// alternate over the 8 octant classes, so with workgroups dealt round-robin
+// to the 8 XCDs each XCD sees one class and caches only that class's
+// operators.  Block = 4 waves = one tile of TW = 64 CG targets; for every
+// stencil entry k of its chunk that has a source in the tile, the block
+// stages the common operator T(t_k) in LDS and each wave multiplies it by its
+// 16 CG gathered source multipoles:
 //     D[i][j] = sum_k A[i][k] B[k][j] (16x16x4 MFMA), A = operator fragment
 //     (lane l: A[l%16][l/16]), B = multipoles (lane l: B[l/16][l%16]); lane l
 //     accumulates D[acc_row(l/16, e)][l%16] in slot e.
 // The loop body has no divergent branch and never edits loaded data: the
 // next operator stage and the next entry's sources (slot indices two entries
 // ahead) are fetched while the current stage is multiplied; a missing source
-// reads the all-zero multipole row zero_row (= ncell).
-template <class T, int RT, int CG, int SCH>
-__global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__ tile_cls,
+// reads the all-zero multipole row zero_row (= ncell).  With G = 1 a block
+// adds its sums to L (launches are ordered, so the sum order is fixed); with
+// G > 1 it writes partial sums that a reduction adds in chunk order.  The
+// four k-groups of a stage sit 16 words apart in LDS bank order when RT is
+// odd, so the operator reads of lanes 0-31 do not collide.
+typedef __attribute__((address_space(1))) const void gmem_t;
+typedef __attribute__((address_space(3))) void lmem_t;
+
+// Copies one operator stage (4 GST elements, contiguous in the table) into an
+// LDS buffer: each lane moves 16 bytes straight to LDS (lane l of a wave
+// writes at its base + 16 l), ROUNDS rounds of 4 KiB per block.
+template <class T, int RT>
+__device__ __forceinline__ void stage_copy(const T *src, T *dst, int wave, int lane)
+{
+    constexpr int WE = 1024 / (int)sizeof(T);  // elements per wave and round
+    constexpr int ROUNDS = m2l_rounds(RT, (int)sizeof(T));
+#pragma unroll
+    for (int u = 0; u < ROUNDS; ++u) {
+        const int o = (u * 4 + wave) * WE;
+        __builtin_amdgcn_global_load_lds((gmem_t *)(src + o + lane * (16 / (int)sizeof(T))), (lmem_t *)(dst + o), 16,
+                                         0, 0);
+    }
+}
+
+template <class T, int RT, int CG>
+__global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__ tile_order, int ntpos,
+                                                     const int32_t *__restrict__ tile_cls,
                                                      const int32_t *__restrict__ slots,
                                                      const int32_t *__restrict__ tile_kl,
                                                      const int32_t *__restrict__ tile_nk,
-                                                     const int32_t *__restrict__ st_op, int K, int KS,
+                                                     const int32_t *__restrict__ st_op, int K, int E, int c0, int G,
                                                      const int32_t *__restrict__ slot_none, int zero_row,
                                                      const T *__restrict__ Tf, const T *__restrict__ M,
                                                      T *__restrict__ part, const int32_t *__restrict__ tile_tgt,
                                                      T *__restrict__ L, int64_t ntile)
 {
-    constexpr int P2pad = 16 * RT, Q = 4 * RT, NC = Q / SCH, TW = 64 * CG;
-    constexpr int STAGE = 4 * SCH * P2pad;
-    constexpr int VN = Vec16<T>::n;
-    constexpr int NV = STAGE / VN;
-    constexpr int PV = (NV + 255) / 256;
-    typedef typename Vec16<T>::t vec_t;
+    constexpr int ESZ = (int)sizeof(T);
+    constexpr int P2pad = 16 * RT, Q = 4 * RT, TW = 64 * CG;
+    constexpr int SCH = m2l_sch(RT, ESZ), NC = Q / SCH, GST = m2l_gst(RT, ESZ);
+    constexpr int64_t OPSZ = m2l_opsz(RT, ESZ);
+    constexpr int BUF = m2l_rounds(RT, ESZ) * 4096 / ESZ;  // elements per LDS stage buffer
+    constexpr int VB = BVec<T, SCH>::n;                   // vector width of the multipole loads
+    typedef typename BVec<T, SCH>::t bvec_t;
     typedef typename Mfma<T>::acc_t acc_t;
-    __shared__ __align__(16) T lds[STAGE];
+    __shared__ __align__(16) T lds[2 * BUF];
 
     const int64_t b = blockIdx.x;
-    const int ks = (int)(b % KS);
-    const int64_t tile = b / KS;
+    const int gch = (int)(b / ntpos);
+    const int tile = tile_order[b % ntpos];
+    if (tile < 0) return;  // an empty slot of the class-interleaved order (whole block)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
     const int cls = tile_cls[tile];
     const int nk = tile_nk[tile];
-    const int Kc = (nk + KS - 1) / KS;
-    const int i0 = ks * Kc, i1 = min(nk, i0 + Kc);
-    const int32_t *kl = tile_kl + tile * (int64_t)K;
-    const int32_t *sl = slots + tile * (int64_t)K * TW + wave * CG * 16 + j;
+    const int32_t *kl = tile_kl + (int64_t)tile * K;
+    // the tile's listed entries with k in this chunk: [i0, i1) of its sorted list
+    const int klo = (c0 + gch) * E, khi = min(K, klo + E);
+    int lo = 0, hi = nk;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (kl[mid] < klo) lo = mid + 1;
+        else hi = mid;
+    }
+    const int i0 = lo;
+    hi = nk;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (kl[mid] < khi) lo = mid + 1;
+        else hi = mid;
+    }
+    const int i1 = lo;
+    if (G == 1 && i0 == i1) return;  // nothing to add (whole block)
+    const int32_t *sl = slots + (int64_t)tile * K * TW + wave * CG * 16 + j;
     const int32_t *sl_none = slot_none + wave * CG * 16 + j;  // a row of -1
     const int32_t *opk = st_op + (int64_t)cls * K;
 
@@ -122,111 +174,124 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
         for (int r = 0; r < RT; ++r) acc[cg][r] = acc_t{0, 0, 0, 0};
 
     if (i0 < i1) {
-        vec_t treg[PV];
-        // operator stage (entry KK, chunk CC): rows s in [CC SCH, (CC+1) SCH) of the 4 groups
-#define M2L_LOAD_STAGE(KK, CC)                                                                     \
+#define M2L_STAGE(KK, CC, BUFI)                                                                    \
     {                                                                                              \
         int op_ = opk[KK];                                                                         \
         op_ = op_ < 0 ? 0 : op_;                                                                   \
-        _Pragma("unroll") for (int u = 0; u < PV; ++u)                                             \
-        {                                                                                          \
-            const int v = min(tid + 256 * u, NV - 1);                                              \
-            const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);            \
-            treg[u] = *reinterpret_cast<const vec_t *>(Tf + ((int64_t)(op_ * 4 + gg) * Q + (CC) * SCH) * P2pad + rem); \
-        }                                                                                          \
-    }
-#define M2L_STORE_STAGE()                                                                          \
-    {                                                                                              \
-        _Pragma("unroll") for (int u = 0; u < PV; ++u)                                             \
-        {                                                                                          \
-            const int v = tid + 256 * u;                                                           \
-            if (NV % 256 == 0 || v < NV) *reinterpret_cast<vec_t *>(lds + v * VN) = treg[u];        \
-        }                                                                                          \
+        stage_copy<T, RT>(Tf + (int64_t)op_ * OPSZ + (CC) * 4 * GST, lds + (BUFI) * BUF, wave, lane); \
     }
 #define M2L_SLOTS(II, DST)                                                                         \
     {                                                                                              \
         const int32_t *sp_ = (II) < i1 ? sl + (int64_t)kl[II] * TW : sl_none;                      \
         _Pragma("unroll") for (int cg = 0; cg < CG; ++cg) DST[cg] = sp_[cg * 16];                  \
     }
-#define M2L_LOAD_B(SRC, DST)                                                                       \
+        // multipole values of chunk CC for this lane's columns (rows g Q + CC SCH + [0, SCH))
+#define M2L_LOAD_B(SRC, CC, DST)                                                                   \
     {                                                                                              \
         _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                                          \
         {                                                                                          \
             const int sv = SRC[cg];                                                                \
-            const vec_t *mp = reinterpret_cast<const vec_t *>(M + (int64_t)(sv < 0 ? zero_row : sv) * P2pad + g * Q); \
-            _Pragma("unroll") for (int v = 0; v < Q / VN; ++v)                                     \
+            const bvec_t *mp = reinterpret_cast<const bvec_t *>(M + (int64_t)(sv < 0 ? zero_row : sv) * P2pad + g * Q + (CC) * SCH); \
+            _Pragma("unroll") for (int v = 0; v < SCH / VB; ++v)                                   \
             {                                                                                      \
-                const vec_t x = mp[v];                                                             \
-                _Pragma("unroll") for (int w = 0; w < VN; ++w) DST[cg][v * VN + w] = x[w];         \
+                const bvec_t x = mp[v];                                                            \
+                _Pragma("unroll") for (int w = 0; w < VB; ++w) DST[cg][v * VB + w] = x[w];         \
             }                                                                                      \
         }                                                                                          \
     }
-        T bA[CG][Q], bB[CG][Q];
-        int sA[CG], sB[CG];
-        {
-            int s0[CG];
-            M2L_SLOTS(i0, s0);
-            M2L_SLOTS(i0 + 1, sA);
-            M2L_LOAD_STAGE(kl[i0], 0);
-            M2L_LOAD_B(s0, bA);
-            M2L_STORE_STAGE();
-        }
-        // One stencil entry: multiply with BCUR while the next entry's sources
-        // (slot indices SREAD) go to BNEXT and the slot indices two entries
-        // ahead go to SWRITE.  Two entries per trip with swapped roles, so no
-        // loaded register is ever copied; an odd tail runs one entry whose
-        // sources are all missing (it adds exact zeros).
-#define M2L_ENTRY(IT, BCUR, BNEXT, SREAD, SWRITE)                                                  \
+        T bq[2][CG][SCH];
+        int sX[CG], sY[CG];
+        M2L_SLOTS(i0, sX);
+        M2L_SLOTS(i0 + 1, sY);
+        M2L_STAGE(kl[i0], 0, 0);
+        M2L_LOAD_B(sX, 0, bq[0]);
+        // One stencil entry, step by step (a step = one chunk of SCH input
+        // rows).  At the top of a step every wave waits for its own copies and
+        // loads of this step and meets the others at the barrier, after which
+        // the other LDS buffer is free: the next step's operator rows are
+        // copied into it and its multipole values loaded into bq[cur ^ 1]
+        // while this step is multiplied.  After the last chunk the next
+        // entry's first chunk follows (slot indices SN, loaded one entry
+        // ahead).  PAR is the parity of chunk 0.  With NC odd the parity
+        // alternates, so two entries run per trip (every register role fixed
+        // at compile time) and an odd tail runs one entry whose sources are
+        // all missing (exact zeros are added).
+#define M2L_ENTRY(IT, SC, SN, PAR)                                                                 \
     {                                                                                              \
         const int k_ = kl[min(IT, i1 - 1)];                                                        \
         const int kn_ = kl[min((IT) + 1, i1 - 1)];                                                 \
+        bool hv[CG]; /* a column group without any source adds nothing: skip its products */      \
+        _Pragma("unroll") for (int cg = 0; cg < CG; ++cg) hv[cg] = __ballot(SC[cg] >= 0) != 0;     \
         _Pragma("unroll") for (int c = 0; c < NC; ++c)                                             \
         {                                                                                          \
-            if (c + 1 < NC) M2L_LOAD_STAGE(k_, c + 1)                                              \
-            else M2L_LOAD_STAGE(kn_, 0)                                                            \
-            if (c == 0) {                                                                          \
-                M2L_SLOTS((IT) + 2, SWRITE);                                                       \
-                M2L_LOAD_B(SREAD, BNEXT);                                                          \
-            }                                                                                      \
+            const int cur = ((PAR) + c) & 1;                                                       \
+            __builtin_amdgcn_s_waitcnt(0);                                                         \
             __syncthreads();                                                                       \
-            _Pragma("unroll") for (int ss = 0; ss < SCH; ++ss)                                     \
+            if (c + 1 < NC) {                                                                      \
+                M2L_STAGE(k_, c + 1, cur ^ 1);                                                     \
+                M2L_LOAD_B(SC, c + 1, bq[cur ^ 1]);                                                \
+            } else {                                                                               \
+                M2L_STAGE(kn_, 0, cur ^ 1);                                                        \
+                M2L_LOAD_B(SN, 0, bq[cur ^ 1]);                                                    \
+                M2L_SLOTS((IT) + 2, SC);                                                           \
+            }                                                                                      \
+            const T *sbuf = lds + cur * BUF + g * GST + j * RT;                                    \
             {                                                                                      \
-                T a[RT];                                                                           \
-                const T *ap = lds + g * (SCH * P2pad) + ss * P2pad + j * RT;                       \
-                _Pragma("unroll") for (int r = 0; r < RT; ++r) a[r] = ap[r];                       \
-                _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                                  \
-                    _Pragma("unroll") for (int r = 0; r < RT; ++r)                                 \
-                        acc[cg][r] = Mfma<T>::run(a[r], BCUR[cg][c * SCH + ss], acc[cg][r]);       \
+                _Pragma("unroll") for (int ss = 0; ss < SCH; ++ss)                                 \
+                {                                                                                  \
+                    T a[RT];                                                                       \
+                    _Pragma("unroll") for (int r = 0; r < RT; ++r) a[r] = sbuf[ss * P2pad + r];    \
+                    _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                              \
+                        if (CG == 1 || hv[cg]) /* (with one group, skipping costs more than it saves) */ \
+                            _Pragma("unroll") for (int r = 0; r < RT; ++r)                         \
+                                acc[cg][r] = Mfma<T>::run(a[r], bq[cur][cg][ss], acc[cg][r]);      \
+                }                                                                                  \
             }                                                                                      \
-            __syncthreads();                                                                       \
-            M2L_STORE_STAGE();                                                                     \
         }                                                                                          \
     }
-        for (int it = i0; it < i1; it += 2) {
-            M2L_ENTRY(it, bA, bB, sA, sB);
-            M2L_ENTRY(it + 1, bB, bA, sB, sA);
+        if constexpr (NC % 2 == 0) {
+            // every entry starts on buffer 0: one entry per trip, slot roles swapped by copies
+            for (int it = i0; it < i1; ++it) {
+                M2L_ENTRY(it, sX, sY, 0);
+#pragma unroll
+                for (int cg = 0; cg < CG; ++cg) {
+                    const int t_ = sX[cg];
+                    sX[cg] = sY[cg];
+                    sY[cg] = t_;
+                }
+            }
+        } else {
+            for (int it = i0; it < i1; it += 2) {
+                M2L_ENTRY(it, sX, sY, 0);
+                M2L_ENTRY(it + 1, sY, sX, 1);
+            }
         }
 #undef M2L_ENTRY
-#undef M2L_LOAD_STAGE
-#undef M2L_STORE_STAGE
+#undef M2L_STAGE
 #undef M2L_SLOTS
 #undef M2L_LOAD_B
+        // the last prefetch still writes LDS: let it land before the block ends
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
         const int col = wave * CG * 16 + cg * 16 + j;
-        T *dst;
-        if (KS == 1) {
-            const int tgt = tile_tgt[tile * TW + col];
+        if (G == 1) {
+            const int tgt = tile_tgt[(int64_t)tile * TW + col];
             if (tgt < 0) continue;
-            dst = L + (int64_t)tgt * P2pad;
+            T *dst = L + (int64_t)tgt * P2pad;
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] += acc[cg][r][e];
         } else {
-            dst = part + (((int64_t)ks * ntile + tile) * TW + col) * P2pad;
+            T *dst = part + (((int64_t)gch * ntile + tile) * TW + col) * P2pad;
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
         }
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
     }
 }
 
@@ -262,9 +327,9 @@ __global__ __launch_bounds__(256) void k_tile_klist(const uint8_t *kflag, int K,
     if (threadIdx.x == 0) nk[tile] = s_base;
 }
 
-// Sum of the KS partial products of each target, in chunk order.
+// L += the G partial products of each target, in chunk order.
 template <class T>
-__global__ __launch_bounds__(256) void k_m2l_reduce(const T *part, int KS, int64_t ncol, int P2pad,
+__global__ __launch_bounds__(256) void k_m2l_reduce(const T *part, int G, int64_t ncol, int P2pad,
                                                     const int32_t *tile_tgt, T *L)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -273,8 +338,8 @@ __global__ __launch_bounds__(256) void k_m2l_reduce(const T *part, int KS, int64
     if (pos >= ncol) return;
     const int tgt = tile_tgt[pos];
     if (tgt < 0) return;
-    T s = 0;
-    for (int k = 0; k < KS; ++k) s += part[((int64_t)k * ncol + pos) * P2pad + row];
+    T s = L[(int64_t)tgt * P2pad + row];
+    for (int k = 0; k < G; ++k) s += part[((int64_t)k * ncol + pos) * P2pad + row];
     L[(int64_t)tgt * P2pad + row] = s;
 }
 
@@ -557,37 +622,31 @@ __global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const in
 }
 
 // One tile of TW pairs sharing one operator: out[pair] = T(key) M[src(pair)].
-// Block = 4 waves; the operator passes through LDS in NC stages, the next
-// stage loading while the current one is multiplied.
-template <class T, int RT, int CG, int SCH>
+// Block = 4 waves; the operator passes through two LDS stage buffers, the
+// next stage copied while the current one is multiplied.
+template <class T, int RT, int CG>
 __global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t_op,
                                                    const int64_t *__restrict__ t_first,
                                                    const int32_t *__restrict__ t_cnt, const int32_t *__restrict__ src,
                                                    int zero_row, const T *__restrict__ Tf, const T *__restrict__ M,
                                                    T *__restrict__ out, int64_t pos0)
 {
-    constexpr int P2pad = 16 * RT, Q = 4 * RT, NC = Q / SCH;
-    constexpr int STAGE = 4 * SCH * P2pad;
+    constexpr int ESZ = (int)sizeof(T);
+    constexpr int P2pad = 16 * RT, Q = 4 * RT;
+    constexpr int SCH = m2l_sch(RT, ESZ), NC = Q / SCH, GST = m2l_gst(RT, ESZ);
+    constexpr int BUF = m2l_rounds(RT, ESZ) * 4096 / ESZ;
     constexpr int VN = Vec16<T>::n;
-    constexpr int NV = STAGE / VN;
-    constexpr int PV = (NV + 255) / 256;
     typedef typename Vec16<T>::t vec_t;
     typedef typename Mfma<T>::acc_t acc_t;
-    __shared__ __align__(16) T lds[STAGE];
+    __shared__ __align__(16) T lds[2 * BUF];
 
     const int64_t tile = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
     const int cnt = t_cnt[tile];
     const int64_t first = t_first[tile];
-    const T *opb = Tf + (int64_t)t_op[tile] * 4 * Q * P2pad;
+    const T *opb = Tf + (int64_t)t_op[tile] * m2l_opsz(RT, ESZ);
 
-    vec_t treg[PV];
-#pragma unroll
-    for (int u = 0; u < PV; ++u) {
-        const int v = min(tid + 256 * u, NV - 1);
-        const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);
-        treg[u] = *reinterpret_cast<const vec_t *>(opb + (int64_t)gg * Q * P2pad + rem);
-    }
+    stage_copy<T, RT>(opb, lds, wave, lane);
     T bq[CG][Q];
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
@@ -609,27 +668,15 @@ __global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t
 
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (c > 0) __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PV; ++u) {
-            const int v = tid + 256 * u;
-            if (NV % 256 == 0 || v < NV) *reinterpret_cast<vec_t *>(lds + v * VN) = treg[u];
-        }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (c + 1 < NC) {
-#pragma unroll
-            for (int u = 0; u < PV; ++u) {
-                const int v = min(tid + 256 * u, NV - 1);
-                const int e = v * VN, gg = e / (SCH * P2pad), rem = e - gg * (SCH * P2pad);
-                treg[u] = *reinterpret_cast<const vec_t *>(opb + ((int64_t)gg * Q + (c + 1) * SCH) * P2pad + rem);
-            }
-        }
+        if (c + 1 < NC) stage_copy<T, RT>(opb + (c + 1) * 4 * GST, lds + ((c + 1) & 1) * BUF, wave, lane);
+        const T *sbuf = lds + (c & 1) * BUF + g * GST + j * RT;
 #pragma unroll
         for (int ss = 0; ss < SCH; ++ss) {
             T a[RT];
-            const T *ap = lds + g * (SCH * P2pad) + ss * P2pad + j * RT;
 #pragma unroll
-            for (int r = 0; r < RT; ++r) a[r] = ap[r];
+            for (int r = 0; r < RT; ++r) a[r] = sbuf[ss * P2pad + r];
 #pragma unroll
             for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
@@ -685,24 +732,29 @@ __global__ void k_mfma_probe_f64(double *out)
     for (int e = 0; e < 4; ++e) out[l * 4 + e] = acc[e];
 }
 
+// Launches chunk after chunk (G chunks at a time) over every tile.
 template <class T, int RT>
 void launch_batched(fmm_plan *P, hipStream_t s)
 {
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
-    constexpr int SCH = m2l_sch(RT, (int)sizeof(T));
-    const int64_t nb = P->ntile * P->KS;
-    FMM_CHECK(nb * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
     FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
-    k_m2l_batched<T, RT, CG, SCH><<<(unsigned)nb, 256, 0, s>>>(
-        P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->KS, P->slot_none, (int)P->ncell,
-        static_cast<const T *>(P->ops),
-        static_cast<const T *>(P->Mc), static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
-    FMM_HIP(hipGetLastError());
-    if (P->KS > 1) {
-        const int64_t ncol = P->ntile * P->TW;
-        k_m2l_reduce<T><<<grid1(ncol * P->P2pad, 256), 256, 0, s>>>(static_cast<const T *>(P->m2l_part), P->KS, ncol,
-                                                                   P->P2pad, P->tile_tgt, static_cast<T *>(P->Lc));
+    const int ntpos = 8 * P->TPC;
+    for (int c0 = 0; c0 < P->NCH; c0 += P->G) {
+        const int g = std::min(P->G, P->NCH - c0);
+        const int64_t nb = (int64_t)g * ntpos;
+        FMM_CHECK(nb * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
+        k_m2l_batched<T, RT, CG><<<(unsigned)nb, 256, 0, s>>>(
+            P->tile_order, ntpos, P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->E, c0, g,
+            P->slot_none, (int)P->ncell, static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
+            static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
         FMM_HIP(hipGetLastError());
+        if (g > 1) {
+            const int64_t ncol = P->ntile * P->TW;
+            k_m2l_reduce<T><<<grid1(ncol * P->P2pad, 256), 256, 0, s>>>(static_cast<const T *>(P->m2l_part), g, ncol,
+                                                                       P->P2pad, P->tile_tgt,
+                                                                       static_cast<T *>(P->Lc));
+            FMM_HIP(hipGetLastError());
+        }
     }
 }
 
@@ -730,12 +782,11 @@ template <class T, int RT>
 void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 {
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
-    constexpr int SCH = m2l_sch(RT, (int)sizeof(T));
     FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
     const int64_t nt = ch.t1 - ch.t0;
     FMM_CHECK(nt * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
     if (nt > 0) {
-        k_m2l_pairs<T, RT, CG, SCH><<<(unsigned)nt, 256, 0, s>>>(
+        k_m2l_pairs<T, RT, CG><<<(unsigned)nt, 256, 0, s>>>(
             P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, (int)P->ncell,
             static_cast<const T *>(P->xops), static_cast<const T *>(P->Mc), static_cast<T *>(P->xbuf), ch.p0);
         FMM_HIP(hipGetLastError());
@@ -780,11 +831,14 @@ int bits_of(int64_t v)
 
 int m2l_tile_width(int p, bool f64) { return 64 * m2l_cg(p2pad_of(p) / 16, f64); }
 
-// Stencil split: enough blocks to fill the chip (about 8 per compute unit),
-// but at least 8 stencil entries per chunk.
+// Chunking of the stencils and the class-interleaved tile order.  Chunks
+// hold E entries whose operators fit comfortably in one XCD's L2 next to the
+// gathered multipoles; G chunks share a launch when there are too few tiles
+// to fill the chip.
 void m2l_prepare(fmm_plan *P, hipStream_t s)
 {
-    P->KS = 1;
+    P->NCH = 0;
+    P->G = 1;
     if (P->ntile <= 0 || P->K <= 0) return;
     P->tile_kl = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->ntile * P->K));
     P->slot_none = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->TW));
@@ -792,27 +846,43 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     P->tile_nk = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->ntile));
     k_tile_klist<<<(unsigned)P->ntile, 256, 0, s>>>(P->tile_kflag, P->K, P->tile_kl, P->tile_nk);
     FMM_HIP(hipGetLastError());
-    // a power of two (a divisor or multiple of the 8 XCDs), at least 8 entries per chunk
-    int64_t ks = 1;
-    while (ks < 16 && P->ntile * ks < 2048 && P->K / (2 * ks) >= 8) ks *= 2;
-    P->KS = (int)ks;
-    if (P->KS > 1) {
-        const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
-        P->m2l_part = plan_alloc(P, esz * (size_t)P->KS * P->ntile * P->TW * P->P2pad);
-    }
+
+    const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const double opbytes = (double)P->P2pad * P->P2pad * esz;
+    const bool many = P->ntile >= 1024;
+    const double budget = many ? 2.5 * 1048576.0 : 1.0 * 1048576.0;
+    P->E = std::max(8, std::min(P->K, (int)(budget / opbytes)));
+    P->NCH = (P->K + P->E - 1) / P->E;
+    P->G = many ? 1 : (int)std::min<int64_t>(P->NCH, (2048 + P->ntile - 1) / P->ntile);
+    if (P->G > 1)
+        P->m2l_part = plan_alloc(P, esz * (size_t)P->G * P->ntile * P->TW * P->P2pad);
+
+    // class-interleaved order: slot 8 i + c holds the i-th tile of class c
+    std::vector<int32_t> cls(P->ntile);
+    FMM_HIP(hipMemcpyAsync(cls.data(), P->tile_cls, sizeof(int32_t) * P->ntile, hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    std::vector<std::vector<int32_t>> by(8);
+    for (int64_t t = 0; t < P->ntile; ++t) by[cls[t] & 7].push_back((int32_t)t);
+    size_t tpc = 0;
+    for (auto &v : by) tpc = std::max(tpc, v.size());
+    P->TPC = (int)tpc;
+    std::vector<int32_t> order(8 * tpc, -1);
+    for (int c = 0; c < 8; ++c)
+        for (size_t i = 0; i < by[c].size(); ++i) order[8 * i + c] = by[c][i];
+    P->tile_order = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * order.size()));
+    FMM_HIP(hipMemcpyAsync(P->tile_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, s));
+    FMM_HIP(hipStreamSynchronize(s));
 }
 
 void m2l_same(fmm_plan *P, hipStream_t s)
 {
     const bool f64 = P->precision == FMM_PREC_FP64;
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
-    // root (and any cell outside the tiles) starts from zero
-    FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * P->P2pad, s));
+    // every local expansion starts from zero; the chunks add to it
+    FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * P->P2pad * P->ncell, s));
     if (P->ntile > 0 && P->K > 0) {
         if (f64) dispatch_tiles<double>(P, s);
         else dispatch_tiles<float>(P, s);
-    } else {
-        FMM_HIP(hipMemsetAsync(P->Lc, 0, esz * P->P2pad * P->ncell, s));
     }
 }
 
@@ -927,7 +997,10 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     FMM_HIP(hipMemcpyAsync(P->xt_cnt, h_cnt.data(), sizeof(int32_t) * P->nxt, hipMemcpyHostToDevice, s));
     double4 *d_tr = static_cast<double4 *>(al.alloc(sizeof(double4) * nk));
     FMM_HIP(hipMemcpyAsync(d_tr, tr.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, s));
-    P->xops = plan_alloc(P, esz * (size_t)nk * P->P2pad * P->P2pad);
+    const int RTx = P->P2pad / 16;
+    const size_t xn = (size_t)nk * m2l_opsz(RTx, (int)esz) + m2l_tail(RTx, (int)esz);
+    P->xops = plan_alloc(P, esz * xn);
+    FMM_HIP(hipMemsetAsync(P->xops, 0, esz * xn, s));
     make_m2l_ops(P, d_tr, nk, P->xops, s);
     int32_t *d_id_of = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * xc.ncode));
     int32_t *d_chunk_of = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nk));
