@@ -5,7 +5,8 @@
 // in LDS in batches of up to 256, shifted into the target leaf's frame
 // (offsets from leaf centers keep float32 differences accurate to ~1e-7 of
 // the leaf size at any depth).  When the leaf holds few bodies, G lanes share
-// a target and split each batch; a butterfly of wave shuffles sums them.
+// a target and split each batch (G close to 64 / bodies, not only powers of
+// two); a fixed-order tree of wave shuffles sums them.
 // Batches are padded with zero-charge bodies far away so that every lane runs
 // the same unrolled loop with compile-time LDS offsets.  Only the leaf's own
 // bodies can coincide with a target, so only that batch tests r^2 > 0.
@@ -79,6 +80,9 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
                            int64_t k0, int64_t k1, const int32_t *src, const double *ctr, const V4 *ub, T *phi_s,
                            T *E_s)
 {
+    // sources per batch: a multiple of G kUnroll, so a padded batch never
+    // runs past its kStage slots
+    constexpr int SMAX = (kStage / (G * kUnroll)) * (G * kUnroll);
     const int lane = threadIdx.x;
     const int ti = lane / G, sub = lane % G;
     const bool active = ti < cnt;
@@ -97,8 +101,8 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
     };
     const int32_t ab = beg[A], ae = end[A];
     // 1) the leaf's own bodies (may coincide with the target): masked
-    for (int32_t o = ab; o < ae; o += kStage) {
-        const int take = min(kStage, ae - o);
+    for (int32_t o = ab; o < ae; o += SMAX) {
+        const int take = min(SMAX, ae - o);
         const int npad = (take + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
         for (int l = lane; l < npad; l += 64) sb[l] = l < take ? ub[o + l] : far_dummy<T, V4>();
         __syncthreads();
@@ -114,11 +118,11 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
         int32_t o = 0;
         while (k < k1) {
             int staged = 0;
-            while (staged < kStage && k < k1) {
+            while (staged < SMAX && k < k1) {
                 const int b = src[k];
                 if (b == A) { ++k; o = 0; continue; }
                 const int32_t bb = beg[b] + o, be = end[b];
-                const int take = min(min(be - bb, kStage - staged), 64);
+                const int take = min(min(be - bb, SMAX - staged), 64);
                 if (lane < take) {
                     V4 v = ub[bb + lane];
                     v.x += (T)(ctr[3 * b] - cax);
@@ -164,7 +168,7 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
                 const int32_t v = __shfl_up(pre, d, 64);
                 if (lane >= d) pre += v;
             }
-            const int staged = min(__shfl(pre, 63, 64), kStage);
+            const int staged = min(__shfl(pre, 63, 64), SMAX);
             s_incl[lane] = pre;
             s_excl[lane] = pre - sz;
             s_base[lane] = beg[b] + skip;
@@ -228,12 +232,18 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
     if (KAHAN) {
         s.p -= c.p; s.x -= c.x; s.y -= c.y; s.z -= c.z;
     }
+    // sum over the G lanes of a target (lanes ti G + [0, G)): a tree in a
+    // fixed order, sub 0 ends with the total
 #pragma unroll
-    for (int w = G >> 1; w >= 1; w >>= 1) {
-        s.p += __shfl_xor(s.p, w, 64);
-        s.x += __shfl_xor(s.x, w, 64);
-        s.y += __shfl_xor(s.y, w, 64);
-        s.z += __shfl_xor(s.z, w, 64);
+    for (int w = 1; w < G; w <<= 1) {
+        const T op = __shfl_down(s.p, w, 64), ox = __shfl_down(s.x, w, 64);
+        const T oy = __shfl_down(s.y, w, 64), oz = __shfl_down(s.z, w, 64);
+        if (sub % (2 * w) == 0 && sub + w < G) {
+            s.p += op;
+            s.x += ox;
+            s.y += oy;
+            s.z += oz;
+        }
     }
     if (active && sub == 0) {
         const int64_t i = tb + base + ti;
@@ -256,12 +266,18 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     const int64_t k0 = off[A], k1 = off[A + 1];
     for (int base = 0; base < nt; base += 64) {
         const int cnt = min(64, nt - base);
-        // lanes per target: the largest power of two (<= 16) with G * cnt <= 64
-        if (cnt <= 4) leaf_chunk<T, V4, KAHAN, GATHER, 16>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else if (cnt <= 8) leaf_chunk<T, V4, KAHAN, GATHER, 8>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else if (cnt <= 16) leaf_chunk<T, V4, KAHAN, GATHER, 4>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else if (cnt <= 32) leaf_chunk<T, V4, KAHAN, GATHER, 2>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
-        else leaf_chunk<T, V4, KAHAN, GATHER, 1>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s);
+        // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
+#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GATHER, GG>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
+        if (cnt <= 4) P2P_CHUNK(16);
+        else if (cnt <= 5) P2P_CHUNK(12);
+        else if (cnt <= 8) P2P_CHUNK(8);
+        else if (cnt <= 10) P2P_CHUNK(6);
+        else if (cnt <= 12) P2P_CHUNK(5);
+        else if (cnt <= 16) P2P_CHUNK(4);
+        else if (cnt <= 21) P2P_CHUNK(3);
+        else if (cnt <= 32) P2P_CHUNK(2);
+        else P2P_CHUNK(1);
+#undef P2P_CHUNK
     }
 }
 
