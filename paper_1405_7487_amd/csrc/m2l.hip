@@ -954,7 +954,13 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
 
     // tiles of TW pairs per key; chunks of whole keys whose products fit the buffer
     const int TW = P->TW;
-    const int64_t budget = std::max<int64_t>((int64_t)TW, (int64_t)(2ll << 30) / (int64_t)(P->P2pad * esz));
+    // buffer of per-pair products: a quarter of all of them, within [2, 16] GiB
+    // (each chunk's reduction reads and writes every target it touches once)
+    int64_t allpairs = 0;
+    for (int id = 0; id < nk; ++id) allpairs += key_cnt[id];
+    const int64_t pbytes = (int64_t)P->P2pad * (int64_t)esz;
+    const int64_t bbytes = std::min<int64_t>(16ll << 30, std::max<int64_t>(2ll << 30, allpairs * pbytes / 4));
+    const int64_t budget = std::max<int64_t>((int64_t)TW, bbytes / pbytes);
     std::vector<int32_t> h_op, h_cnt, chunk_of(nk);
     std::vector<int64_t> h_first;
     P->xchunks.clear();

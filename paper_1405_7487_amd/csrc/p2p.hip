@@ -75,8 +75,16 @@ __device__ __forceinline__ V4 far_dummy()
     return v;
 }
 
+// LDS of the cooperative gather: per list entry of a batch, its body-count
+// prefix sums, first body and center shift.  Declared once per kernel so that
+// the instantiations for each G share it.
+template <class T> struct GatherLds {
+    int32_t excl[64], incl[64], base[64];
+    T sh[64][3];
+};
+
 template <class T, class V4, bool KAHAN, bool GATHER, int G>
-__device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const int32_t *beg, const int32_t *end,
+__device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base, int cnt, const int32_t *beg, const int32_t *end,
                            int64_t k0, int64_t k1, const int32_t *src, const double *ctr, const V4 *ub, T *phi_s,
                            T *E_s)
 {
@@ -151,8 +159,8 @@ __device__ void leaf_chunk(V4 *sb, int A, int32_t tb, int base, int cnt, const i
         //    that sum.  The loads of batch i+1 are in flight while batch i is
         //    multiplied (two LDS buffers); slots past the batch hold zero-charge
         //    dummies, which also pad the batch for the unrolled loop.
-        __shared__ int32_t s_excl[64], s_incl[64], s_base[64];
-        __shared__ T s_sh[64][3];
+        int32_t *s_excl = gs->excl, *s_incl = gs->incl, *s_base = gs->base;
+        T(*s_sh)[3] = gs->sh;
         int64_t k = k0;
         int32_t o = 0;  // bodies of entry k already consumed
         V4 regs[kStage / 64];
@@ -260,6 +268,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
                                             T *phi_s, T *E_s)
 {
     __shared__ V4 sb[2 * kStage];
+    __shared__ GatherLds<T> gs;
     const int A = leaves[blockIdx.x];
     const int32_t tb = beg[A], te = end[A];
     const int nt = te - tb;
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     for (int base = 0; base < nt; base += 64) {
         const int cnt = min(64, nt - base);
         // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
-#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GATHER, GG>(sb, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
+#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GATHER, GG>(sb, &gs, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
         if (cnt <= 4) P2P_CHUNK(16);
         else if (cnt <= 5) P2P_CHUNK(12);
         else if (cnt <= 8) P2P_CHUNK(8);

@@ -219,14 +219,18 @@ __global__ __launch_bounds__(256) void k_csr_sources(const uint64_t *keys, int64
 }
 
 // Body pairs of one target's list: |A| * sum_B |B| (one thread per cell).
+// |A| * sum over A's P2P sources of |B|, one wave per cell (lists reach
+// thousands of entries in dense regions, so lanes share a list).
 __global__ __launch_bounds__(256) void k_body_pairs(const int64_t *off, const int32_t *src, const int32_t *beg,
                                                     const int32_t *end, int64_t nc, int64_t *out)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (c >= nc) return;
-    int64_t s = 0;
-    for (int64_t k = off[c]; k < off[c + 1]; ++k) s += end[src[k]] - beg[src[k]];
-    out[c] = s * (int64_t)(end[c] - beg[c]);
+    long long s = 0;
+    for (int64_t k = off[c] + lane; k < off[c + 1]; k += 64) s += end[src[k]] - beg[src[k]];
+    for (int w = 32; w >= 1; w >>= 1) s += __shfl_xor(s, w, 64);
+    if (lane == 0) out[c] = (int64_t)s * (int64_t)(end[c] - beg[c]);
 }
 
 // List digests: the sum, mod 2^64, of mix64(target << 32 | source) over the
@@ -377,7 +381,7 @@ static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int6
     if (body_pairs_dev) {
         int64_t *per = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
         int64_t *scn = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
-        k_body_pairs<<<grid1(P->ncell, 256), 256, 0, s>>>(*off, *src, P->c_beg, P->c_end, P->ncell, per);
+        k_body_pairs<<<grid1(P->ncell * 64, 256), 256, 0, s>>>(*off, *src, P->c_beg, P->c_end, P->ncell, per);
         FMM_HIP(hipGetLastError());
         scan_exclusive_i64(per, scn, P->ncell, body_pairs_dev, P->al, s);
         P->al.free(scn);
@@ -392,7 +396,7 @@ int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s)
     int64_t *per = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
     int64_t *scn = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t) * P->ncell));
     int64_t *tot = static_cast<int64_t *>(P->al.alloc(sizeof(int64_t)));
-    k_body_pairs<<<grid1(P->ncell, 256), 256, 0, s>>>(P->p2p_off, P->p2p_src, P->c_beg, P->c_end, P->ncell, per);
+    k_body_pairs<<<grid1(P->ncell * 64, 256), 256, 0, s>>>(P->p2p_off, P->p2p_src, P->c_beg, P->c_end, P->ncell, per);
     FMM_HIP(hipGetLastError());
     scan_exclusive_i64(per, scn, P->ncell, tot, P->al, s);
     int64_t h = 0;
