@@ -32,8 +32,9 @@ KERNEL_SOURCE = {"k_m2l_batched": "m2l.hip", "k_p2p": "p2p.hip"}
 
 
 def recorded_traffic(kernel, config, precision):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when the kernel's source has changed since the counters were taken."""
+    """HBM bytes that `kernel` moves in one evaluation (all its launches), from
+    the committed counter summary, or None when the kernel's source has
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(HERE, "profiles", f"hbm_traffic_{config}.md")
     src = os.path.join(HERE, "paper_1405_7487_amd", "csrc", KERNEL_SOURCE[kernel])
@@ -145,8 +146,10 @@ def main():
     if m2l_ms >= p2p_ms:
         achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
         peak = PEAK["mfma_f32"] if args.precision == "mixed" else PEAK["mfma_f64"]
-        roof = {"kernel": "k_m2l_batched (same-level M2L)", "bound": "mfma", "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        # the phase is the chunk launches of k_m2l_batched (and their ordered
+        # partial-sum reductions) of one evaluation, timed by events on its stream
+        roof = {"kernel": "k_m2l_batched (same-level M2L, all chunk launches of one evaluation)", "bound": "mfma",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": recorded_traffic("k_m2l_batched", args.config, args.precision),
                 "launch_ms": m2l_ms, "flops_per_launch": m2l_flops}
     else:

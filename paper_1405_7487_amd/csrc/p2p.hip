@@ -1,8 +1,9 @@
 // p2p.hip -- particle-to-particle near field on gfx950 (Section II.A: P2P
 // between the leaves that the dual traversal did not accept for M2L).
 //
-// One wave per target leaf.  Source bodies of the leaf's P2P list are staged
-// in LDS in batches of up to 256, shifted into the target leaf's frame
+// One wave per target leaf.  Source bodies of the leaf's P2P list are
+// gathered into LDS in batches of up to 256 bodies drawn from as many list
+// entries as fill a batch, shifted into the target leaf's frame
 // (offsets from leaf centers keep float32 differences accurate to ~1e-7 of
 // the leaf size at any depth).  When the leaf holds few bodies, G lanes share
 // a target and split each batch (G close to 64 / bodies, not only powers of
@@ -83,7 +84,7 @@ template <class T> struct GatherLds {
     T sh[64][3];
 };
 
-template <class T, class V4, bool KAHAN, bool GATHER, int G>
+template <class T, class V4, bool KAHAN, int G>
 __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base, int cnt, const int32_t *beg, const int32_t *end,
                            int64_t k0, int64_t k1, const int32_t *src, const double *ctr, const V4 *ub, T *phi_s,
                            T *E_s)
@@ -119,39 +120,7 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
         fold(pa);
         __syncthreads();
     }
-    if constexpr (!GATHER) {
-        // 2) every other leaf of the list, staged leaf by leaf (lanes load the
-        //    bodies of one source leaf per step; good for well-filled leaves)
-        int64_t k = k0;
-        int32_t o = 0;
-        while (k < k1) {
-            int staged = 0;
-            while (staged < SMAX && k < k1) {
-                const int b = src[k];
-                if (b == A) { ++k; o = 0; continue; }
-                const int32_t bb = beg[b] + o, be = end[b];
-                const int take = min(min(be - bb, SMAX - staged), 64);
-                if (lane < take) {
-                    V4 v = ub[bb + lane];
-                    v.x += (T)(ctr[3 * b] - cax);
-                    v.y += (T)(ctr[3 * b + 1] - cay);
-                    v.z += (T)(ctr[3 * b + 2] - caz);
-                    sb[staged + lane] = v;
-                }
-                staged += take;
-                o += take;
-                if (bb + take == be) { ++k; o = 0; }
-            }
-            if (staged == 0) break;
-            const int npad = (staged + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
-            for (int l = staged + lane; l < npad; l += 64) sb[l] = far_dummy<T, V4>();
-            __syncthreads();
-            Acc<T> pa{0, 0, 0, 0};
-            batch<T, V4, G, false>(sb, npad, sub, u.x, u.y, u.z, pa);
-            fold(pa);
-            __syncthreads();
-        }
-    } else {
+    {
         // 2) every other leaf of the list, batched, no test needed.  A batch is
         //    gathered from the next (up to) 64 list entries at once: lane l takes
         //    entry k + l, a wave prefix sum of the leaf sizes places the bodies,
@@ -262,7 +231,7 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
     }
 }
 
-template <class T, class V4, bool KAHAN, bool GATHER>
+template <class T, class V4, bool KAHAN>
 __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t *beg, const int32_t *end,
                                             const int64_t *off, const int32_t *src, const double *ctr, const V4 *ub,
                                             T *phi_s, T *E_s)
@@ -276,7 +245,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     for (int base = 0; base < nt; base += 64) {
         const int cnt = min(64, nt - base);
         // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
-#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GATHER, GG>(sb, &gs, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
+#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
         if (cnt <= 4) P2P_CHUNK(16);
         else if (cnt <= 5) P2P_CHUNK(12);
         else if (cnt <= 8) P2P_CHUNK(8);
@@ -290,20 +259,19 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     }
 }
 
-template <bool GATHER>
 void launch_p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
     const unsigned nb = (unsigned)P->nleaf;
     if (P->precision == FMM_PREC_FP64)
-        k_p2p<double, double4, false, GATHER><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off,
+        k_p2p<double, double4, false><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off,
                                                                 P->p2p_src, P->c_ctr, static_cast<const double4 *>(ub),
                                                                 static_cast<double *>(phi_s), static_cast<double *>(E_s));
     else if (P->kahan)
-        k_p2p<float, float4, true, GATHER><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
+        k_p2p<float, float4, true><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
                                                              P->c_ctr, static_cast<const float4 *>(ub),
                                                              static_cast<float *>(phi_s), static_cast<float *>(E_s));
     else
-        k_p2p<float, float4, false, GATHER><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
+        k_p2p<float, float4, false><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
                                                               P->c_ctr, static_cast<const float4 *>(ub),
                                                               static_cast<float *>(phi_s), static_cast<float *>(E_s));
     FMM_HIP(hipGetLastError());
@@ -311,13 +279,10 @@ void launch_p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t
 
 }  // namespace
 
-// Staging by leaf when leaves are well filled (mean >= 24 bodies), otherwise
-// the cooperative gather that packs many small leaves per batch.
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
     if (P->nleaf == 0) return;
-    if (P->n >= 24 * P->nleaf) launch_p2p<false>(P, ub, phi_s, E_s, s);
-    else launch_p2p<true>(P, ub, phi_s, E_s, s);
+    launch_p2p(P, ub, phi_s, E_s, s);
 }
 
 }  // namespace fmm
