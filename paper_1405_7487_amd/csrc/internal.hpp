@@ -73,8 +73,14 @@ __host__ __device__ constexpr int m2l_gst(int RT, int esz) { return m2l_sch(RT, 
 // elements per operator, and the zero tail a table needs after its last operator
 // (the last stage copy is rounded up to whole 4 KiB block rounds)
 __host__ __device__ constexpr int64_t m2l_opsz(int RT, int esz) { return (int64_t)(4 * RT / m2l_sch(RT, esz)) * 4 * m2l_gst(RT, esz); }
-__host__ __device__ constexpr int m2l_rounds(int RT, int esz) { return (4 * m2l_gst(RT, esz) * esz + 4095) / 4096; }
-__host__ __device__ constexpr int64_t m2l_tail(int RT, int esz) { return (int64_t)m2l_rounds(RT, esz) * 4096 / esz; }
+// rounds of WV KiB (WV waves copying 1 KiB each) that copy one stage
+__host__ __device__ constexpr int m2l_rounds(int RT, int esz, int WV) { return (4 * m2l_gst(RT, esz) * esz + 1024 * WV - 1) / (1024 * WV); }
+__host__ __device__ constexpr int64_t m2l_tail(int RT, int esz) { return (int64_t)m2l_rounds(RT, esz, 8) * 8192 / esz; }
+// Tiles of the batched M2L: CG column groups of 16 targets per wave, WV waves
+// per block.  Two groups per wave where the accumulators allow (float32,
+// P2pad <= 64), else one; four waves (eight measured slower at P = 10 and 12).
+__host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (RT <= 4 ? 2 : 1); }
+__host__ __device__ constexpr int m2l_wv(int RT, bool f64) { return 4; }
 
 // ---------------------------------------------------------------- memory
 struct Allocator {

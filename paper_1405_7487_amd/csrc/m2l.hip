@@ -72,7 +72,6 @@ template <int SCH> struct BVec<double, SCH> {
 
 // Column groups of 16 targets per wave: more groups reuse each operator
 // fragment more often but need more accumulator registers.
-__host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (RT <= 4 ? 2 : 1); }
 
 
 // Batched same-level M2L.  The stencil of each octant class is cut into
@@ -82,7 +81,7 @@ __host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (R
 // slot b % ntpos of the class-interleaved tile order): consecutive blocks
 // alternate over the 8 octant classes, so with workgroups dealt round-robin
 // to the 8 XCDs each XCD sees one class and caches only that class's
-// operators.  Block = 4 waves = one tile of TW = 64 CG targets; for every
+// operators.  Block = WV waves = one tile of TW = 16 CG WV targets; for every
 // stencil entry k of its chunk that has a source in the tile, the block
 // stages the common operator T(t_k) in LDS and each wave multiplies it by its
 // 16 CG gathered source multipoles:
@@ -102,22 +101,22 @@ typedef __attribute__((address_space(3))) void lmem_t;
 
 // Copies one operator stage (4 GST elements, contiguous in the table) into an
 // LDS buffer: each lane moves 16 bytes straight to LDS (lane l of a wave
-// writes at its base + 16 l), ROUNDS rounds of 4 KiB per block.
-template <class T, int RT>
+// writes at its base + 16 l), ROUNDS rounds of WV KiB per block.
+template <class T, int RT, int WV>
 __device__ __forceinline__ void stage_copy(const T *src, T *dst, int wave, int lane)
 {
     constexpr int WE = 1024 / (int)sizeof(T);  // elements per wave and round
-    constexpr int ROUNDS = m2l_rounds(RT, (int)sizeof(T));
+    constexpr int ROUNDS = m2l_rounds(RT, (int)sizeof(T), WV);
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
-        const int o = (u * 4 + wave) * WE;
+        const int o = (u * WV + wave) * WE;
         __builtin_amdgcn_global_load_lds((gmem_t *)(src + o + lane * (16 / (int)sizeof(T))), (lmem_t *)(dst + o), 16,
                                          0, 0);
     }
 }
 
-template <class T, int RT, int CG>
-__global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__ tile_order, int ntpos,
+template <class T, int RT, int CG, int WV>
+__global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restrict__ tile_order, int ntpos,
                                                      const int32_t *__restrict__ tile_cls,
                                                      const int32_t *__restrict__ slots,
                                                      const int32_t *__restrict__ tile_kl,
@@ -129,10 +128,10 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
                                                      T *__restrict__ L, int64_t ntile)
 {
     constexpr int ESZ = (int)sizeof(T);
-    constexpr int P2pad = 16 * RT, Q = 4 * RT, TW = 64 * CG;
+    constexpr int P2pad = 16 * RT, Q = 4 * RT, TW = 16 * CG * WV;
     constexpr int SCH = m2l_sch(RT, ESZ), NC = Q / SCH, GST = m2l_gst(RT, ESZ);
     constexpr int64_t OPSZ = m2l_opsz(RT, ESZ);
-    constexpr int BUF = m2l_rounds(RT, ESZ) * 4096 / ESZ;  // elements per LDS stage buffer
+    constexpr int BUF = m2l_rounds(RT, ESZ, WV) * 1024 * WV / ESZ;  // elements per LDS stage buffer
     constexpr int VB = BVec<T, SCH>::n;                   // vector width of the multipole loads
     typedef typename BVec<T, SCH>::t bvec_t;
     typedef typename Mfma<T>::acc_t acc_t;
@@ -178,7 +177,7 @@ __global__ __launch_bounds__(256) void k_m2l_batched(const int32_t *__restrict__
     {                                                                                              \
         int op_ = opk[KK];                                                                         \
         op_ = op_ < 0 ? 0 : op_;                                                                   \
-        stage_copy<T, RT>(Tf + (int64_t)op_ * OPSZ + (CC) * 4 * GST, lds + (BUFI) * BUF, wave, lane); \
+        stage_copy<T, RT, WV>(Tf + (int64_t)op_ * OPSZ + (CC) * 4 * GST, lds + (BUFI) * BUF, wave, lane); \
     }
 #define M2L_SLOTS(II, DST)                                                                         \
     {                                                                                              \
@@ -622,10 +621,10 @@ __global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const in
 }
 
 // One tile of TW pairs sharing one operator: out[pair] = T(key) M[src(pair)].
-// Block = 4 waves; the operator passes through two LDS stage buffers, the
+// Block = WV waves; the operator passes through two LDS stage buffers, the
 // next stage copied while the current one is multiplied.
-template <class T, int RT, int CG>
-__global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t_op,
+template <class T, int RT, int CG, int WV>
+__global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict__ t_op,
                                                    const int64_t *__restrict__ t_first,
                                                    const int32_t *__restrict__ t_cnt, const int32_t *__restrict__ src,
                                                    int zero_row, const T *__restrict__ Tf, const T *__restrict__ M,
@@ -634,7 +633,7 @@ __global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t
     constexpr int ESZ = (int)sizeof(T);
     constexpr int P2pad = 16 * RT, Q = 4 * RT;
     constexpr int SCH = m2l_sch(RT, ESZ), NC = Q / SCH, GST = m2l_gst(RT, ESZ);
-    constexpr int BUF = m2l_rounds(RT, ESZ) * 4096 / ESZ;
+    constexpr int BUF = m2l_rounds(RT, ESZ, WV) * 1024 * WV / ESZ;
     constexpr int VN = Vec16<T>::n;
     typedef typename Vec16<T>::t vec_t;
     typedef typename Mfma<T>::acc_t acc_t;
@@ -646,7 +645,7 @@ __global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t
     const int64_t first = t_first[tile];
     const T *opb = Tf + (int64_t)t_op[tile] * m2l_opsz(RT, ESZ);
 
-    stage_copy<T, RT>(opb, lds, wave, lane);
+    stage_copy<T, RT, WV>(opb, lds, wave, lane);
     T bq[CG][Q];
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
@@ -670,7 +669,7 @@ __global__ __launch_bounds__(256) void k_m2l_pairs(const int32_t *__restrict__ t
     for (int c = 0; c < NC; ++c) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (c + 1 < NC) stage_copy<T, RT>(opb + (c + 1) * 4 * GST, lds + ((c + 1) & 1) * BUF, wave, lane);
+        if (c + 1 < NC) stage_copy<T, RT, WV>(opb + (c + 1) * 4 * GST, lds + ((c + 1) & 1) * BUF, wave, lane);
         const T *sbuf = lds + (c & 1) * BUF + g * GST + j * RT;
 #pragma unroll
         for (int ss = 0; ss < SCH; ++ss) {
@@ -736,14 +735,14 @@ __global__ void k_mfma_probe_f64(double *out)
 template <class T, int RT>
 void launch_batched(fmm_plan *P, hipStream_t s)
 {
-    constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
-    FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
+    constexpr int CG = m2l_cg(RT, sizeof(T) == 8), WV = m2l_wv(RT, sizeof(T) == 8);
+    FMM_CHECK(P->TW == 16 * CG * WV, FMM_ERR_DEVICE, "m2l: tile width mismatch");
     const int ntpos = 8 * P->TPC;
     for (int c0 = 0; c0 < P->NCH; c0 += P->G) {
         const int g = std::min(P->G, P->NCH - c0);
         const int64_t nb = (int64_t)g * ntpos;
-        FMM_CHECK(nb * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
-        k_m2l_batched<T, RT, CG><<<(unsigned)nb, 256, 0, s>>>(
+        FMM_CHECK(nb * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
+        k_m2l_batched<T, RT, CG, WV><<<(unsigned)nb, 64 * WV, 0, s>>>(
             P->tile_order, ntpos, P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->E, c0, g,
             P->slot_none, (int)P->ncell, static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
             static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
@@ -781,12 +780,12 @@ void dispatch_tiles(fmm_plan *P, hipStream_t s)
 template <class T, int RT>
 void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 {
-    constexpr int CG = m2l_cg(RT, sizeof(T) == 8);
-    FMM_CHECK(P->TW == 64 * CG, FMM_ERR_DEVICE, "m2l: tile width mismatch");
+    constexpr int CG = m2l_cg(RT, sizeof(T) == 8), WV = m2l_wv(RT, sizeof(T) == 8);
+    FMM_CHECK(P->TW == 16 * CG * WV, FMM_ERR_DEVICE, "m2l: tile width mismatch");
     const int64_t nt = ch.t1 - ch.t0;
-    FMM_CHECK(nt * 256 < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
+    FMM_CHECK(nt * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
     if (nt > 0) {
-        k_m2l_pairs<T, RT, CG><<<(unsigned)nt, 256, 0, s>>>(
+        k_m2l_pairs<T, RT, CG, WV><<<(unsigned)nt, 64 * WV, 0, s>>>(
             P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, (int)P->ncell,
             static_cast<const T *>(P->xops), static_cast<const T *>(P->Mc), static_cast<T *>(P->xbuf), ch.p0);
         FMM_HIP(hipGetLastError());
@@ -829,7 +828,11 @@ int bits_of(int64_t v)
 
 }  // namespace
 
-int m2l_tile_width(int p, bool f64) { return 64 * m2l_cg(p2pad_of(p) / 16, f64); }
+int m2l_tile_width(int p, bool f64)
+{
+    const int RT = p2pad_of(p) / 16;
+    return 16 * m2l_cg(RT, f64) * m2l_wv(RT, f64);
+}
 
 // Chunking of the stencils and the class-interleaved tile order.  Chunks
 // hold E entries whose operators fit comfortably in one XCD's L2 next to the
