@@ -242,8 +242,12 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     const int32_t tb = beg[A], te = end[A];
     const int nt = te - tb;
     const int64_t k0 = off[A], k1 = off[A + 1];
-    for (int base = 0; base < nt; base += 64) {
-        const int cnt = min(64, nt - base);
+    // chunks of at most 64 targets; a leaf of 33-55 bodies runs as 32 (two
+    // lanes each) plus the rest, which keeps more lanes busy than 64-wide
+    // chunks with most lanes idle, at the price of a second pass over the list
+    for (int base = 0, cnt = 0; base < nt; base += cnt) {
+        const int rem = nt - base;
+        cnt = (rem > 32 && rem < 56) ? 32 : min(64, rem);
         // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
 #define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
         if (cnt <= 4) P2P_CHUNK(16);
