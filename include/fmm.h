@@ -118,6 +118,7 @@ typedef struct {
     double ms_m2l_cross;     /* cross-level M2L (ms_m2l: same-level, batched) */
     int64_t m2l_cross_keys;     /* cross-level (level difference, offset) keys with an operator */
     int64_t m2l_cross_batched;  /* cross-level pairs run as shared-operator products */
+    int64_t p2p_cut_leaves;     /* leaves whose P2P list is split over several work items */
 } fmm_stats;
 
 /* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are

@@ -57,7 +57,8 @@ class _Stats(C.Structure):
                 ("ms_p2m", C.c_double), ("ms_m2m", C.c_double), ("ms_m2l", C.c_double), ("ms_l2l", C.c_double),
                 ("ms_l2p", C.c_double), ("ms_p2p", C.c_double), ("ms_evaluate", C.c_double),
                 ("ms_adjoint", C.c_double), ("ms_m2l_cross", C.c_double),
-                ("m2l_cross_keys", C.c_int64), ("m2l_cross_batched", C.c_int64)]
+                ("m2l_cross_keys", C.c_int64), ("m2l_cross_batched", C.c_int64),
+                ("p2p_cut_leaves", C.c_int64)]
 
 
 class _Export(C.Structure):

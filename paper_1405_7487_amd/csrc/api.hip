@@ -380,6 +380,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         make_operators(P, s);
         m2l_prepare(P, s);
         m2l_cross_prepare(P, s);
+        p2p_prepare(P, s);
         FMM_HIP(hipStreamSynchronize(s));
         P->st.ms_ops = ms_since(t2a);
         const bool f64 = P->precision == FMM_PREC_FP64;
@@ -575,6 +576,7 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
     st.m2l_slots = P->ntile * (int64_t)P->K * P->TW;
     st.m2l_cross_keys = P->nxk;
     st.m2l_cross_batched = P->nxb;
+    st.p2p_cut_leaves = P->p2p_ncut;
     st.device_bytes = P->bytes_held;
     {
         std::lock_guard<std::mutex> lk(g_ev_mu);

@@ -147,6 +147,14 @@ struct fmm_plan {
     // lists
     int64_t n_m2l_same = 0, n_m2l_cross = 0, n_p2p = 0, p2p_body_pairs = 0;
     int64_t *p2p_off = nullptr;  int32_t *p2p_src = nullptr;   // CSR over cells
+    // P2P work items: (leaf, list range, output); long lists are cut into items
+    int64_t p2p_nitem = 0, p2p_ncut = 0, p2p_npart = 0;
+    int32_t *p2p_it_leaf = nullptr;
+    int64_t *p2p_it_k0 = nullptr, *p2p_it_k1 = nullptr;
+    int64_t *p2p_it_out = nullptr;   // >= 0: first body index; < 0: -(partial slot) - 1
+    int32_t *p2p_cl_leaf = nullptr, *p2p_cl_n = nullptr;   // cut leaves, their item counts
+    int64_t *p2p_cl_part = nullptr;  // first partial slot of each cut leaf
+    void *p2p_part = nullptr;        // [4 npart] partial phi, then partial E (3 per slot)
     int64_t *m2lx_off = nullptr; int32_t *m2lx_src = nullptr;  // cross-level M2L
     // batched same-level M2L
     int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius
@@ -235,6 +243,7 @@ void m2l_cross(fmm_plan *P, hipStream_t s);
 void m2l_cross_prepare(fmm_plan *P, hipStream_t s);
 // p2p.hip
 void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
+void p2p_prepare(fmm_plan *P, hipStream_t s);
 // api.hip helpers
 void gather_bodies(fmm_plan *P, const void *q, void *ub, hipStream_t s);
 

@@ -20,6 +20,7 @@ namespace fmm {
 namespace {
 
 constexpr int kStage = 256;
+constexpr int64_t kItemEntries = 4096;  // list entries per P2P work item of a cut leaf
 constexpr int kUnroll = 4;
 
 template <class T> __device__ __forceinline__ T rsqrt_t(T x);
@@ -84,10 +85,13 @@ template <class T> struct GatherLds {
     T sh[64][3];
 };
 
+// Targets [base, base + cnt) of leaf A against list entries [k0, k1) (and
+// the leaf's own bodies when own is set); sums go to op[oi], oE[3 oi + d]
+// with oi = o0 + target.
 template <class T, class V4, bool KAHAN, int G>
-__device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base, int cnt, const int32_t *beg, const int32_t *end,
-                           int64_t k0, int64_t k1, const int32_t *src, const double *ctr, const V4 *ub, T *phi_s,
-                           T *E_s)
+__device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base, int cnt, bool own,
+                           const int32_t *beg, const int32_t *end, int64_t k0, int64_t k1, const int32_t *src,
+                           const double *ctr, const V4 *ub, T *op, T *oE, int64_t o0)
 {
     // sources per batch: a multiple of G kUnroll, so a padded batch never
     // runs past its kStage slots
@@ -108,7 +112,7 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
             s.p += pa.p; s.x += pa.x; s.y += pa.y; s.z += pa.z;
         }
     };
-    const int32_t ab = beg[A], ae = end[A];
+    const int32_t ab = beg[A], ae = own ? end[A] : beg[A];
     // 1) the leaf's own bodies (may coincide with the target): masked
     for (int32_t o = ab; o < ae; o += SMAX) {
         const int take = min(SMAX, ae - o);
@@ -213,35 +217,49 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
     // fixed order, sub 0 ends with the total
 #pragma unroll
     for (int w = 1; w < G; w <<= 1) {
-        const T op = __shfl_down(s.p, w, 64), ox = __shfl_down(s.x, w, 64);
-        const T oy = __shfl_down(s.y, w, 64), oz = __shfl_down(s.z, w, 64);
+        const T rp = __shfl_down(s.p, w, 64), rx = __shfl_down(s.x, w, 64);
+        const T ry = __shfl_down(s.y, w, 64), rz = __shfl_down(s.z, w, 64);
         if (sub % (2 * w) == 0 && sub + w < G) {
-            s.p += op;
-            s.x += ox;
-            s.y += oy;
-            s.z += oz;
+            s.p += rp;
+            s.x += rx;
+            s.y += ry;
+            s.z += rz;
         }
     }
     if (active && sub == 0) {
-        const int64_t i = tb + base + ti;
-        phi_s[i] = s.p;
-        E_s[3 * i] = s.x;
-        E_s[3 * i + 1] = s.y;
-        E_s[3 * i + 2] = s.z;
+        const int64_t i = o0 + base + ti;
+        op[i] = s.p;
+        oE[3 * i] = s.x;
+        oE[3 * i + 1] = s.y;
+        oE[3 * i + 2] = s.z;
     }
 }
 
+// One wave per work item: a target leaf and a range of its list.  Leaves
+// whose list is longer than kItemEntries are cut into consecutive items (only
+// the first also runs the leaf's own bodies); their partial sums go to a
+// buffer and k_p2p_reduce adds them in item order.  Without the cut, a coarse leaf
+// whose list reaches every body of the tree keeps one wave busy long after
+// the rest of the chip has finished.
 template <class T, class V4, bool KAHAN>
-__global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t *beg, const int32_t *end,
-                                            const int64_t *off, const int32_t *src, const double *ctr, const V4 *ub,
-                                            T *phi_s, T *E_s)
+__global__ __launch_bounds__(64) void k_p2p(const int32_t *it_leaf, const int64_t *it_k0, const int64_t *it_k1,
+                                            const int64_t *it_out, const int32_t *beg, const int32_t *end,
+                                            const int32_t *src, const double *ctr, const V4 *ub, T *phi_s, T *E_s,
+                                            T *part_p, T *part_E)
 {
     __shared__ V4 sb[2 * kStage];
     __shared__ GatherLds<T> gs;
-    const int A = leaves[blockIdx.x];
+    const int64_t item = blockIdx.x;
+    const int A = it_leaf[item];
     const int32_t tb = beg[A], te = end[A];
     const int nt = te - tb;
-    const int64_t k0 = off[A], k1 = off[A + 1];
+    const int64_t k0 = it_k0[item], k1 = it_k1[item], ov = it_out[item];
+    // ov >= 0: write to phi_s / E_s at body ov + t; ov < 0: partial sums at -ov - 1 + t
+    const bool direct = ov >= 0;
+    T *op = direct ? phi_s : part_p;
+    T *oE = direct ? E_s : part_E;
+    const int64_t o0 = direct ? ov : -ov - 1;
+    const bool first = direct || item == 0 || it_leaf[item - 1] != A;  // the leaf's first item
     // chunks of at most 64 targets; a leaf of 33-55 bodies runs as 32 (two
     // lanes each) plus the rest, which keeps more lanes busy than 64-wide
     // chunks with most lanes idle, at the price of a second pass over the list
@@ -249,7 +267,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
         const int rem = nt - base;
         cnt = (rem > 32 && rem < 56) ? 32 : min(64, rem);
         // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
-#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, beg, end, k0, k1, src, ctr, ub, phi_s, E_s)
+#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, first, beg, end, k0, k1, src, ctr, ub, op, oE, o0)
         if (cnt <= 4) P2P_CHUNK(16);
         else if (cnt <= 5) P2P_CHUNK(12);
         else if (cnt <= 8) P2P_CHUNK(8);
@@ -263,22 +281,108 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *leaves, const int32_t
     }
 }
 
+// phi / E of the bodies of a cut leaf: the items' partial sums in item order,
+// added in float64.  One block per cut leaf.
+template <class T>
+__global__ __launch_bounds__(64) void k_p2p_reduce(const int32_t *cl_leaf, const int64_t *cl_part, const int32_t *cl_n,
+                                                   const int32_t *beg, const int32_t *end, const T *part_p,
+                                                   const T *part_E, T *phi_s, T *E_s)
+{
+    const int64_t l = blockIdx.x;
+    const int A = cl_leaf[l];
+    const int32_t tb = beg[A], nt = end[A] - beg[A];
+    const int64_t p0 = cl_part[l];
+    const int nch = cl_n[l];
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        double p = 0, x = 0, y = 0, z = 0;
+        for (int c = 0; c < nch; ++c) {
+            const int64_t i = p0 + (int64_t)c * nt + t;
+            p += (double)part_p[i];
+            x += (double)part_E[3 * i];
+            y += (double)part_E[3 * i + 1];
+            z += (double)part_E[3 * i + 2];
+        }
+        const int64_t o = tb + t;
+        phi_s[o] = (T)p;
+        E_s[3 * o] = (T)x;
+        E_s[3 * o + 1] = (T)y;
+        E_s[3 * o + 2] = (T)z;
+    }
+}
+
+__device__ __forceinline__ int64_t item_count(int64_t entries) { return max((int64_t)1, (entries + kItemEntries - 1) / kItemEntries); }
+
+// per leaf (index i < nl): items, partial slots (cut leaves) and cut flag; 0 at i = nl
+__global__ __launch_bounds__(256) void k_items_count(const int32_t *leaves, int64_t nl, const int64_t *off,
+                                                     const int32_t *beg, const int32_t *end, int32_t *ni,
+                                                     int32_t *np, int32_t *nc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nl) return;
+    if (i == nl) {
+        ni[i] = np[i] = nc[i] = 0;
+        return;
+    }
+    const int A = leaves[i];
+    const int64_t nch = item_count(off[A + 1] - off[A]);
+    ni[i] = (int32_t)nch;
+    np[i] = nch > 1 ? (int32_t)(nch * (end[A] - beg[A])) : 0;
+    nc[i] = nch > 1 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_items_fill(const int32_t *leaves, int64_t nl, const int64_t *off,
+                                                    const int32_t *beg, const int32_t *end, const int64_t *si,
+                                                    const int64_t *sp, const int64_t *scut, int32_t *it_leaf,
+                                                    int64_t *it_k0, int64_t *it_k1, int64_t *it_out,
+                                                    int32_t *cl_leaf, int64_t *cl_part, int32_t *cl_n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int A = leaves[i];
+    const int64_t k0 = off[A], k1 = off[A + 1], nch = item_count(k1 - k0);
+    const int64_t o = si[i];
+    if (nch == 1) {
+        it_leaf[o] = A;
+        it_k0[o] = k0;
+        it_k1[o] = k1;
+        it_out[o] = beg[A];
+        return;
+    }
+    const int nt = end[A] - beg[A];
+    const int64_t part = sp[i], c0 = scut[i];
+    cl_leaf[c0] = A;
+    cl_part[c0] = part;
+    cl_n[c0] = (int32_t)nch;
+    for (int64_t c = 0; c < nch; ++c) {
+        it_leaf[o + c] = A;
+        it_k0[o + c] = k0 + c * kItemEntries;
+        it_k1[o + c] = min(k1, k0 + (c + 1) * kItemEntries);
+        it_out[o + c] = -(part + c * nt) - 1;
+    }
+}
+
+template <class T, class V4, bool KAHAN>
+void launch_items(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
+{
+    FMM_CHECK(P->p2p_nitem * 64 < (1ll << 32), FMM_ERR_UNSUPPORTED, "p2p: too many work items");
+    k_p2p<T, V4, KAHAN><<<(unsigned)P->p2p_nitem, 64, 0, s>>>(
+        P->p2p_it_leaf, P->p2p_it_k0, P->p2p_it_k1, P->p2p_it_out, P->c_beg, P->c_end, P->p2p_src, P->c_ctr,
+        static_cast<const V4 *>(ub), static_cast<T *>(phi_s), static_cast<T *>(E_s),
+        static_cast<T *>(P->p2p_part), static_cast<T *>(P->p2p_part) + P->p2p_npart);
+    FMM_HIP(hipGetLastError());
+    if (P->p2p_ncut > 0) {
+        k_p2p_reduce<T><<<(unsigned)P->p2p_ncut, 64, 0, s>>>(
+            P->p2p_cl_leaf, P->p2p_cl_part, P->p2p_cl_n, P->c_beg, P->c_end, static_cast<const T *>(P->p2p_part),
+            static_cast<const T *>(P->p2p_part) + P->p2p_npart, static_cast<T *>(phi_s), static_cast<T *>(E_s));
+        FMM_HIP(hipGetLastError());
+    }
+}
+
 void launch_p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
-    const unsigned nb = (unsigned)P->nleaf;
-    if (P->precision == FMM_PREC_FP64)
-        k_p2p<double, double4, false><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off,
-                                                                P->p2p_src, P->c_ctr, static_cast<const double4 *>(ub),
-                                                                static_cast<double *>(phi_s), static_cast<double *>(E_s));
-    else if (P->kahan)
-        k_p2p<float, float4, true><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
-                                                             P->c_ctr, static_cast<const float4 *>(ub),
-                                                             static_cast<float *>(phi_s), static_cast<float *>(E_s));
-    else
-        k_p2p<float, float4, false><<<nb, 64, 0, s>>>(P->leaves, P->c_beg, P->c_end, P->p2p_off, P->p2p_src,
-                                                              P->c_ctr, static_cast<const float4 *>(ub),
-                                                              static_cast<float *>(phi_s), static_cast<float *>(E_s));
-    FMM_HIP(hipGetLastError());
+    if (P->precision == FMM_PREC_FP64) launch_items<double, double4, false>(P, ub, phi_s, E_s, s);
+    else if (P->kahan) launch_items<float, float4, true>(P, ub, phi_s, E_s, s);
+    else launch_items<float, float4, false>(P, ub, phi_s, E_s, s);
 }
 
 }  // namespace
@@ -287,6 +391,51 @@ void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
     if (P->nleaf == 0) return;
     launch_p2p(P, ub, phi_s, E_s, s);
+}
+
+// Work items of the P2P kernel: one per leaf, or one per kItemEntries list
+// entries for leaves with longer lists, with their partial-sum slots; built
+// on the device by two scans in leaf order.
+void p2p_prepare(fmm_plan *P, hipStream_t s)
+{
+    const int64_t nl = P->nleaf;
+    P->p2p_nitem = 0;
+    P->p2p_ncut = 0;
+    P->p2p_npart = 0;
+    if (nl == 0) return;
+    Allocator &al = P->al;
+    int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 3 * (nl + 1)));
+    int64_t *sc = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3 * (nl + 1)));
+    int64_t *tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3));
+    k_items_count<<<grid1(nl + 1, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->c_beg, P->c_end, cnt,
+                                                      cnt + (nl + 1), cnt + 2 * (nl + 1));
+    FMM_HIP(hipGetLastError());
+    for (int j = 0; j < 3; ++j)
+        scan_exclusive_i32to64(cnt + j * (nl + 1), sc + j * (nl + 1), nl + 1, tot + j, al, s);
+    int64_t h[3];
+    FMM_HIP(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    P->p2p_nitem = h[0];
+    P->p2p_npart = h[1];
+    P->p2p_ncut = h[2];
+    P->p2p_it_leaf = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * h[0]));
+    P->p2p_it_k0 = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * h[0]));
+    P->p2p_it_k1 = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * h[0]));
+    P->p2p_it_out = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * h[0]));
+    if (h[2] > 0) {
+        const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
+        P->p2p_part = plan_alloc(P, esz * 4 * h[1]);
+        P->p2p_cl_leaf = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * h[2]));
+        P->p2p_cl_part = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * h[2]));
+        P->p2p_cl_n = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * h[2]));
+    }
+    k_items_fill<<<grid1(nl, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->c_beg, P->c_end, sc, sc + (nl + 1),
+                                               sc + 2 * (nl + 1), P->p2p_it_leaf, P->p2p_it_k0, P->p2p_it_k1,
+                                               P->p2p_it_out, P->p2p_cl_leaf, P->p2p_cl_part, P->p2p_cl_n);
+    FMM_HIP(hipGetLastError());
+    al.free(tot);
+    al.free(sc);
+    al.free(cnt);
 }
 
 }  // namespace fmm

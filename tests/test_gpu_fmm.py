@@ -138,6 +138,24 @@ def test_cross_level_pairs_plummer(p, n, ncrit, theta):
         assert rel(ph, po) < tol and rel(Eh, Eo) < tol, (precision, rel(ph, po), rel(Eh, Eo))
 
 
+def test_p2p_long_lists_split_over_work_items():
+    # small leaves and a tight acceptance criterion: coarse halo leaves of a
+    # Plummer tree carry P2P lists of (nearly) every leaf, which are cut into
+    # several work items whose partial sums are reduced in order
+    x, _, _ = W.plummer(50000, 21)
+    q = np.random.default_rng(22).uniform(0.0, 1.0, 50000)
+    T = oracle.Tree(x, 6, 0.3)
+    po, Eo = T.fmm(q, 3)
+    outs = []
+    for precision, tol in (("fp64", 1e-11), ("mixed", 1e-4)):
+        plan, ph, Eh = gpu_fmm(x, q, 3, 0.3, 6, precision)
+        assert plan.stats()["p2p_cut_leaves"] > 0
+        assert rel(ph, po) < tol and rel(Eh, Eo) < tol, (precision, rel(ph, po), rel(Eh, Eo))
+        outs.append((ph, Eh))
+    plan, ph, Eh = gpu_fmm(x, q, 3, 0.3, 6, "mixed")
+    assert ph.tobytes() == outs[1][0].tobytes() and Eh.tobytes() == outs[1][1].tobytes()
+
+
 def test_coarse_fp64_levels_variants():
     x, _, _ = W.plummer(20000, 4)
     q = np.random.default_rng(1).uniform(-1, 1, 20000)
