@@ -853,10 +853,10 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
     const double opbytes = (double)P->P2pad * P->P2pad * esz;
     const bool many = P->ntile >= 1024;
-    const double budget = many ? 2.5 * 1048576.0 : 1.0 * 1048576.0;
+    const double budget = many ? 2.5 * 1048576.0 : 2.0 * 1048576.0;
     P->E = std::max(8, std::min(P->K, (int)(budget / opbytes)));
     P->NCH = (P->K + P->E - 1) / P->E;
-    P->G = many ? 1 : (int)std::min<int64_t>(P->NCH, (2048 + P->ntile - 1) / P->ntile);
+    P->G = many ? 1 : (int)std::min<int64_t>(P->NCH, (8192 + P->ntile - 1) / P->ntile);
     if (P->G > 1)
         P->m2l_part = plan_alloc(P, esz * (size_t)P->G * P->ntile * P->TW * P->P2pad);
 
