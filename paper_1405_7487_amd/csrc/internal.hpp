@@ -187,8 +187,8 @@ struct fmm_plan {
     int64_t *xt_first = nullptr;     // [nxt] position of its first pair
     int32_t *xt_cnt = nullptr;       // [nxt] pairs in the tile
     int32_t *xp_src = nullptr;       // [nxb] source cell of each batched pair
-    int32_t *xr_pos = nullptr;       // [nxb] pair positions in (chunk, target, key) order
-    int64_t *xs_off = nullptr;       // [nseg + 1] segment starts in xr_pos (one target of one chunk)
+    int32_t *xr_inv = nullptr;       // [nxb] position of each pair in (chunk, target, key) order
+    int64_t *xs_off = nullptr;       // [nseg + 1] segment starts in that order (one target of one chunk)
     int32_t *xs_tgt = nullptr;       // [nseg] target cell of the segment
     std::vector<fmm::XChunk> xchunks;
     void *xbuf = nullptr;            // per-pair products of one chunk

@@ -601,6 +601,13 @@ __global__ __launch_bounds__(256) void k_x_key2(const uint64_t *k1, int64_t nb, 
     v2[i] = (int32_t)i;
 }
 
+// inv[pos[i]] = i: the reduce-order position of each pair in key order
+__global__ __launch_bounds__(256) void k_x_invert(const int32_t *pos, int64_t nb, int32_t *inv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) inv[pos[i]] = (int32_t)i;
+}
+
 __global__ __launch_bounds__(256) void k_x_segflag(const uint64_t *k2, int64_t nb, int32_t *flag)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -620,14 +627,17 @@ __global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const in
     if (i == 0 || (k2[i - 1] >> 52) != ch) chunk_seg0[ch] = seg;
 }
 
-// One tile of TW pairs sharing one operator: out[pair] = T(key) M[src(pair)].
+// One tile of TW pairs sharing one operator: out[rpos(pair)] = T(key) M[src(pair)],
+// rpos = the pair's position in (chunk, target, key) order, so each target's
+// products lie together for the reduction.
 // Block = WV waves; the operator passes through two LDS stage buffers, the
 // next stage copied while the current one is multiplied.
 template <class T, int RT, int CG, int WV>
 __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict__ t_op,
                                                    const int64_t *__restrict__ t_first,
                                                    const int32_t *__restrict__ t_cnt, const int32_t *__restrict__ src,
-                                                   int zero_row, const T *__restrict__ Tf, const T *__restrict__ M,
+                                                   const int32_t *__restrict__ rpos, int zero_row,
+                                                   const T *__restrict__ Tf, const T *__restrict__ M,
                                                    T *__restrict__ out, int64_t pos0)
 {
     constexpr int ESZ = (int)sizeof(T);
@@ -686,7 +696,7 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
     for (int cg = 0; cg < CG; ++cg) {
         const int col = wave * CG * 16 + cg * 16 + j;
         if (col >= cnt) continue;
-        T *dst = out + (first + col - pos0) * P2pad;
+        T *dst = out + ((int64_t)rpos[first + col] - pos0) * P2pad;
 #pragma unroll
         for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -698,14 +708,14 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
 // sum in float64).  One thread per (segment, coefficient).
 template <class T>
 __global__ __launch_bounds__(256) void k_x_reduce(const int64_t *s_off, const int32_t *s_tgt, int64_t nseg,
-                                                  const int32_t *pos, int64_t pos0, const T *buf, int P2pad, T *L)
+                                                  int64_t pos0, const T *buf, int P2pad, T *L)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t seg = t / P2pad;
     const int row = (int)(t % P2pad);
     if (seg >= nseg) return;
     double acc = 0.0;
-    for (int64_t k = s_off[seg]; k < s_off[seg + 1]; ++k) acc += (double)buf[(pos[k] - pos0) * P2pad + row];
+    for (int64_t k = s_off[seg]; k < s_off[seg + 1]; ++k) acc += (double)buf[(k - pos0) * P2pad + row];
     T *dst = L + (int64_t)s_tgt[seg] * P2pad + row;
     *dst = (T)((double)*dst + acc);
 }
@@ -786,14 +796,13 @@ void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
     FMM_CHECK(nt * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
     if (nt > 0) {
         k_m2l_pairs<T, RT, CG, WV><<<(unsigned)nt, 64 * WV, 0, s>>>(
-            P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, (int)P->ncell,
+            P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, P->xr_inv, (int)P->ncell,
             static_cast<const T *>(P->xops), static_cast<const T *>(P->Mc), static_cast<T *>(P->xbuf), ch.p0);
         FMM_HIP(hipGetLastError());
     }
     const int64_t ns = ch.s1 - ch.s0;
     if (ns > 0) {
-        k_x_reduce<T><<<grid1(ns * P->P2pad, 256), 256, 0, s>>>(P->xs_off + ch.s0, P->xs_tgt + ch.s0, ns, P->xr_pos,
-                                                               ch.p0, static_cast<const T *>(P->xbuf), P->P2pad,
+        k_x_reduce<T><<<grid1(ns * P->P2pad, 256), 256, 0, s>>>(P->xs_off + ch.s0, P->xs_tgt + ch.s0, ns, ch.p0, static_cast<const T *>(P->xbuf), P->P2pad,
                                                                static_cast<T *>(P->Lc));
         FMM_HIP(hipGetLastError());
     }
@@ -1039,8 +1048,9 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     k_x_key2<<<grid1(nb, 256), 256, 0, s>>>(k1, nb, d_chunk_of, k2, v2);
     FMM_HIP(hipGetLastError());
     radix_sort_u64(k2, v2, nb, 52 + bits_of(nchunk), al, s);
-    P->xr_pos = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nb));
-    FMM_HIP(hipMemcpyAsync(P->xr_pos, v2, sizeof(int32_t) * nb, hipMemcpyDeviceToDevice, s));
+    P->xr_inv = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nb));
+    k_x_invert<<<grid1(nb, 256), 256, 0, s>>>(v2, nb, P->xr_inv);
+    FMM_HIP(hipGetLastError());
     int32_t *flag = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nb));
     int64_t *sidx = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * nb));
     int64_t *d_nseg = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
