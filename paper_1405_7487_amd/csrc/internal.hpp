@@ -158,6 +158,7 @@ struct fmm_plan {
     int64_t *m2lx_off = nullptr; int32_t *m2lx_src = nullptr;  // cross-level M2L
     // batched same-level M2L
     int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius
+    int st_reach = 0;                // largest |component| of a stencil offset
     int TW = 64;                     // targets per batched-M2L tile (64, 128 or 256)
     int E = 0;                       // stencil entries per chunk
     int NCH = 0;                     // chunks of the stencil (launched chunk after chunk)

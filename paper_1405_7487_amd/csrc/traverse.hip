@@ -149,17 +149,35 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
         }
 }
 
-// Cell class keys for the stable class-major ordering of each level.
-__global__ __launch_bounds__(256) void k_class_keys(const int32_t *lvl, const uint64_t *key, int64_t nc, uint64_t *ck,
-                                                    int32_t *idx, int32_t *cnt)
+// Tile order keys: level and octant class (the tiles; bits 16 and up), then,
+// inside a class, the cell's place relative to the faces of the root box
+// along each axis -- its distance to the nearer face when below CAP, signed by
+// face, else CAP; three digits of base 2 CAP + 1 -- and finally Morton order
+// (the cell order, kept by the stable sort).  Cells
+// that share these face classes have sources at the same stencil entries, so
+// grouping them leaves fewer empty target columns in the batched products.
+__device__ __forceinline__ uint32_t face_class(int v, int n, int cap)
+{
+    if (v < cap) return (uint32_t)v;
+    if (n - 1 - v < cap) return (uint32_t)(2 * cap - (n - 1 - v));
+    return (uint32_t)cap;
+}
+
+__global__ __launch_bounds__(256) void k_class_keys(const int32_t *lvl, const uint64_t *key, const int32_t *ix,
+                                                    int64_t nc, int cap, uint64_t *ck, int32_t *idx, int32_t *cnt)
 {
     __shared__ int32_t h[(kLevels + 1) * 8];
     for (int t = threadIdx.x; t < (kLevels + 1) * 8; t += blockDim.x) h[t] = 0;
     __syncthreads();
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nc) {
-        const int g = lvl[c] * 8 + (int)(key[c] & 7u);
-        ck[c] = (uint64_t)g;
+        const int l = lvl[c];
+        const int g = l * 8 + (int)(key[c] & 7u);
+        const int n = 1 << l;
+        const uint32_t F = 2 * cap + 1;
+        const uint32_t code = (face_class(ix[3 * c], n, cap) * F + face_class(ix[3 * c + 1], n, cap)) * F +
+                              face_class(ix[3 * c + 2], n, cap);
+        ck[c] = ((uint64_t)g << 16) | code;
         idx[c] = (int32_t)c;
         atomicAdd(&h[g], 1);
     }
@@ -174,7 +192,7 @@ __global__ __launch_bounds__(256) void k_fill_tiles(const uint64_t *ck, const in
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nc) return;
-    const int g = (int)ck[j];
+    const int g = (int)(ck[j] >> 16);
     const int c = idx[j];
     if (gtile[g] < 0) {  // level 0: no same-level partner
         tile_pos[c] = -1;
@@ -280,7 +298,7 @@ int ceil_div2(int v) { return (v >= 0) ? (v + 1) / 2 : -((-v) / 2); }
 // and kept for the life of the process.
 namespace {
 struct StencilCache {
-    int K = 0, R = 0, nops = 0;
+    int K = 0, R = 0, nops = 0, reach = 0;
     std::vector<int32_t> ops_t, st_t;
     int32_t *d_op = nullptr, *d_kidx = nullptr;
 };
@@ -305,6 +323,7 @@ StencilCache make_stencils(double t4)
                     if (mac_same_level((int64_t)Tx * Tx + (int64_t)Ty * Ty + (int64_t)Tz * Tz, t4)) continue;
                     S[c].push_back({tx, ty, tz});
                     uni[{tx, ty, tz}] = 0;
+                    C.reach = std::max({C.reach, std::abs(tx), std::abs(ty), std::abs(tz)});
                 }
     }
     int id = 0;
@@ -352,6 +371,7 @@ static void build_stencils(fmm_plan *P)
     const StencilCache &C = it->second;
     P->K = C.K;
     P->R = C.R;
+    P->st_reach = C.reach;
     P->nops = C.nops;
     P->h_ops_t = C.ops_t;
     P->h_st_t = C.st_t;
@@ -450,9 +470,14 @@ void traverse(fmm_plan *P, hipStream_t s)
     int32_t *idx = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nc));
     int32_t *gcnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * G));
     FMM_HIP(hipMemsetAsync(gcnt, 0, sizeof(int32_t) * G, s));
-    k_class_keys<<<grid1(nc, 256), 256, 0, s>>>(P->c_lvl, P->c_key, nc, ck, idx, gcnt);
+    // face classes are capped one cell short of the stencil's reach
+    const int cap = std::max(1, P->st_reach - 1);
+    FMM_CHECK((int64_t)(2 * cap + 1) * (2 * cap + 1) * (2 * cap + 1) <= 65536, FMM_ERR_UNSUPPORTED,
+              "traversal: stencil reach too large");
+    FMM_CHECK(G <= 256, FMM_ERR_UNSUPPORTED, "traversal: too many levels");
+    k_class_keys<<<grid1(nc, 256), 256, 0, s>>>(P->c_lvl, P->c_key, P->c_ix, nc, cap, ck, idx, gcnt);
     FMM_HIP(hipGetLastError());
-    radix_sort_u64(ck, idx, nc, 8, al, s);
+    radix_sort_u64(ck, idx, nc, 24, al, s);
     std::vector<int32_t> hcnt(G);
     FMM_HIP(hipMemcpyAsync(hcnt.data(), gcnt, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
     FMM_HIP(hipStreamSynchronize(s));
