@@ -104,17 +104,14 @@ __host__ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
 // M2L operator for lattice offset t (target minus source, in cell sides):
 // scaled local coefficients lt = T(t) mt with
 //     L_j^s = (-1)^j sum_{n,m} M_n^m I_{n+j}^{m+s}(t).
-// Written in the fragment layout of the batched kernel (Q = P2pad/4,
-// RT = P2pad/16, row = 16 r + i):
-//     Tf[(op*4 + g)*Q + s][i*RT + r] = T[16 r + i][g*Q + s].
-// Written in the table layout of m2l_opsz / m2l_sch / m2l_gst.
+// Written in the table layout of m2l_opsz / m2l_sch / m2l_gst (P2pad rows,
+// 4 m2l_q(p) input columns; rows and columns beyond p^2 stay zero).
 // Each operator is given as tr = (tau_x, tau_y, tau_z, e): the center offset
 // c_A - c_B in units of the target's cell size h_A, and the source-to-target
 // size ratio rho = h_B / h_A = 2^e (0 for same-level pairs), which scales
 // input degree n by rho^n.
 template <class T>
-__global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nops, int p, int P2pad, T *Tf,
-                                                      double *Tdense)
+__global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nops, int p, int P2pad, T *Tf)
 {
     const int op = blockIdx.x;
     if (op >= nops) return;
@@ -124,12 +121,12 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nop
     const int e2 = (int)t.w;
     if (threadIdx.x == 0) irregular_table(t.x, t.y, t.z, nI, H);
     __syncthreads();
-    const int P2 = p * p, Q = P2pad / 4;
+    const int P2 = p * p, Q = m2l_q(p), NCOL = 4 * Q;
     const int RT = P2pad / 16, esz = (int)sizeof(T);
-    const int SCH = m2l_sch(RT, esz), GST = m2l_gst(RT, esz);
-    const int64_t OPSZ = m2l_opsz(RT, esz);
-    for (int e = threadIdx.x; e < P2pad * P2pad; e += blockDim.x) {
-        const int row = e / P2pad, col = e % P2pad;
+    const int SCH = m2l_sch(RT, Q, esz), GST = m2l_gst(RT, Q, esz);
+    const int64_t OPSZ = m2l_opsz(RT, Q, esz);
+    for (int e = threadIdx.x; e < P2pad * NCOL; e += blockDim.x) {
+        const int row = e / NCOL, col = e % NCOL;
         double v = 0.0;
         if (row < P2 && col < P2) {
             int j, s, rim, n, m, cim;
@@ -149,7 +146,6 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nop
         }
         const int g = col / Q, sq = col % Q, c = sq / SCH, ss = sq % SCH;
         Tf[(size_t)op * OPSZ + (size_t)(c * 4 + g) * GST + ss * P2pad + (row % 16) * RT + row / 16] = (T)v;
-        if (Tdense) Tdense[((size_t)op * P2pad + row) * P2pad + col] = v;
     }
 }
 
@@ -472,7 +468,8 @@ void make_operators(fmm_plan *P, hipStream_t s)
     if (it == g_ops.end()) {
         OpCache C;
         const int esz = f64 ? (int)sizeof(double) : (int)sizeof(float);
-        const size_t opn = (size_t)std::max(1, P->nops) * m2l_opsz(P2pad / 16, esz) + m2l_tail(P2pad / 16, esz);
+        const int Q = m2l_q(P->p);
+        const size_t opn = (size_t)std::max(1, P->nops) * m2l_opsz(P2pad / 16, Q, esz) + m2l_tail(P2pad / 16, Q, esz);
         std::vector<double4> tr(std::max(1, P->nops));
         for (int k = 0; k < P->nops; ++k)
             tr[k] = make_double4(P->h_ops_t[3 * k], P->h_ops_t[3 * k + 1], P->h_ops_t[3 * k + 2], 0.0);
@@ -483,11 +480,9 @@ void make_operators(fmm_plan *P, hipStream_t s)
         FMM_HIP(hipMemsetAsync(C.ops, 0, (f64 ? sizeof(double) : sizeof(float)) * opn, s));
         if (P->nops > 0) {
             if (f64)
-                k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<double *>(C.ops),
-                                                                nullptr);
+                k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<double *>(C.ops));
             else
-                k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<float *>(C.ops),
-                                                               nullptr);
+                k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<float *>(C.ops));
             FMM_HIP(hipGetLastError());
         }
         const size_t shn = (size_t)8 * P2pad * P2pad;
@@ -523,9 +518,9 @@ void make_m2l_ops(fmm_plan *P, const double4 *tr_dev, int nops, void *out, hipSt
 {
     if (nops <= 0) return;
     if (P->precision == FMM_PREC_FP64)
-        k_make_m2l_ops<double><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<double *>(out), nullptr);
+        k_make_m2l_ops<double><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<double *>(out));
     else
-        k_make_m2l_ops<float><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<float *>(out), nullptr);
+        k_make_m2l_ops<float><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<float *>(out));
     FMM_HIP(hipGetLastError());
 }
 

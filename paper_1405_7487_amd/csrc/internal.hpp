@@ -48,34 +48,58 @@ struct Error : std::runtime_error {
 inline int p2pad_of(int p) { return ((p * p + 15) / 16) * 16; }
 
 // ------------------------------------------------- M2L operator table layout
-// An operator (P2pad x P2pad, RT = P2pad / 16 row tiles, Q = 4 RT input steps
-// per k-group) is stored as NC stages of SCH input steps; a stage holds the 4
-// k-groups one after another, GST elements apart, each group SCH rows of
-// P2pad values in MFMA fragment order:
+// An operator (P2pad output rows, RT = P2pad / 16 row tiles; 4 Q input
+// columns, Q input steps per k-group) is stored as NC stages of SCH input
+// steps; a stage holds the 4 k-groups one after another, GST elements apart,
+// each group SCH rows of P2pad values in MFMA fragment order:
 //     op[(c 4 + g) GST + ss P2pad + (row % 16) RT + row / 16] = T[row][g Q + c SCH + ss].
 // A stage is contiguous so that four waves copy it straight into LDS, 1 KiB
 // per wave and instruction; with RT odd the groups sit 64 bytes apart so the
 // fragment reads of lanes 0-31 fall in different LDS banks.  SCH is the
 // largest divisor of Q (a multiple of 4, else of 2, when one exists) whose
-// stage fits 16 KiB (32 KiB for float64, whose fragments are half as long).
-__host__ __device__ constexpr int m2l_sch(int RT, int esz)
+// stage fits 16 KiB (32 KiB for float64, whose fragments are half as long),
+// i.e. SCH RT <= 64.
+__host__ __device__ constexpr int m2l_sch(int RT, int Q, int esz)
 {
     int b4 = 0, b2 = 0, b1 = 1;
-    for (int sc = 1; sc <= 4 * RT; ++sc)
-        if ((4 * RT) % sc == 0 && 4 * sc * 16 * RT * esz <= (esz == 8 ? 32768 : 16384)) {
+    for (int sc = 1; sc <= Q; ++sc)
+        if (Q % sc == 0 && 4 * sc * 16 * RT * esz <= (esz == 8 ? 32768 : 16384)) {
             if (sc % 4 == 0) b4 = sc;
             if (sc % 2 == 0) b2 = sc;
             b1 = sc;
         }
     return b4 ? b4 : (b2 ? b2 : b1);
 }
-__host__ __device__ constexpr int m2l_gst(int RT, int esz) { return m2l_sch(RT, esz) * 16 * RT + ((RT & 1) ? 64 / esz : 0); }
+// Input steps per k-group for order p: ceil(p^2 / 4), so that the operator
+// carries no padded input columns (the MFMA needs the inputs in fours only),
+// when that count has a divisor of at least 4 (or is itself small) whose
+// stage fits; else 4 RT, the padded count.  p = 10: 25 steps of 4 inputs for
+// 100 coefficients instead of 28.
+__host__ __device__ constexpr int m2l_q(int p)
+{
+    const int RT = (p * p + 15) / 16, q0 = (p * p + 3) / 4;
+    int best = 0;
+    for (int sc = 1; sc <= q0; ++sc)
+        if (q0 % sc == 0 && sc * RT <= 64) best = sc;
+    return (best >= 4 || best == q0) ? q0 : 4 * RT;
+}
+__host__ __device__ constexpr int m2l_rt(int p) { return (p * p + 15) / 16; }
+__host__ __device__ constexpr int m2l_gst(int RT, int Q, int esz)
+{
+    return m2l_sch(RT, Q, esz) * 16 * RT + ((RT & 1) ? 64 / esz : 0);
+}
 // elements per operator, and the zero tail a table needs after its last operator
 // (the last stage copy is rounded up to whole 4 KiB block rounds)
-__host__ __device__ constexpr int64_t m2l_opsz(int RT, int esz) { return (int64_t)(4 * RT / m2l_sch(RT, esz)) * 4 * m2l_gst(RT, esz); }
+__host__ __device__ constexpr int64_t m2l_opsz(int RT, int Q, int esz)
+{
+    return (int64_t)(Q / m2l_sch(RT, Q, esz)) * 4 * m2l_gst(RT, Q, esz);
+}
 // rounds of WV KiB (WV waves copying 1 KiB each) that copy one stage
-__host__ __device__ constexpr int m2l_rounds(int RT, int esz, int WV) { return (4 * m2l_gst(RT, esz) * esz + 1024 * WV - 1) / (1024 * WV); }
-__host__ __device__ constexpr int64_t m2l_tail(int RT, int esz) { return (int64_t)m2l_rounds(RT, esz, 8) * 8192 / esz; }
+__host__ __device__ constexpr int m2l_rounds(int RT, int Q, int esz, int WV)
+{
+    return (4 * m2l_gst(RT, Q, esz) * esz + 1024 * WV - 1) / (1024 * WV);
+}
+__host__ __device__ constexpr int64_t m2l_tail(int RT, int Q, int esz) { return (int64_t)m2l_rounds(RT, Q, esz, 8) * 8192 / esz; }
 // Tiles of the batched M2L: CG column groups of 16 targets per wave, WV waves
 // per block.  Two groups per wave where the accumulators allow (float32,
 // P2pad <= 64), else one; four waves (eight measured slower at P = 10 and 12).

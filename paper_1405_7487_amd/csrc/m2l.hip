@@ -44,19 +44,9 @@ template <> struct Mfma<double> {
     }
 };
 
-template <class T> struct Vec16;
+// Widest vector of T (16 bytes at most) whose length divides SCH.
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
-template <> struct Vec16<float> {
-    typedef f4v t;
-    static constexpr int n = 4;
-};
-template <> struct Vec16<double> {
-    typedef d2v t;
-    static constexpr int n = 2;
-};
-
-// Widest vector of T (16 bytes at most) whose length divides SCH.
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f1v __attribute__((ext_vector_type(1)));
 typedef double d1v __attribute__((ext_vector_type(1)));
@@ -102,11 +92,11 @@ typedef __attribute__((address_space(3))) void lmem_t;
 // Copies one operator stage (4 GST elements, contiguous in the table) into an
 // LDS buffer: each lane moves 16 bytes straight to LDS (lane l of a wave
 // writes at its base + 16 l), ROUNDS rounds of WV KiB per block.
-template <class T, int RT, int WV>
+template <class T, int RT, int Q, int WV>
 __device__ __forceinline__ void stage_copy(const T *src, T *dst, int wave, int lane)
 {
     constexpr int WE = 1024 / (int)sizeof(T);  // elements per wave and round
-    constexpr int ROUNDS = m2l_rounds(RT, (int)sizeof(T), WV);
+    constexpr int ROUNDS = m2l_rounds(RT, Q, (int)sizeof(T), WV);
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
         const int o = (u * WV + wave) * WE;
@@ -115,7 +105,7 @@ __device__ __forceinline__ void stage_copy(const T *src, T *dst, int wave, int l
     }
 }
 
-template <class T, int RT, int CG, int WV>
+template <class T, int RT, int Q, int CG, int WV>
 __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restrict__ tile_order, int ntpos,
                                                      const int32_t *__restrict__ tile_cls,
                                                      const int32_t *__restrict__ slots,
@@ -128,10 +118,10 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restri
                                                      T *__restrict__ L, int64_t ntile)
 {
     constexpr int ESZ = (int)sizeof(T);
-    constexpr int P2pad = 16 * RT, Q = 4 * RT, TW = 16 * CG * WV;
-    constexpr int SCH = m2l_sch(RT, ESZ), NC = Q / SCH, GST = m2l_gst(RT, ESZ);
-    constexpr int64_t OPSZ = m2l_opsz(RT, ESZ);
-    constexpr int BUF = m2l_rounds(RT, ESZ, WV) * 1024 * WV / ESZ;  // elements per LDS stage buffer
+    constexpr int P2pad = 16 * RT, TW = 16 * CG * WV;
+    constexpr int SCH = m2l_sch(RT, Q, ESZ), NC = Q / SCH, GST = m2l_gst(RT, Q, ESZ);
+    constexpr int64_t OPSZ = m2l_opsz(RT, Q, ESZ);
+    constexpr int BUF = m2l_rounds(RT, Q, ESZ, WV) * 1024 * WV / ESZ;  // elements per LDS stage buffer
     constexpr int VB = BVec<T, SCH>::n;                   // vector width of the multipole loads
     typedef typename BVec<T, SCH>::t bvec_t;
     typedef typename Mfma<T>::acc_t acc_t;
@@ -177,7 +167,7 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restri
     {                                                                                              \
         int op_ = opk[KK];                                                                         \
         op_ = op_ < 0 ? 0 : op_;                                                                   \
-        stage_copy<T, RT, WV>(Tf + (int64_t)op_ * OPSZ + (CC) * 4 * GST, lds + (BUFI) * BUF, wave, lane); \
+        stage_copy<T, RT, Q, WV>(Tf + (int64_t)op_ * OPSZ + (CC) * 4 * GST, lds + (BUFI) * BUF, wave, lane); \
     }
 #define M2L_SLOTS(II, DST)                                                                         \
     {                                                                                              \
@@ -632,7 +622,7 @@ __global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const in
 // products lie together for the reduction.
 // Block = WV waves; the operator passes through two LDS stage buffers, the
 // next stage copied while the current one is multiplied.
-template <class T, int RT, int CG, int WV>
+template <class T, int RT, int Q, int CG, int WV>
 __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict__ t_op,
                                                    const int64_t *__restrict__ t_first,
                                                    const int32_t *__restrict__ t_cnt, const int32_t *__restrict__ src,
@@ -641,11 +631,11 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
                                                    T *__restrict__ out, int64_t pos0)
 {
     constexpr int ESZ = (int)sizeof(T);
-    constexpr int P2pad = 16 * RT, Q = 4 * RT;
-    constexpr int SCH = m2l_sch(RT, ESZ), NC = Q / SCH, GST = m2l_gst(RT, ESZ);
-    constexpr int BUF = m2l_rounds(RT, ESZ, WV) * 1024 * WV / ESZ;
-    constexpr int VN = Vec16<T>::n;
-    typedef typename Vec16<T>::t vec_t;
+    constexpr int P2pad = 16 * RT;
+    constexpr int SCH = m2l_sch(RT, Q, ESZ), NC = Q / SCH, GST = m2l_gst(RT, Q, ESZ);
+    constexpr int BUF = m2l_rounds(RT, Q, ESZ, WV) * 1024 * WV / ESZ;
+    constexpr int VN = BVec<T, Q>::n;
+    typedef typename BVec<T, Q>::t vec_t;
     typedef typename Mfma<T>::acc_t acc_t;
     __shared__ __align__(16) T lds[2 * BUF];
 
@@ -653,9 +643,9 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
     const int cnt = t_cnt[tile];
     const int64_t first = t_first[tile];
-    const T *opb = Tf + (int64_t)t_op[tile] * m2l_opsz(RT, ESZ);
+    const T *opb = Tf + (int64_t)t_op[tile] * m2l_opsz(RT, Q, ESZ);
 
-    stage_copy<T, RT, WV>(opb, lds, wave, lane);
+    stage_copy<T, RT, Q, WV>(opb, lds, wave, lane);
     T bq[CG][Q];
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
@@ -679,7 +669,7 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
     for (int c = 0; c < NC; ++c) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (c + 1 < NC) stage_copy<T, RT, WV>(opb + (c + 1) * 4 * GST, lds + ((c + 1) & 1) * BUF, wave, lane);
+        if (c + 1 < NC) stage_copy<T, RT, Q, WV>(opb + (c + 1) * 4 * GST, lds + ((c + 1) & 1) * BUF, wave, lane);
         const T *sbuf = lds + (c & 1) * BUF + g * GST + j * RT;
 #pragma unroll
         for (int ss = 0; ss < SCH; ++ss) {
@@ -742,7 +732,7 @@ __global__ void k_mfma_probe_f64(double *out)
 }
 
 // Launches chunk after chunk (G chunks at a time) over every tile.
-template <class T, int RT>
+template <class T, int RT, int Q>
 void launch_batched(fmm_plan *P, hipStream_t s)
 {
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8), WV = m2l_wv(RT, sizeof(T) == 8);
@@ -752,7 +742,7 @@ void launch_batched(fmm_plan *P, hipStream_t s)
         const int g = std::min(P->G, P->NCH - c0);
         const int64_t nb = (int64_t)g * ntpos;
         FMM_CHECK(nb * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
-        k_m2l_batched<T, RT, CG, WV><<<(unsigned)nb, 64 * WV, 0, s>>>(
+        k_m2l_batched<T, RT, Q, CG, WV><<<(unsigned)nb, 64 * WV, 0, s>>>(
             P->tile_order, ntpos, P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->E, c0, g,
             P->slot_none, (int)P->ncell, static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
             static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
@@ -767,27 +757,22 @@ void launch_batched(fmm_plan *P, hipStream_t s)
     }
 }
 
+// One instantiation per expansion order (row tiles and input steps follow from p).
+#define M2L_FOR_EACH_P(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
 template <class T>
 void dispatch_tiles(fmm_plan *P, hipStream_t s)
 {
-    switch (P->P2pad / 16) {
-    case 1: launch_batched<T, 1>(P, s); break;
-    case 2: launch_batched<T, 2>(P, s); break;
-    case 3: launch_batched<T, 3>(P, s); break;
-    case 4: launch_batched<T, 4>(P, s); break;
-    case 6: launch_batched<T, 6>(P, s); break;
-    case 7: launch_batched<T, 7>(P, s); break;
-    case 8: launch_batched<T, 8>(P, s); break;
-    case 9: launch_batched<T, 9>(P, s); break;
-    case 11: launch_batched<T, 11>(P, s); break;
-    case 13: launch_batched<T, 13>(P, s); break;
-    case 15: launch_batched<T, 15>(P, s); break;
-    case 16: launch_batched<T, 16>(P, s); break;
-    default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported padded coefficient count");
+    switch (P->p) {
+#define M2L_CASE(pp)                                             \
+    case pp: launch_batched<T, m2l_rt(pp), m2l_q(pp)>(P, s); break;
+        M2L_FOR_EACH_P(M2L_CASE)
+#undef M2L_CASE
+    default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported expansion order");
     }
 }
 
-template <class T, int RT>
+template <class T, int RT, int Q>
 void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 {
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8), WV = m2l_wv(RT, sizeof(T) == 8);
@@ -795,7 +780,7 @@ void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
     const int64_t nt = ch.t1 - ch.t0;
     FMM_CHECK(nt * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
     if (nt > 0) {
-        k_m2l_pairs<T, RT, CG, WV><<<(unsigned)nt, 64 * WV, 0, s>>>(
+        k_m2l_pairs<T, RT, Q, CG, WV><<<(unsigned)nt, 64 * WV, 0, s>>>(
             P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, P->xr_inv, (int)P->ncell,
             static_cast<const T *>(P->xops), static_cast<const T *>(P->Mc), static_cast<T *>(P->xbuf), ch.p0);
         FMM_HIP(hipGetLastError());
@@ -811,20 +796,12 @@ void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 template <class T>
 void dispatch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 {
-    switch (P->P2pad / 16) {
-    case 1: launch_pairs<T, 1>(P, ch, s); break;
-    case 2: launch_pairs<T, 2>(P, ch, s); break;
-    case 3: launch_pairs<T, 3>(P, ch, s); break;
-    case 4: launch_pairs<T, 4>(P, ch, s); break;
-    case 6: launch_pairs<T, 6>(P, ch, s); break;
-    case 7: launch_pairs<T, 7>(P, ch, s); break;
-    case 8: launch_pairs<T, 8>(P, ch, s); break;
-    case 9: launch_pairs<T, 9>(P, ch, s); break;
-    case 11: launch_pairs<T, 11>(P, ch, s); break;
-    case 13: launch_pairs<T, 13>(P, ch, s); break;
-    case 15: launch_pairs<T, 15>(P, ch, s); break;
-    case 16: launch_pairs<T, 16>(P, ch, s); break;
-    default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported padded coefficient count");
+    switch (P->p) {
+#define M2L_CASE(pp)                                                    \
+    case pp: launch_pairs<T, m2l_rt(pp), m2l_q(pp)>(P, ch, s); break;
+        M2L_FOR_EACH_P(M2L_CASE)
+#undef M2L_CASE
+    default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported expansion order");
     }
 }
 
@@ -860,7 +837,7 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     FMM_HIP(hipGetLastError());
 
     const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
-    const double opbytes = (double)P->P2pad * P->P2pad * esz;
+    const double opbytes = (double)m2l_opsz(P->P2pad / 16, m2l_q(P->p), (int)esz) * esz;
     const bool many = P->ntile >= 1024;
     const double budget = many ? 2.5 * 1048576.0 : 2.0 * 1048576.0;
     P->E = std::max(8, std::min(P->K, (int)(budget / opbytes)));
@@ -1016,7 +993,8 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     double4 *d_tr = static_cast<double4 *>(al.alloc(sizeof(double4) * nk));
     FMM_HIP(hipMemcpyAsync(d_tr, tr.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, s));
     const int RTx = P->P2pad / 16;
-    const size_t xn = (size_t)nk * m2l_opsz(RTx, (int)esz) + m2l_tail(RTx, (int)esz);
+    const int Qx = m2l_q(P->p);
+    const size_t xn = (size_t)nk * m2l_opsz(RTx, Qx, (int)esz) + m2l_tail(RTx, Qx, (int)esz);
     P->xops = plan_alloc(P, esz * xn);
     FMM_HIP(hipMemsetAsync(P->xops, 0, esz * xn, s));
     make_m2l_ops(P, d_tr, nk, P->xops, s);
