@@ -104,7 +104,8 @@ typedef struct {
     int64_t n_m2l_same;      /* M2L pairs between cells of one level            */
     int64_t n_m2l_cross;     /* M2L pairs between cells of different levels     */
     int64_t n_p2p;           /* P2P leaf pairs                                 */
-    int64_t p2p_body_pairs;  /* sum over P2P pairs of |A| * |B|                */
+    int64_t p2p_body_pairs;  /* sum over P2P pairs of |A| * |B|, -1 until
+                                fmm_count_body_pairs has counted it            */
     int64_t m2l_stencil;     /* same-level offsets per target octant class     */
     int64_t m2l_offsets;     /* distinct same-level offsets (operators)        */
     int64_t m2l_slots;       /* slot entries scanned by the batched M2L         */
@@ -190,6 +191,14 @@ FMM_API fmm_status fmm_export_tree(const fmm_plan *plan, const fmm_tree_export *
  * out_host is a HOST array of 2 uint64.  Synchronises the plan's stream.
  * Errors: FMM_ERR_INVALID (NULL argument), FMM_ERR_DEVICE. */
 FMM_API fmm_status fmm_list_digest(const fmm_plan *plan, uint64_t *out_host);
+
+/* Body pairs of the P2P list: the sum over P2P leaf pairs (A <- B) of
+ * |A| |B| (the near-field work of Section II.A, self pairs included), into
+ * *out_host (a HOST int64).  A statistic kept apart from fmm_plan_stats,
+ * which reports it once counted: the count walks the whole list and
+ * synchronises the plan's stream.
+ * Errors: FMM_ERR_INVALID (NULL argument), FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_count_body_pairs(const fmm_plan *plan, int64_t *out_host);
 
 /* Per-phase event timing on (1) or off (0, default).  Timing adds one event
  * pair per phase to the stream. */

@@ -24,7 +24,7 @@ PREC = {"fp64": 0, "mixed": 1}
 EXPORTS = (
     "fmm_params_default", "fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_adjoint",
     "fmm_plan_stats", "fmm_export_tree", "fmm_set_timing", "fmm_destroy", "fmm_last_error",
-    "fmm_debug_mfma_layout", "fmm_list_digest",
+    "fmm_debug_mfma_layout", "fmm_list_digest", "fmm_count_body_pairs",
 )
 
 
@@ -93,8 +93,10 @@ def load():
     L.fmm_last_error.restype = C.c_char_p
     L.fmm_debug_mfma_layout.argtypes = [C.c_int32, vp]
     L.fmm_list_digest.argtypes = [vp, C.POINTER(C.c_uint64)]
+    L.fmm_count_body_pairs.argtypes = [vp, C.POINTER(C.c_int64)]
     for name in ("fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_adjoint", "fmm_plan_stats",
-                 "fmm_export_tree", "fmm_set_timing", "fmm_debug_mfma_layout", "fmm_list_digest"):
+                 "fmm_export_tree", "fmm_set_timing", "fmm_debug_mfma_layout", "fmm_list_digest",
+                 "fmm_count_body_pairs"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L
@@ -240,6 +242,13 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(load().fmm_list_digest(self._h, out))
         return int(out[0]), int(out[1])
+
+    def body_pairs(self) -> int:
+        """Sum over P2P leaf pairs of |A| |B| (fmm_count_body_pairs)."""
+        out = C.c_int64(0)
+        with torch.cuda.device(self.device):
+            _check(load().fmm_count_body_pairs(self._h, C.byref(out)))
+        return int(out.value)
 
     def export_tree(self, lists: bool = True) -> dict:
         """Host copies of keys, permutation, cells and (optionally) lists."""

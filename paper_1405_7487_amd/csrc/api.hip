@@ -566,11 +566,7 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
     st.n_m2l_cross = P->n_m2l_cross;
     st.n_m2l = P->n_m2l_same + P->n_m2l_cross;
     st.n_p2p = P->n_p2p;
-    try {
-        st.p2p_body_pairs = P->n > 0 ? p2p_body_pairs(P, P->al.stream) : 0;
-    } catch (const Error &e) {
-        return fail(e);
-    }
+    st.p2p_body_pairs = P->n > 0 ? P->p2p_body_pairs : 0;  // -1 until counted
     st.m2l_stencil = P->K;
     st.m2l_offsets = P->nops;
     st.m2l_slots = P->ntile * (int64_t)P->K * P->TW;
@@ -607,6 +603,19 @@ fmm_status fmm_list_digest(const fmm_plan *Pc, uint64_t *out)
         list_digest(P, h, P->al.stream);
         out[0] = h[0];
         out[1] = h[1];
+    } catch (const Error &e) {
+        return fail(e);
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_count_body_pairs(const fmm_plan *Pc, int64_t *out)
+{
+    g_err.clear();
+    try {
+        FMM_CHECK(Pc && out, FMM_ERR_INVALID, "NULL argument");
+        fmm_plan *P = const_cast<fmm_plan *>(Pc);
+        *out = P->n > 0 ? p2p_body_pairs(P, P->al.stream) : 0;
     } catch (const Error &e) {
         return fail(e);
     }

@@ -43,6 +43,7 @@ def test_params_default_and_last_error_without_gpu():
     assert lib.fmm_evaluate_plan(None, None, None, None, None) == 1
     assert lib.fmm_adjoint(None, None, None, None, None, None, None) == 1
     assert lib.fmm_list_digest(None, None) == 1
+    assert lib.fmm_count_body_pairs(None, None) == 1
 
 
 def test_product_path_does_not_import_the_oracle():

@@ -74,6 +74,13 @@ def test_tree_and_lists_bit_exact(case):
     st = plan.stats()
     assert (st["ncell"], st["nleaf"], st["depth"]) == (T.ncell, T.nleaf, T.depth)
     assert (st["n_m2l"], st["n_p2p"]) == (T.n_m2l, T.n_p2p)
+    # body pairs of the P2P list: counted on request only, then reported by stats
+    assert st["p2p_body_pairs"] == -1
+    o = T.export()
+    size = (o["end"] - o["begin"]).astype(np.int64)
+    want = int(np.sum(size[o["p2p"][:, 0]] * size[o["p2p"][:, 1]]))
+    assert plan.body_pairs() == want
+    assert plan.stats()["p2p_body_pairs"] == want
 
 
 def test_float32_coordinates_widen_exactly():
