@@ -146,6 +146,25 @@ def test_cross_level_pairs_plummer(p, n, ncrit, theta):
         assert rel(ph, po) < tol and rel(Eh, Eo) < tol, (precision, rel(ph, po), rel(Eh, Eo))
 
 
+def test_many_tiles_plummer():
+    # at least 1024 same-level tiles: every stencil chunk runs in a launch of
+    # its own and adds straight to the local expansions
+    x, q, _ = W.plummer(400_000, 11)
+    p, theta, ncrit = 10, 0.35, 8
+    tg = W.sample_targets(x.shape[0], 256)
+    T = oracle.Tree(x, ncrit, theta, targets=tg)
+    po, Eo = T.fmm(q, p, targets=tg)
+    for precision, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
+        plan = F.Plan(dev(x), F.Params(p=p, theta=theta, ncrit=ncrit, precision=precision))
+        st = plan.stats()
+        assert st["m2l_slots"] // (st["m2l_stencil"] * 64) >= 1024  # tiles of 64 targets at p = 10
+        assert (st["n_m2l"], st["n_p2p"]) == (T.n_m2l, T.n_p2p)
+        assert plan.list_digest() == (T.digest_m2l, T.digest_p2p)
+        phi, E = plan.evaluate(dev(q))
+        assert rel(host(phi)[tg], po) < tol and rel(host(E)[tg], Eo) < tol, precision
+        plan.close()
+
+
 def test_p2p_long_lists_split_over_work_items():
     # small leaves and a tight acceptance criterion: coarse halo leaves of a
     # Plummer tree carry P2P lists of (nearly) every leaf, which are cut into
