@@ -823,7 +823,8 @@ int m2l_tile_width(int p, bool f64)
 // Chunking of the stencils and the class-interleaved tile order.  Chunks
 // hold E entries whose operators fit comfortably in one XCD's L2 next to the
 // gathered multipoles; G chunks share a launch when there are too few tiles
-// to fill the chip.
+// to fill the chip, and with very few tiles the chunks are shortened so that
+// the launch still has enough blocks.
 void m2l_prepare(fmm_plan *P, hipStream_t s)
 {
     P->NCH = 0;
@@ -840,7 +841,11 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     const double opbytes = (double)m2l_opsz(P->P2pad / 16, m2l_q(P->p), (int)esz) * esz;
     const bool many = P->ntile >= 1024;
     const double budget = many ? 2.5 * 1048576.0 : 2.0 * 1048576.0;
-    P->E = std::max(8, std::min(P->K, (int)(budget / opbytes)));
+    // entries per chunk: what the operator budget allows, but short enough
+    // that tiles x chunks gives about 4096 blocks when the tiles are few
+    // (each block walks its entries one after another)
+    const int64_t e_fill = ((int64_t)P->K * P->ntile + 4095) / 4096;
+    P->E = (int)std::max<int64_t>(8, std::min<int64_t>({(int64_t)P->K, (int64_t)(budget / opbytes), e_fill}));
     P->NCH = (P->K + P->E - 1) / P->E;
     P->G = many ? 1 : (int)std::min<int64_t>(P->NCH, (8192 + P->ntile - 1) / P->ntile);
     if (P->G > 1)
