@@ -221,6 +221,35 @@ __global__ __launch_bounds__(256) void k_geometry(const uint64_t *ckey, const in
     }
 }
 
+// Per-level cell arrays of the level loop and where each level starts in
+// the (level, key)-ordered arrays.
+struct LevelSrc {
+    const int32_t *beg, *end, *par, *nch, *cbeg;
+    const uint64_t *key;
+    int64_t start;
+};
+
+// Cell c of the final order: its level is the last one starting at or before
+// c (levels are few; a linear scan over them).
+__global__ __launch_bounds__(256) void k_gather_levels(const LevelSrc *src, int nlev, int64_t nc, int32_t *lvl,
+                                                       int32_t *beg, int32_t *end, int32_t *par, int32_t *nch,
+                                                       int32_t *cbeg, uint64_t *key)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int l = 0;
+    while (l + 1 < nlev && src[l + 1].start <= c) ++l;
+    const LevelSrc &b = src[l];
+    const int64_t i = c - b.start;
+    lvl[c] = l;
+    beg[c] = b.beg[i];
+    end[c] = b.end[i];
+    par[c] = b.par[i];
+    nch[c] = b.nch[i];
+    cbeg[c] = b.cbeg[i];
+    key[c] = b.key[i];
+}
+
 __global__ __launch_bounds__(256) void k_leaf_flags(const int32_t *nch, int64_t ncell, int32_t *flag)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,23 +398,23 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s)
     P->c_nch = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nc));
     P->c_key = static_cast<uint64_t *>(plan_alloc(P, sizeof(uint64_t) * nc));
     P->lv.assign(P->depth + 1, Level{});
-    std::vector<int32_t> hl;
+    // one gather of the per-level arrays into the (level, key)-ordered SoA
+    std::vector<LevelSrc> hsrc(P->depth + 1);
     int64_t o = 0;
     for (int l = 0; l <= P->depth; ++l) {
         const LvlBufs &b = L[l];
         P->lv[l].start = o;
         P->lv[l].count = b.cnt;
-        FMM_HIP(hipMemcpyAsync(P->c_beg + o, b.beg, sizeof(int32_t) * b.cnt, hipMemcpyDeviceToDevice, s));
-        FMM_HIP(hipMemcpyAsync(P->c_end + o, b.end, sizeof(int32_t) * b.cnt, hipMemcpyDeviceToDevice, s));
-        FMM_HIP(hipMemcpyAsync(P->c_par + o, b.par, sizeof(int32_t) * b.cnt, hipMemcpyDeviceToDevice, s));
-        FMM_HIP(hipMemcpyAsync(P->c_nch + o, b.nch, sizeof(int32_t) * b.cnt, hipMemcpyDeviceToDevice, s));
-        FMM_HIP(hipMemcpyAsync(P->c_cbeg + o, b.cbeg, sizeof(int32_t) * b.cnt, hipMemcpyDeviceToDevice, s));
-        FMM_HIP(hipMemcpyAsync(P->c_key + o, b.key, sizeof(uint64_t) * b.cnt, hipMemcpyDeviceToDevice, s));
-        hl.insert(hl.end(), (size_t)b.cnt, (int32_t)l);
+        hsrc[l] = LevelSrc{b.beg, b.end, b.par, b.nch, b.cbeg, b.key, o};
         o += b.cnt;
     }
-    FMM_HIP(hipMemcpyAsync(P->c_lvl, hl.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
-    FMM_HIP(hipStreamSynchronize(s));  // hl is host memory; per-level buffers are freed below
+    LevelSrc *dsrc = static_cast<LevelSrc *>(al.alloc(sizeof(LevelSrc) * hsrc.size()));
+    FMM_HIP(hipMemcpyAsync(dsrc, hsrc.data(), sizeof(LevelSrc) * hsrc.size(), hipMemcpyHostToDevice, s));
+    k_gather_levels<<<grid1(nc, 256), 256, 0, s>>>(dsrc, P->depth + 1, nc, P->c_lvl, P->c_beg, P->c_end, P->c_par,
+                                                   P->c_nch, P->c_cbeg, P->c_key);
+    FMM_HIP(hipGetLastError());
+    FMM_HIP(hipStreamSynchronize(s));  // hsrc is host memory; per-level buffers are freed below
+    al.free(dsrc);
     for (auto &b : L) {
         al.free(b.beg); al.free(b.end); al.free(b.par); al.free(b.key);
         al.free(b.nch); al.free(b.cbeg);
