@@ -13,7 +13,8 @@ on a CPU cluster; here the same shapes are drawn at one rank's share:
   drawn by inverse-CDF sampling of the enclosed mass (Aarseth, Henon &
   Wielen 1974) with no rejection; isotropic directions.
 * ``sphere_surface``- points on the unit sphere's surface (boundary-integral
-  style workload).
+  style workload): z and the azimuth uniform, which is uniform on the
+  surface (Archimedes' hat-box theorem); charges uniform in [-1,1].
 
 All draws use numpy's PCG64 ``default_rng`` in a fixed order, in float64.
 """
@@ -105,13 +106,15 @@ def fd_coordinates(n: int, k: int = 64, seed=(0, 2)):
     return idx, ax
 
 
-# The five workloads: (name, n, distribution, p, theta, ncrit)
+# The workloads: (name, n, distribution, p, theta, ncrit)
 CONFIGS = {
     "cube16k": dict(n=16384, dist="cube", p=4, theta=0.4, ncrit=64),
     "cube1m": dict(n=1 << 20, dist="cube", p=8, theta=0.4, ncrit=64),
     "plummer4m": dict(n=1 << 22, dist="plummer", p=10, theta=0.35, ncrit=32),
     "cube1m_adjoint": dict(n=1 << 20, dist="cube", p=8, theta=0.4, ncrit=64),
     "plummer16m": dict(n=1 << 24, dist="plummer_unit", p=12, theta=0.3, ncrit=64),
+    # Table I case 2 (Sphere) at one rank's share: P, theta and N_crit of the paper
+    "sphere4m": dict(n=1 << 22, dist="sphere", p=10, theta=0.4, ncrit=512),
 }
 
 
@@ -125,4 +128,6 @@ def make_config(name: str, n: int | None = None, seed: int = 0):
         return plummer(n, seed, "equal")
     if c["dist"] == "plummer_unit":
         return plummer(n, seed, "unit")
+    if c["dist"] == "sphere":
+        return sphere_surface(n, seed)
     raise ValueError(c["dist"])

@@ -56,10 +56,13 @@ def _compare_tree(plan, x, ncrit, theta):
     return T
 
 
-@pytest.mark.parametrize("case", ["cube16k", "plummer", "dups"])
+@pytest.mark.parametrize("case", ["cube16k", "plummer", "sphere", "dups"])
 def test_tree_and_lists_bit_exact(case):
     if case == "cube16k":
         x, q, _ = W.make_config("cube16k")
+        ncrit, theta = 64, 0.4
+    elif case == "sphere":
+        x, _, _ = W.sphere_surface(40000, 7)
         ncrit, theta = 64, 0.4
     elif case == "plummer":
         x, _, _ = W.plummer(30000, 5)
@@ -90,11 +93,14 @@ def test_float32_coordinates_widen_exactly():
     _compare_tree(plan, x32.astype(np.float64), 24, 0.4)
 
 
-@pytest.mark.parametrize("case", ["cube16k", "plummer"])
+@pytest.mark.parametrize("case", ["cube16k", "plummer", "sphere"])
 def test_fmm_matches_oracle(case):
     if case == "cube16k":
         x, q, _ = W.make_config("cube16k")
         p, theta, ncrit = 4, 0.4, 64
+    elif case == "sphere":
+        x, q, _ = W.sphere_surface(40000, 8)
+        p, theta, ncrit = 10, 0.4, 128
     else:
         x, _, _ = W.plummer(40000, 2)
         q = np.random.default_rng(3).uniform(-1, 1, 40000)

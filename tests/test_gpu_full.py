@@ -5,6 +5,7 @@ times (plan built on torch's allocator, one evaluate, mixed and FP64 paths).
 * plummer4m  N = 2^22 Plummer, P = 10, theta = 0.35, N_crit = 32
 * cube1m_adjoint: the adjoint of L = sum w phi at 2^20
 * plummer16m N = 2^24 Plummer, P = 12, theta = 0.3, N_crit = 64
+* sphere4m   N = 2^22 on the unit sphere's surface, P = 10, theta = 0.4, N_crit = 512
 
 The oracle cannot evaluate every body at these sizes, so potentials and fields
 are compared on sampled targets (the oracle's target-subset mode gives exactly
@@ -45,7 +46,7 @@ def _check_tree(plan, T):
     return st
 
 
-@pytest.mark.parametrize("name,ntarget", [("cube1m", 512), ("plummer4m", 96)])
+@pytest.mark.parametrize("name,ntarget", [("cube1m", 512), ("plummer4m", 96), ("sphere4m", 96)])
 def test_full_size_parity(name, ntarget):
     cfg = W.CONFIGS[name]
     x_np, q_np, _ = W.make_config(name)

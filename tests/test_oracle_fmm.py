@@ -69,11 +69,14 @@ def _a_priori_bound(x, q, T, e, p, targets):
     return bphi, bE
 
 
-@pytest.mark.parametrize("case", ["cube16k", "plummer"])
+@pytest.mark.parametrize("case", ["cube16k", "plummer", "sphere"])
 def test_error_within_a_priori_bound(case):
     if case == "cube16k":
         x, q, _ = W.make_config("cube16k")
         ncrit, theta, p = 64, 0.4, 4
+    elif case == "sphere":
+        x, q, _ = W.sphere_surface(6000, 3)
+        ncrit, theta, p = 32, 0.4, 5
     else:
         x, q, _ = W.plummer(6000, 1)
         q = np.random.default_rng(2).uniform(-1, 1, 6000)
