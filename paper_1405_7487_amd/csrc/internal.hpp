@@ -167,6 +167,7 @@ struct fmm_plan {
     double *c_ctr = nullptr;       // [3*ncell]
     int32_t *leaves = nullptr;     // [nleaf] leaf cell indices (ascending)
     void *ubody = nullptr;         // [n] float4 or double4 (u, q)
+    void *ulo = nullptr;           // [n] float4: float32 rounding residuals of ubody (mixed path)
 
     // lists
     int64_t n_m2l_same = 0, n_m2l_cross = 0, n_p2p = 0, p2p_body_pairs = 0;

@@ -66,6 +66,40 @@ __device__ __forceinline__ void batch(const V4 *sb, int npad, int sub, T ux, T u
     }
 }
 
+// The same with compensated coordinates, for a leaf's own bodies: offsets
+// u + l (u rounded, l its residual), differences formed as (u_i - u_j) +
+// (l_i - l_j).  For close bodies the first difference is exact, so the pair's
+// separation keeps its own relative precision instead of the leaf size's;
+// coincident bodies still give exactly zero and are skipped.
+template <class T, class V4, int G>
+__device__ __forceinline__ void batch_own(const V4 *sb, const V4 *sl, int npad, int sub, T ux, T uy, T uz, T lx,
+                                          T ly, T lz, Acc<T> &a)
+{
+    const V4 *p = sb + sub, *r = sl + sub;
+    for (int it = 0; it < npad; it += G * kUnroll, p += G * kUnroll, r += G * kUnroll) {
+        V4 v[kUnroll], w[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            v[u] = p[u * G];
+            w[u] = r[u * G];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const T dx = (ux - v[u].x) + (lx - w[u].x), dy = (uy - v[u].y) + (ly - w[u].y),
+                    dz = (uz - v[u].z) + (lz - w[u].z);
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            T ri = rsqrt_t<T>(r2);
+            ri = r2 > (T)0 ? ri : (T)0;
+            const T qri = v[u].w * ri;
+            const T qr3 = qri * (ri * ri);
+            a.p += qri;
+            a.x += qr3 * dx;
+            a.y += qr3 * dy;
+            a.z += qr3 * dz;
+        }
+    }
+}
+
 template <class T, class V4>
 __device__ __forceinline__ V4 far_dummy()
 {
@@ -91,7 +125,7 @@ template <class T> struct GatherLds {
 template <class T, class V4, bool KAHAN, int G>
 __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base, int cnt, bool own,
                            const int32_t *beg, const int32_t *end, int64_t k0, int64_t k1, const int32_t *src,
-                           const double *ctr, const V4 *ub, T *op, T *oE, int64_t o0)
+                           const double *ctr, const V4 *ub, const V4 *ul, T *op, T *oE, int64_t o0)
 {
     // sources per batch: a multiple of G kUnroll, so a padded batch never
     // runs past its kStage slots
@@ -113,14 +147,19 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
         }
     };
     const int32_t ab = beg[A], ae = own ? end[A] : beg[A];
-    // 1) the leaf's own bodies (may coincide with the target): masked
+    // 1) the leaf's own bodies (may coincide with the target): masked, with
+    //    the residuals (when given) staged in the second buffer
+    const V4 ut = ul ? ul[tb + base + (active ? ti : 0)] : V4{};
     for (int32_t o = ab; o < ae; o += SMAX) {
         const int take = min(SMAX, ae - o);
         const int npad = (take + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
         for (int l = lane; l < npad; l += 64) sb[l] = l < take ? ub[o + l] : far_dummy<T, V4>();
+        if (ul)
+            for (int l = lane; l < npad; l += 64) sb[kStage + l] = l < take ? ul[o + l] : V4{};
         __syncthreads();
         Acc<T> pa{0, 0, 0, 0};
-        batch<T, V4, G, true>(sb, npad, sub, u.x, u.y, u.z, pa);
+        if (ul) batch_own<T, V4, G>(sb, sb + kStage, npad, sub, u.x, u.y, u.z, ut.x, ut.y, ut.z, pa);
+        else batch<T, V4, G, true>(sb, npad, sub, u.x, u.y, u.z, pa);
         fold(pa);
         __syncthreads();
     }
@@ -244,8 +283,8 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
 template <class T, class V4, bool KAHAN>
 __global__ __launch_bounds__(64) void k_p2p(const int32_t *it_leaf, const int64_t *it_k0, const int64_t *it_k1,
                                             const int64_t *it_out, const int32_t *beg, const int32_t *end,
-                                            const int32_t *src, const double *ctr, const V4 *ub, T *phi_s, T *E_s,
-                                            T *part_p, T *part_E)
+                                            const int32_t *src, const double *ctr, const V4 *ub, const V4 *ul,
+                                            T *phi_s, T *E_s, T *part_p, T *part_E)
 {
     __shared__ V4 sb[2 * kStage];
     __shared__ GatherLds<T> gs;
@@ -267,7 +306,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *it_leaf, const int64_
         const int rem = nt - base;
         cnt = (rem > 32 && rem < 56) ? 32 : min(64, rem);
         // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
-#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, first, beg, end, k0, k1, src, ctr, ub, op, oE, o0)
+#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, first, beg, end, k0, k1, src, ctr, ub, ul, op, oE, o0)
         if (cnt <= 4) P2P_CHUNK(16);
         else if (cnt <= 5) P2P_CHUNK(12);
         else if (cnt <= 8) P2P_CHUNK(8);
@@ -367,7 +406,7 @@ void launch_items(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream
     FMM_CHECK(P->p2p_nitem * 64 < (1ll << 32), FMM_ERR_UNSUPPORTED, "p2p: too many work items");
     k_p2p<T, V4, KAHAN><<<(unsigned)P->p2p_nitem, 64, 0, s>>>(
         P->p2p_it_leaf, P->p2p_it_k0, P->p2p_it_k1, P->p2p_it_out, P->c_beg, P->c_end, P->p2p_src, P->c_ctr,
-        static_cast<const V4 *>(ub), static_cast<T *>(phi_s), static_cast<T *>(E_s),
+        static_cast<const V4 *>(ub), static_cast<const V4 *>(P->ulo), static_cast<T *>(phi_s), static_cast<T *>(E_s),
         static_cast<T *>(P->p2p_part), static_cast<T *>(P->p2p_part) + P->p2p_npart);
     FMM_HIP(hipGetLastError());
     if (P->p2p_ncut > 0) {

@@ -266,21 +266,33 @@ __global__ __launch_bounds__(256) void k_leaf_list(const int32_t *nch, const int
     for (int32_t i = beg[c]; i < end[c]; ++i) leaf_of[i] = (int32_t)c;
 }
 
-// Offsets of the bodies from their leaf centers, in the compute type.
+// Offsets of the bodies from their leaf centers, in the compute type; with
+// ul given (float32), also what the rounding left out, so that u + ul carries
+// the float64 offset to about 48 bits.
 template <class TX, class V4>
 __global__ __launch_bounds__(256) void k_body_offsets(const TX *x, const int32_t *perm, const int32_t *leaf_of,
-                                                      const double *ctr, int64_t n, V4 *ub)
+                                                      const double *ctr, int64_t n, V4 *ub, V4 *ul)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t o = perm[i];
     int64_t c = leaf_of[i];
+    const double dx = (double)x[3 * o] - ctr[3 * c], dy = (double)x[3 * o + 1] - ctr[3 * c + 1],
+                 dz = (double)x[3 * o + 2] - ctr[3 * c + 2];
     V4 u;
-    u.x = (decltype(u.x))((double)x[3 * o] - ctr[3 * c]);
-    u.y = (decltype(u.y))((double)x[3 * o + 1] - ctr[3 * c + 1]);
-    u.z = (decltype(u.z))((double)x[3 * o + 2] - ctr[3 * c + 2]);
+    u.x = (decltype(u.x))dx;
+    u.y = (decltype(u.y))dy;
+    u.z = (decltype(u.z))dz;
     u.w = 0;
     ub[i] = u;
+    if (ul) {
+        V4 r;
+        r.x = (decltype(r.x))(dx - (double)u.x);
+        r.y = (decltype(r.y))(dy - (double)u.y);
+        r.z = (decltype(r.z))(dz - (double)u.z);
+        r.w = 0;
+        ul[i] = r;
+    }
 }
 
 template <class T>
@@ -448,18 +460,23 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s)
         P->ubody = plan_alloc(P, sizeof(double4) * n);
         if (P->dtype == FMM_F64)
             k_body_offsets<double, double4><<<grid1(n, 256), 256, 0, s>>>(
-                static_cast<const double *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<double4 *>(P->ubody));
+                static_cast<const double *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<double4 *>(P->ubody),
+                nullptr);
         else
             k_body_offsets<float, double4><<<grid1(n, 256), 256, 0, s>>>(
-                static_cast<const float *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<double4 *>(P->ubody));
+                static_cast<const float *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<double4 *>(P->ubody),
+                nullptr);
     } else {
         P->ubody = plan_alloc(P, sizeof(float4) * n);
+        P->ulo = plan_alloc(P, sizeof(float4) * n);
         if (P->dtype == FMM_F64)
             k_body_offsets<double, float4><<<grid1(n, 256), 256, 0, s>>>(
-                static_cast<const double *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<float4 *>(P->ubody));
+                static_cast<const double *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<float4 *>(P->ubody),
+                static_cast<float4 *>(P->ulo));
         else
             k_body_offsets<float, float4><<<grid1(n, 256), 256, 0, s>>>(
-                static_cast<const float *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<float4 *>(P->ubody));
+                static_cast<const float *>(x), P->perm, P->leaf_of, P->c_ctr, n, static_cast<float4 *>(P->ubody),
+                static_cast<float4 *>(P->ulo));
     }
     FMM_HIP(hipGetLastError());
 

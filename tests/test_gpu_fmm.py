@@ -152,6 +152,23 @@ def test_cross_level_pairs_plummer(p, n, ncrit, theta):
         assert rel(ph, po) < tol and rel(Eh, Eo) < tol, (precision, rel(ph, po), rel(Eh, Eo))
 
 
+def test_nearly_coincident_bodies_keep_their_field():
+    # pairs 1e-7 apart inside leaves about 0.06 wide: with float32 offsets from
+    # the leaf center alone their separation would carry a 1e-2 error, and
+    # these few bodies dominate the L2 norm of E; the own-leaf pass uses
+    # compensated coordinates, so all bodies stay within the 1e-4 bar
+    x, q, _ = W.uniform_cube(20000, 21)
+    d = np.random.default_rng(22).normal(size=(10, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    x[1:20:2] = x[0:20:2] + 1e-7 * d
+    T = oracle.Tree(x, 64, 0.4)
+    po, Eo = T.fmm(q, 6)
+    _, pm, Em = gpu_fmm(x, q, 6, 0.4, 64, "mixed")
+    assert rel(pm, po) < 1e-4 and rel(Em, Eo) < 1e-4, (rel(pm, po), rel(Em, Eo))
+    near = np.arange(20)
+    assert rel(Em[near], Eo[near]) < 1e-4
+
+
 def test_many_tiles_plummer():
     # at least 1024 same-level tiles: every stencil chunk runs in a launch of
     # its own and adds straight to the local expansions

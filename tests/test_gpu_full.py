@@ -58,17 +58,24 @@ def test_full_size_parity(name, ntarget):
     pd, Ed = oracle.direct(x_np, q_np, targets=tg)
     say(f"[{name}] oracle vs direct: phi {rel(po, pd):.3e} E {rel(Eo, Ed):.3e}")
     x, q = dev(x_np), dev(q_np)
+    full = {}
     for precision, tol in (("fp64", 1e-10), ("mixed", 1e-4)):
         say(f"[{name}] GPU {precision}")
         plan = _plan(x, cfg, precision)
         phi, E = plan.evaluate(q)
         torch.cuda.synchronize()
         _check_tree(plan, T)
-        phi_h, E_h = host(phi)[tg], host(E)[tg]
+        full[precision] = (host(phi), host(E))
+        phi_h, E_h = full[precision][0][tg], full[precision][1][tg]
         ep, eE = rel(phi_h, po), rel(E_h, Eo)
         say(f"[{name}] {precision}: vs oracle phi {ep:.3e} E {eE:.3e}; vs direct phi {rel(phi_h, pd):.3e}")
         assert ep < tol and eE < tol, (precision, ep, eE)
         plan.close()
+    # every body: the mixed path against the FP64 path (itself ~1e-15 from the oracle)
+    ap = rel(full["mixed"][0], full["fp64"][0])
+    aE = rel(full["mixed"][1], full["fp64"][1])
+    say(f"[{name}] mixed vs fp64 GPU, all {n} bodies: phi {ap:.3e} E {aE:.3e}")
+    assert ap < 1e-4 and aE < 1e-4
 
 
 def test_full_size_tree_bit_exact_plummer4m():
