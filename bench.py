@@ -7,7 +7,8 @@ evaluation (P2M, M2M, M2L, L2L, L2P, P2P, unpermute) and the adjoint of
 L = sum w phi.  `value` is the forward throughput N / T_forward in
 particles/s (potential + field); the adjoint time is reported beside it.
 
-Prints ONE JSON line.  Multi-GPU runs are not part of this build.
+Prints ONE JSON line.  The library evaluates one rank's share on one GPU;
+multi-GPU runs are not supported.
 """
 from __future__ import annotations
 
@@ -61,7 +62,7 @@ def main():
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build evaluates one rank's share on one GPU; --gpus must be 1 "
+        print("bench.py: the library evaluates one rank's share on one GPU; --gpus must be 1 "
               "(the multi-GPU LET exchange is out of scope)", file=sys.stderr)
         sys.exit(2)
 
