@@ -57,7 +57,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cube1m")
     ap.add_argument("--precision", default="mixed")
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="oracle targets for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=12000, help="oracle targets for cpu_baseline (0 = skip)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 GPU forward runs for the speedup (0 = skip)")
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
     args = ap.parse_args()

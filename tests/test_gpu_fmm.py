@@ -253,6 +253,23 @@ def test_autograd_function():
         assert rel(host(xt.grad), -(w[:, None] * Eq + q[:, None] * Ew)) < 1e-11
 
 
+def test_one_body_leaves():
+    # N_crit = 1: every leaf holds one body (or coincident ones), the deepest
+    # trees and the most cross-level pairs a distribution gives
+    x, _, _ = W.plummer(3000, 14)
+    q = np.random.default_rng(15).uniform(-1, 1, 3000)
+    x[2990:] = x[:10]  # coincident bodies end in shared leaves at level 21
+    T = oracle.Tree(x, 1, 0.4)
+    po, Eo = T.fmm(q, 5)
+    plan, p64, E64 = gpu_fmm(x, q, 5, 0.4, 1, "fp64")
+    st = plan.stats()
+    assert (st["ncell"], st["depth"], st["n_m2l"], st["n_p2p"]) == (T.ncell, T.depth, T.n_m2l, T.n_p2p)
+    assert plan.list_digest() == (T.digest_m2l, T.digest_p2p)
+    assert rel(p64, po) < 1e-11 and rel(E64, Eo) < 1e-11
+    _, pm, Em = gpu_fmm(x, q, 5, 0.4, 1, "mixed")
+    assert rel(pm, po) < 1e-4 and rel(Em, Eo) < 1e-4
+
+
 def test_deterministic_bits():
     x, _, _ = W.plummer(30000, 11)
     q = np.random.default_rng(0).uniform(-1, 1, 30000)
