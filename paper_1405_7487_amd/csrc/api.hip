@@ -655,6 +655,7 @@ fmm_status fmm_export_tree(const fmm_plan *Pc, const fmm_tree_export *o)
         if (o->p2p) {
             std::vector<uint64_t> v;
             csr_pairs(P->p2p_off, P->p2p_src, P->n_p2p, v);
+            std::sort(v.begin(), v.end());  // canonical (target, source) order
             for (size_t k = 0; k < v.size(); ++k) {
                 o->p2p[2 * k] = (int32_t)(v[k] >> 32);
                 o->p2p[2 * k + 1] = (int32_t)(v[k] & 0xffffffffu);

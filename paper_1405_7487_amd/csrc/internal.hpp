@@ -247,7 +247,9 @@ namespace fmm {
 void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s);
 void scan_exclusive_i32to64(const int32_t *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s);
 // stable LSD radix sort of 64-bit keys (optionally with 32-bit values) on bits [0, bits)
-void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s);
+// Stable LSD sort of keys (and vals, when given) by key bits [lo_bit, bits).
+void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s,
+                    int lo_bit = 0);
 
 // tree.hip
 void tree_build(fmm_plan *P, const void *x, hipStream_t s);

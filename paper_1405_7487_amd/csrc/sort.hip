@@ -182,10 +182,10 @@ void scan_exclusive_i32to64(const int32_t *in, int64_t *out, int64_t n, int64_t 
     scan_impl<int32_t>(in, out, n, total_dev, al, s);
 }
 
-void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s)
+void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s, int lo_bit)
 {
-    if (n <= 1 || bits <= 0) return;
-    const int npass = (bits + 7) / 8;
+    if (n <= 1 || bits <= lo_bit) return;
+    const int npass = (bits - lo_bit + 7) / 8;
     const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
     FMM_CHECK(nb < (1ll << 31), FMM_ERR_UNSUPPORTED, "radix sort: too many keys");
     uint64_t *k2 = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * n));
@@ -195,7 +195,7 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocato
     uint64_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;
     for (int ps = 0; ps < npass; ++ps) {
-        const int shift = 8 * ps;
+        const int shift = lo_bit + 8 * ps;
         k_radix_hist<<<(unsigned)nb, kRadixThreads, 0, s>>>(ka, n, shift, hist, nb);
         FMM_HIP(hipGetLastError());
         scan_impl<int32_t>(hist, offs, 256 * nb, nullptr, al, s);

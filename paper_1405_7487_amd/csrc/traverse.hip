@@ -389,7 +389,9 @@ static int bits_for(int64_t v)
 static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int64_t **off, int32_t **src,
                         int64_t *body_pairs_dev, hipStream_t s)
 {
-    radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s);
+    // grouped by target only (the target bits): within a target the pairs keep
+    // the traversal's order, which is fixed, so the lists are deterministic
+    radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s, cbits);
     *off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (P->ncell + 1)));
     *src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, np)));
     k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits, P->ncell, *off);
