@@ -581,13 +581,14 @@ __global__ __launch_bounds__(256) void k_x_key1(const int32_t *tgt, const int32_
 }
 
 // Sort key (chunk, target, key id) of each batched pair; value = its position.
-__global__ __launch_bounds__(256) void k_x_key2(const uint64_t *k1, int64_t nb, const int32_t *chunk_of,
+// (chunk, target, key) packed as chunk << cs | target << 21 | key
+__global__ __launch_bounds__(256) void k_x_key2(const uint64_t *k1, int64_t nb, const int32_t *chunk_of, int cs,
                                                 uint64_t *k2, int32_t *v2)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     const uint64_t id = k1[i] >> 32, a = k1[i] & 0xffffffffull;
-    k2[i] = ((uint64_t)(uint32_t)chunk_of[id] << 52) | (a << 21) | id;
+    k2[i] = ((uint64_t)(uint32_t)chunk_of[id] << cs) | (a << 21) | id;
     v2[i] = (int32_t)i;
 }
 
@@ -606,15 +607,16 @@ __global__ __launch_bounds__(256) void k_x_segflag(const uint64_t *k2, int64_t n
 }
 
 __global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const int32_t *flag, const int64_t *sidx,
-                                                    int64_t nb, int64_t *s_off, int32_t *s_tgt, int64_t *chunk_seg0)
+                                                    int64_t nb, int cs, int64_t *s_off, int32_t *s_tgt,
+                                                    int64_t *chunk_seg0)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb || !flag[i]) return;
     const int64_t seg = sidx[i];
     s_off[seg] = i;
-    s_tgt[seg] = (int32_t)((k2[i] >> 21) & 0x7fffffffull);
-    const uint64_t ch = k2[i] >> 52;
-    if (i == 0 || (k2[i - 1] >> 52) != ch) chunk_seg0[ch] = seg;
+    s_tgt[seg] = (int32_t)((k2[i] >> 21) & ((1ull << (cs - 21)) - 1ull));
+    const uint64_t ch = k2[i] >> cs;
+    if (i == 0 || (k2[i - 1] >> cs) != ch) chunk_seg0[ch] = seg;
 }
 
 // One tile of TW pairs sharing one operator: out[rpos(pair)] = T(key) M[src(pair)],
@@ -1015,7 +1017,9 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     FMM_HIP(hipMemsetAsync(gcnt, 0, sizeof(int32_t) * (nc + 1), s));
     k_x_key1<<<grid1(nx, 256), 256, 0, s>>>(tgt, P->m2lx_src, code, d_id_of, nk, nx, k1, v1, gcnt);
     FMM_HIP(hipGetLastError());
-    radix_sort_u64(k1, v1, nx, 32 + bits_of(nk), al, s);
+    // the pairs arrive in target order, so a stable sort on the key bits alone
+    // gives (key, target) order
+    radix_sort_u64(k1, v1, nx, 32 + bits_of(nk), al, s, 32);
     P->xp_src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nb));
     FMM_HIP(hipMemcpyAsync(P->xp_src, v1, sizeof(int32_t) * nb, hipMemcpyDeviceToDevice, s));
     P->n_gx = nx - nb;
@@ -1028,9 +1032,13 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     // reduction order: (chunk, target, key)
     uint64_t *k2 = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * nb));
     int32_t *v2 = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nb));
-    k_x_key2<<<grid1(nb, 256), 256, 0, s>>>(k1, nb, d_chunk_of, k2, v2);
+    const int csh = 21 + bits_of(nc);
+    FMM_CHECK(csh + bits_of(nchunk) <= 64, FMM_ERR_UNSUPPORTED, "m2l: cross-level key too wide");
+    k_x_key2<<<grid1(nb, 256), 256, 0, s>>>(k1, nb, d_chunk_of, csh, k2, v2);
     FMM_HIP(hipGetLastError());
-    radix_sort_u64(k2, v2, nb, 52 + bits_of(nchunk), al, s);
+    // the input is in (key, target) order, so sorting the chunk and target
+    // bits stably leaves the keys of a target in order
+    radix_sort_u64(k2, v2, nb, csh + bits_of(nchunk), al, s, 21);
     P->xr_inv = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nb));
     k_x_invert<<<grid1(nb, 256), 256, 0, s>>>(v2, nb, P->xr_inv);
     FMM_HIP(hipGetLastError());
@@ -1046,7 +1054,7 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     P->xs_off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (nseg + 1)));
     P->xs_tgt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nseg)));
     int64_t *d_cs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * (nchunk + 1)));
-    k_x_segments<<<grid1(nb, 256), 256, 0, s>>>(k2, flag, sidx, nb, P->xs_off, P->xs_tgt, d_cs);
+    k_x_segments<<<grid1(nb, 256), 256, 0, s>>>(k2, flag, sidx, nb, csh, P->xs_off, P->xs_tgt, d_cs);
     FMM_HIP(hipGetLastError());
     FMM_HIP(hipMemcpyAsync(P->xs_off + nseg, &nb, sizeof(int64_t), hipMemcpyHostToDevice, s));
     std::vector<int64_t> cs(nchunk + 1);
