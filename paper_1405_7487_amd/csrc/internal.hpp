@@ -184,7 +184,7 @@ struct fmm_plan {
     // batched same-level M2L
     int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius
     int st_reach = 0;                // largest |component| of a stencil offset
-    int TW = 64;                     // targets per batched-M2L tile (64, 128 or 256)
+    int TW = 64;                     // targets per batched-M2L tile (64 or 128)
     int E = 0;                       // stencil entries per chunk
     int NCH = 0;                     // chunks of the stencil (launched chunk after chunk)
     int G = 1;                       // chunks per launch (partial sums when > 1)

@@ -4,14 +4,17 @@
 // Same-level pairs.  With level-scaled coefficients the M2L operator between
 // two cells of one level depends only on their integer offset t, so the
 // translation L(A) += T(t) M(A - t) is a dense p^2 x p^2 product.  A block
-// owns a tile of 64 targets of one level and one octant class (so they share
-// one stencil of offsets); for every stencil entry k it multiplies the common
-// operator T(t_k) by the 64 gathered source multipoles with MFMA
+// owns a tile of 64 or 128 targets of one level and one octant class (so they
+// share one stencil of offsets); for every stencil entry k it multiplies the
+// common operator T(t_k) by the gathered source multipoles with MFMA
 // (v_mfma_{f32,f64}_16x16x4), accumulating in registers; each target's sum is
 // written once, without atomics, in a fixed order.
 //
-// Cross-level pairs (a leaf against a finer cell) use a generic kernel that
-// builds the operator of the actual offset on the fly.
+// Cross-level pairs (a leaf against a cell of another level) are keyed by
+// level difference and lattice offset: keys with enough pairs get an operator
+// of their own and run as shared-operator MFMA products, written per pair and
+// summed per target in key order; the rest use a generic kernel that builds
+// the operator of the actual offset on the fly.
 #include "internal.hpp"
 
 #include <cmath>
