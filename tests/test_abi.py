@@ -53,3 +53,22 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "liboracle" not in txt, f
+
+
+def test_entry_build_calls_both_compilers(monkeypatch):
+    """__graft_entry__.build() reaches the oracle's and the library's build
+    functions (stubbed here; the real compile runs outside the unit tests)."""
+    import importlib
+    import sys
+
+    sys.path.insert(0, ROOT)
+    try:
+        entry = importlib.import_module("__graft_entry__")
+    finally:
+        sys.path.remove(ROOT)
+    called = []
+    for mod in ("oracle.build", "paper_1405_7487_amd.build"):
+        m = importlib.import_module(mod)
+        monkeypatch.setattr(m, "build", lambda *a, _m=mod, **k: called.append(_m))
+    entry.build()
+    assert called == ["oracle.build", "paper_1405_7487_amd.build"]
