@@ -57,29 +57,75 @@ struct TreeView {
     double t4;
 };
 
-// Classification of one child pair: 0 = same-level M2L, 1 = cross-level M2L,
-// 2 = P2P, 3 = split further.
-__device__ __forceinline__ int classify(const TreeView &T, int a, int b)
+// A cell as the expansion kernels see it: level, lattice coordinates at that
+// level and child count.
+struct CellG {
+    int l, x, y, z, n;
+};
+
+__device__ __forceinline__ CellG load_cell(const TreeView &T, int c)
 {
-    const int la = T.lvl[a], lb = T.lvl[b];
-    if (mac_dev(la, T.ix[3 * a], T.ix[3 * a + 1], T.ix[3 * a + 2], lb, T.ix[3 * b], T.ix[3 * b + 1], T.ix[3 * b + 2],
-                T.t4))
-        return la == lb ? 0 : 1;
-    if (T.nch[a] == 0 && T.nch[b] == 0) return 2;
+    CellG g;
+    g.l = T.lvl[c];
+    g.x = T.ix[3 * c];
+    g.y = T.ix[3 * c + 1];
+    g.z = T.ix[3 * c + 2];
+    g.n = T.nch[c];
+    return g;
+}
+
+// Classification of one child pair: 0 = same-level M2L, 1 = cross-level M2L,
+// 2 = P2P, 3 = split further.  For two cells of one level the lattice test
+// reduces to sides 2 and center differences 2 (i_A - i_B): the same integers,
+// hence the same decision, as the general form.
+__device__ __forceinline__ int classify(const CellG &A, const CellG &B, double t4)
+{
+#pragma clang fp contract(off)
+    bool acc;
+    if (A.l == B.l) {
+        const int64_t dx = A.x - B.x, dy = A.y - B.y, dz = A.z - B.z;
+        acc = 48.0 < t4 * (double)(4 * (dx * dx + dy * dy + dz * dz));
+    } else {
+        acc = mac_dev(A.l, A.x, A.y, A.z, B.l, B.x, B.y, B.z, t4);
+    }
+    if (acc) return A.l == B.l ? 0 : 1;
+    if (A.n == 0 && B.n == 0) return 2;
     return 3;
 }
 
 // The split rule of the traversal for a pair that was not accepted and is
 // not two leaves.
-__device__ __forceinline__ void split_rule(const TreeView &T, int a, int b, bool &sa, bool &sb)
+__device__ __forceinline__ void split_rule(const CellG &A, const CellG &B, bool &sa, bool &sb)
 {
-    const bool leafa = T.nch[a] == 0, leafb = T.nch[b] == 0;
-    const int la = T.lvl[a], lb = T.lvl[b];
+    const bool leafa = A.n == 0, leafb = B.n == 0;
     if (leafa) { sa = false; sb = true; }
     else if (leafb) { sa = true; sb = false; }
-    else if (la < lb) { sa = true; sb = false; }
-    else if (lb < la) { sa = false; sb = true; }
+    else if (A.l < B.l) { sa = true; sb = false; }
+    else if (B.l < A.l) { sa = false; sb = true; }
     else { sa = true; sb = true; }
+}
+
+// Child pairs of frontier pair (a, b): the source side's (at most 8) cells are
+// loaded into registers once; the target side's one at a time.  The visiting
+// order (target child outer, source child inner) fixes the order of the
+// emitted pairs.
+struct Expansion {
+    int na, nb, a0, b0;
+    CellG ys[8];
+};
+
+__device__ __forceinline__ void expansion(const TreeView &T, int a, int b, Expansion &E)
+{
+    const CellG A = load_cell(T, a), B = load_cell(T, b);
+    bool sa, sb;
+    split_rule(A, B, sa, sb);
+    E.na = sa ? A.n : 1;
+    E.nb = sb ? B.n : 1;
+    E.a0 = sa ? T.cbeg[a] : a;
+    E.b0 = sb ? T.cbeg[b] : b;
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+        if (v < E.nb) E.ys[v] = sb ? load_cell(T, E.b0 + v) : B;
 }
 
 __global__ __launch_bounds__(256) void k_expand_count(TreeView T, const int2 *F, int64_t nf, int32_t *c_cross,
@@ -87,20 +133,21 @@ __global__ __launch_bounds__(256) void k_expand_count(TreeView T, const int2 *F,
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
-    const int a = F[i].x, b = F[i].y;
-    bool sa, sb;
-    split_rule(T, a, b, sa, sb);
-    const int na = sa ? T.nch[a] : 1, nb = sb ? T.nch[b] : 1;
-    const int a0 = sa ? T.cbeg[a] : a, b0 = sb ? T.cbeg[b] : b;
+    Expansion E;
+    expansion(T, F[i].x, F[i].y, E);
     int cx = 0, cp = 0, cn = 0, cs = 0;
-    for (int u = 0; u < na; ++u)
-        for (int v = 0; v < nb; ++v) {
-            int k = classify(T, a0 + u, b0 + v);
-            cs += k == 0;
-            cx += k == 1;
-            cp += k == 2;
-            cn += k == 3;
-        }
+    for (int u = 0; u < E.na; ++u) {
+        const CellG X = load_cell(T, E.a0 + u);
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (v < E.nb) {
+                const int k = classify(X, E.ys[v], T.t4);
+                cs += k == 0;
+                cx += k == 1;
+                cp += k == 2;
+                cn += k == 3;
+            }
+    }
     c_cross[i] = cx;
     c_p2p[i] = cp;
     c_next[i] = cn;
@@ -113,40 +160,43 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nf) return;
-    const int a = F[i].x, b = F[i].y;
-    bool sa, sb;
-    split_rule(T, a, b, sa, sb);
-    const int na = sa ? T.nch[a] : 1, nb = sb ? T.nch[b] : 1;
-    const int a0 = sa ? T.cbeg[a] : a, b0 = sb ? T.cbeg[b] : b;
+    Expansion E;
+    expansion(T, F[i].x, F[i].y, E);
     int64_t ox = o_cross[i], op = o_p2p[i], on = o_next[i];
     const int W = 2 * T.R + 1;
-    for (int u = 0; u < na; ++u)
-        for (int v = 0; v < nb; ++v) {
-            const int x = a0 + u, y = b0 + v;
-            const int k = classify(T, x, y);
-            if (k == 0) {
-                const int tx = T.ix[3 * x] - T.ix[3 * y], ty = T.ix[3 * x + 1] - T.ix[3 * y + 1],
-                          tz = T.ix[3 * x + 2] - T.ix[3 * y + 2];
-                const int cls = (int)(T.key[x] & 7u);
-                int kk = -1;
-                if (abs(tx) <= T.R && abs(ty) <= T.R && abs(tz) <= T.R)
-                    kk = T.kidx[cls * W * W * W + ((tx + T.R) * W + (ty + T.R)) * W + (tz + T.R)];
-                const int pos = T.tile_pos[x];
-                if (kk < 0 || pos < 0) {
-                    atomicOr(err, 1);
+    for (int u = 0; u < E.na; ++u) {
+        const int x = E.a0 + u;
+        const CellG X = load_cell(T, x);
+        const int cls = (int)(T.key[x] & 7u);
+        const int pos = T.tile_pos[x];
+        const int64_t tile = pos / T.TW, lane = pos % T.TW;
+        const int32_t *kx = T.kidx + cls * W * W * W;
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (v < E.nb) {
+                const CellG &Y = E.ys[v];
+                const int y = E.b0 + v;
+                const int k = classify(X, Y, T.t4);
+                if (k == 0) {
+                    const int tx = X.x - Y.x, ty = X.y - Y.y, tz = X.z - Y.z;
+                    int kk = -1;
+                    if (abs(tx) <= T.R && abs(ty) <= T.R && abs(tz) <= T.R)
+                        kk = kx[((tx + T.R) * W + (ty + T.R)) * W + (tz + T.R)];
+                    if (kk < 0 || pos < 0) {
+                        atomicOr(err, 1);
+                    } else {
+                        T.slots[(tile * T.K + kk) * T.TW + lane] = y;
+                        T.kflag[tile * T.K + kk] = 1;
+                    }
+                } else if (k == 1) {
+                    cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
+                } else if (k == 2) {
+                    p2p[op++] = ((uint64_t)x << cbits) | (uint64_t)y;
                 } else {
-                    const int64_t tile = pos / T.TW, lane = pos % T.TW;
-                    T.slots[(tile * T.K + kk) * T.TW + lane] = y;
-                    T.kflag[tile * T.K + kk] = 1;
+                    next[on++] = make_int2(x, y);
                 }
-            } else if (k == 1) {
-                cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
-            } else if (k == 2) {
-                p2p[op++] = ((uint64_t)x << cbits) | (uint64_t)y;
-            } else {
-                next[on++] = make_int2(x, y);
             }
-        }
+    }
 }
 
 // Tile order keys: level and octant class (the tiles; bits 16 and up), then,
