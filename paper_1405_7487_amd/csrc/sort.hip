@@ -49,11 +49,22 @@ __global__ __launch_bounds__(kScanThreads) void k_block_sums(const Tin *in, int6
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Exclusive scan of one tile plus a per-block offset (offs may be null).
+// Exclusive scan of one tile plus a per-block offset: offs[blockIdx.x] when
+// offs is given, else the sum of sums[0, blockIdx.x) when sums is given (each
+// block adds up its predecessors' totals itself), else 0.
 template <class Tin>
 __global__ __launch_bounds__(kScanThreads) void k_block_scan(const Tin *in, int64_t *out, int64_t n,
-                                                             const int64_t *offs, int64_t *total)
+                                                             const int64_t *offs, const int64_t *sums,
+                                                             int64_t *total)
 {
+    int64_t boff = 0;
+    if (offs) {
+        boff = offs[blockIdx.x];
+    } else if (sums) {
+        int64_t part = 0;
+        for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += kScanThreads) part += sums[j];
+        block_scan_incl(part, &boff);
+    }
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int64_t v[kScanItems];
     int64_t s = 0;
@@ -64,7 +75,7 @@ __global__ __launch_bounds__(kScanThreads) void k_block_scan(const Tin *in, int6
     }
     int64_t tot;
     int64_t incl = block_scan_incl(s, &tot);
-    int64_t run = incl - s + (offs ? offs[blockIdx.x] : 0);
+    int64_t run = incl - s + boff;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) out[base + k] = run;
@@ -72,6 +83,11 @@ __global__ __launch_bounds__(kScanThreads) void k_block_scan(const Tin *in, int6
     }
     if (total && threadIdx.x == kScanThreads - 1 && blockIdx.x == gridDim.x - 1) *total = run;
 }
+
+// Up to this many tiles, the blocks of the final pass find their offsets from
+// the raw tile sums (two launches in all); beyond it the tile sums are
+// scanned first.
+constexpr int64_t kSelfOffsetTiles = 2048;
 
 template <class Tin>
 void scan_impl(const Tin *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s)
@@ -82,7 +98,7 @@ void scan_impl(const Tin *in, int64_t *out, int64_t n, int64_t *total_dev, Alloc
     }
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 1) {
-        k_block_scan<Tin><<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, total_dev);
+        k_block_scan<Tin><<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, nullptr, total_dev);
         FMM_HIP(hipGetLastError());
         return;
     }
@@ -90,9 +106,13 @@ void scan_impl(const Tin *in, int64_t *out, int64_t n, int64_t *total_dev, Alloc
     int64_t *soff = sums + nb;
     k_block_sums<Tin><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, sums);
     FMM_HIP(hipGetLastError());
-    scan_impl<int64_t>(sums, soff, nb, nullptr, al, s);
-    // the last block's running sum after its tile is the grand total
-    k_block_scan<Tin><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, soff, total_dev);
+    if (nb <= kSelfOffsetTiles) {
+        k_block_scan<Tin><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, nullptr, sums, total_dev);
+    } else {
+        scan_impl<int64_t>(sums, soff, nb, nullptr, al, s);
+        // the last block's running sum after its tile is the grand total
+        k_block_scan<Tin><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, soff, nullptr, total_dev);
+    }
     FMM_HIP(hipGetLastError());
     al.free(sums);
 }
@@ -101,6 +121,7 @@ void scan_impl(const Tin *in, int64_t *out, int64_t n, int64_t *total_dev, Alloc
 constexpr int kRadixThreads = 256;
 constexpr int kRadixRounds = 16;
 constexpr int kRadixTile = kRadixThreads * kRadixRounds;  // 4096 keys per block
+static_assert(kRadixThreads == kScanThreads, "the scatter uses the block scan");
 
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint64_t *kin, int64_t n, int shift,
                                                               int32_t *hist, int64_t nb)
@@ -117,18 +138,54 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint64_t *ki
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// Per digit d (one block each): exclusive scan of hist[d][0, nb), the counts
+// of digit d in the tiles in order, and the digit's total.
+__global__ __launch_bounds__(kScanThreads) void k_radix_rowscan(const int32_t *hist, int64_t nb, int64_t *rowoff,
+                                                                int64_t *rowtot)
+{
+    const int32_t *h = hist + (int64_t)blockIdx.x * nb;
+    int64_t *o = rowoff + (int64_t)blockIdx.x * nb;
+    int64_t carry = 0;
+    for (int64_t t0 = 0; t0 < nb; t0 += kScanTile) {
+        const int64_t base = t0 + (int64_t)threadIdx.x * kScanItems;
+        int64_t v[kScanItems];
+        int64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            v[k] = base + k < nb ? (int64_t)h[base + k] : 0;
+            sum += v[k];
+        }
+        int64_t tot;
+        int64_t run = block_scan_incl(sum, &tot) - sum + carry;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (base + k < nb) o[base + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
+}
+
 // Stable scatter: element order inside a tile is (round, wave, lane); ranks of
 // equal digits inside a wave come from ballots on the 8 digit bits.
 template <bool kVals>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint64_t *kin, const int32_t *vin,
                                                                  uint64_t *kout, int32_t *vout, int64_t n,
-                                                                 int shift, const int64_t *offs, int64_t nb)
+                                                                 int shift, const int64_t *rowoff,
+                                                                 const int64_t *rowtot, int64_t nb)
 {
     __shared__ int64_t s_base[256];
     __shared__ int32_t s_wcnt[kRadixThreads / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
-    s_base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    {
+        // start of digit tid: the totals of the smaller digits, then the
+        // counts of digit tid in the tiles before this one
+        const int64_t dt = rowtot[tid];
+        int64_t all;
+        s_base[tid] = block_scan_incl(dt, &all) - dt + rowoff[(int64_t)tid * nb + blockIdx.x];
+    }
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     for (int r = 0; r < kRadixRounds; ++r) {
 #pragma unroll
@@ -191,18 +248,21 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocato
     uint64_t *k2 = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * n));
     int32_t *v2 = vals ? static_cast<int32_t *>(al.alloc(sizeof(int32_t) * n)) : nullptr;
     int32_t *hist = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 256 * nb));
-    int64_t *offs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 256 * nb));
+    int64_t *offs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * (256 * nb + 256)));
+    int64_t *dtot = offs + 256 * nb;
     uint64_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;
     for (int ps = 0; ps < npass; ++ps) {
         const int shift = lo_bit + 8 * ps;
         k_radix_hist<<<(unsigned)nb, kRadixThreads, 0, s>>>(ka, n, shift, hist, nb);
         FMM_HIP(hipGetLastError());
-        scan_impl<int32_t>(hist, offs, 256 * nb, nullptr, al, s);
+        k_radix_rowscan<<<256, kScanThreads, 0, s>>>(hist, nb, offs, dtot);
+        FMM_HIP(hipGetLastError());
         if (vals)
-            k_radix_scatter<true><<<(unsigned)nb, kRadixThreads, 0, s>>>(ka, va, kb, vb, n, shift, offs, nb);
+            k_radix_scatter<true><<<(unsigned)nb, kRadixThreads, 0, s>>>(ka, va, kb, vb, n, shift, offs, dtot, nb);
         else
-            k_radix_scatter<false><<<(unsigned)nb, kRadixThreads, 0, s>>>(ka, nullptr, kb, nullptr, n, shift, offs, nb);
+            k_radix_scatter<false><<<(unsigned)nb, kRadixThreads, 0, s>>>(ka, nullptr, kb, nullptr, n, shift, offs,
+                                                                          dtot, nb);
         FMM_HIP(hipGetLastError());
         std::swap(ka, kb);
         std::swap(va, vb);

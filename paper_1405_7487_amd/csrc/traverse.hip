@@ -162,7 +162,9 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
     if (i >= nf) return;
     Expansion E;
     expansion(T, F[i].x, F[i].y, E);
-    int64_t ox = o_cross[i], op = o_p2p[i], on = o_next[i];
+    // one scan covers the three count arrays back to back: each list's
+    // offsets start at its own first entry
+    int64_t ox = o_cross[i] - o_cross[0], op = o_p2p[i] - o_p2p[0], on = o_next[i] - o_next[0];
     const int W = 2 * T.R + 1;
     for (int u = 0; u < E.na; ++u) {
         const int x = E.a0 + u;
@@ -196,6 +198,17 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
                     next[on++] = make_int2(x, y);
                 }
             }
+    }
+}
+
+// Totals of the three lists from the scan over their concatenated counts.
+__global__ void k_list_totals(const int64_t *offs, int64_t nf, int64_t *tot)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t all = tot[3];
+        tot[0] = offs[nf];
+        tot[1] = offs[2 * nf] - offs[nf];
+        tot[2] = all - offs[2 * nf];
     }
 }
 
@@ -635,13 +648,15 @@ void traverse(fmm_plan *P, hipStream_t s)
         FMM_HIP(hipMemcpy(F, &r0, sizeof(int2), hipMemcpyHostToDevice));
         nf = 1;
     }
-    int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3));
+    int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 4));
     while (nf > 0) {
         int32_t *cnts = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 3 * nf));
         int64_t *offs = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3 * nf));
         k_expand_count<<<grid1(nf, 256), 256, 0, s>>>(T, F, nf, cnts, cnts + nf, cnts + 2 * nf, d_cnt);
         FMM_HIP(hipGetLastError());
-        for (int j = 0; j < 3; ++j) scan_exclusive_i32to64(cnts + j * nf, offs + j * nf, nf, d_tot + j, al, s);
+        scan_exclusive_i32to64(cnts, offs, 3 * nf, d_tot + 3, al, s);
+        k_list_totals<<<1, 64, 0, s>>>(offs, nf, d_tot);
+        FMM_HIP(hipGetLastError());
         int64_t tot[3];
         FMM_HIP(hipMemcpyAsync(tot, d_tot, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
