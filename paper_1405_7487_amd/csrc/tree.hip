@@ -152,53 +152,71 @@ __device__ __forceinline__ int32_t lower_digit(const uint64_t *keys, int32_t b, 
     return b;
 }
 
-__global__ __launch_bounds__(256) void k_count_children(const uint64_t *keys, const int32_t *beg, const int32_t *end,
-                                                        int64_t cnt, int level, int ncrit, int32_t *nch)
+// Children of the cells of one level, one thread per (cell, octant digit d):
+// the thread finds where digit d starts inside the cell's body range (digits
+// are non-decreasing there, the keys being sorted), so child d holds
+// [bnd[8c+d], bnd[8c+d+1]) with bnd[8c+8] = end.  The eight lanes of a cell
+// are neighbours in one wave; a ballot over them gives the child count.
+__device__ __forceinline__ bool child_bounds(const uint64_t *keys, const int32_t *beg, const int32_t *end,
+                                             int64_t cnt, int level, int ncrit, int64_t c, int d, int32_t &lo,
+                                             int32_t &hi)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cnt) return;
-    int32_t b = beg[c], e = end[c];
-    int k = 0;
-    if (e - b > ncrit && level < kLevels) {
-        const int shift = 3 * (kLevels - level - 1);
-        int32_t prev = b;
-        for (int d = 1; d <= 8; ++d) {
-            int32_t nb = d < 8 ? lower_digit(keys, prev, e, shift, d) : e;
-            if (nb > prev) ++k;
-            prev = nb;
-        }
+    const bool valid = c < cnt;
+    int32_t b = 0, e = 0;
+    if (valid) {
+        b = beg[c];
+        e = end[c];
     }
-    nch[c] = k;
+    const bool split = valid && e - b > ncrit && level < kLevels;
+    lo = e;
+    if (split) lo = d == 0 ? b : lower_digit(keys, b, e, 3 * (kLevels - level - 1), d);
+    const int lane = threadIdx.x & 63;
+    hi = __shfl(lo, (lane & 7) == 7 ? lane : lane + 1, 64);
+    if (d == 7) hi = e;
+    return split && hi > lo;
 }
 
-__global__ __launch_bounds__(256) void k_write_children(const uint64_t *keys, const int32_t *beg, const int32_t *end,
-                                                        const uint64_t *ckey, int64_t cnt, int64_t cstart,
-                                                        int level, const int64_t *off, int64_t nstart,
-                                                        const int32_t *nch, int32_t *cbeg, int32_t *nbeg,
-                                                        int32_t *nend, int32_t *npar, uint64_t *nkey)
+__global__ __launch_bounds__(256) void k_count_children(const uint64_t *keys, const int32_t *beg, const int32_t *end,
+                                                        int64_t cnt, int level, int ncrit, int32_t *nch,
+                                                        int32_t *bnd)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = t >> 3;
+    const int d = (int)(t & 7);
+    int32_t lo, hi;
+    const bool ne = child_bounds(keys, beg, end, cnt, level, ncrit, c, d, lo, hi);
+    const uint64_t m = __ballot(ne);
+    if (c < cnt) {
+        bnd[t] = lo;
+        if (d == 0) nch[c] = __popcll((m >> (threadIdx.x & 56)) & 0xffull);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_write_children(const int32_t *end, const uint64_t *ckey, int64_t cnt,
+                                                        int64_t cstart, const int64_t *off, int64_t nstart,
+                                                        const int32_t *nch, const int32_t *bnd, int32_t *cbeg,
+                                                        int32_t *nbeg, int32_t *nend, int32_t *npar,
+                                                        uint64_t *nkey)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = t >> 3;
+    const int d = (int)(t & 7);
     if (c >= cnt) return;
-    if (nch[c] == 0) {
-        cbeg[c] = -1;
-        return;
+    const int32_t lo = bnd[t], hi = d == 7 ? end[c] : bnd[t + 1];
+    const bool split = nch[c] > 0;
+    if (d == 0) cbeg[c] = split ? (int32_t)(nstart + off[c]) : -1;
+    if (!split || hi <= lo) return;
+    // children before this one: the non-empty octants below d
+    int before = 0;
+    for (int k = 0; k < d; ++k) {
+        const int32_t a = bnd[8 * c + k], z = bnd[8 * c + k + 1];
+        before += z > a;
     }
-    const int shift = 3 * (kLevels - level - 1);
-    int32_t b = beg[c], e = end[c];
-    int64_t o = off[c];
-    cbeg[c] = (int32_t)(nstart + o);
-    int32_t prev = b;
-    for (int d = 0; d < 8; ++d) {
-        int32_t nb = d < 7 ? lower_digit(keys, prev, e, shift, d + 1) : e;
-        if (nb > prev) {
-            nbeg[o] = prev;
-            nend[o] = nb;
-            npar[o] = (int32_t)(cstart + c);
-            nkey[o] = (ckey[c] << 3) | (uint64_t)d;
-            ++o;
-        }
-        prev = nb;
-    }
+    const int64_t o = off[c] + before;
+    nbeg[o] = lo;
+    nend[o] = hi;
+    npar[o] = (int32_t)(cstart + c);
+    nkey[o] = (ckey[c] << 3) | (uint64_t)d;
 }
 
 // Lattice coordinates and centers c_d = lo_d + (i_d + 1/2) h_l, h_l = S 2^-l.
@@ -371,8 +389,9 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s)
         LvlBufs &cur = L[level];
         cur.nch = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * cur.cnt));
         cur.cbeg = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * cur.cnt));
-        k_count_children<<<grid1(cur.cnt, 256), 256, 0, s>>>(P->keys, cur.beg, cur.end, cur.cnt, level, P->ncrit,
-                                                              cur.nch);
+        int32_t *bnd = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 8 * cur.cnt));
+        k_count_children<<<grid1(8 * cur.cnt, 256), 256, 0, s>>>(P->keys, cur.beg, cur.end, cur.cnt, level,
+                                                                  P->ncrit, cur.nch, bnd);
         FMM_HIP(hipGetLastError());
         int64_t *off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * cur.cnt));
         scan_exclusive_i32to64(cur.nch, off, cur.cnt, d_total, al, s);
@@ -388,11 +407,12 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s)
             nx.par = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * total));
             nx.key = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * total));
         }
-        k_write_children<<<grid1(cur.cnt, 256), 256, 0, s>>>(P->keys, cur.beg, cur.end, cur.key, cur.cnt, start, level,
-                                                              off, nstart, cur.nch, cur.cbeg, nx.beg, nx.end, nx.par,
-                                                              nx.key);
+        k_write_children<<<grid1(8 * cur.cnt, 256), 256, 0, s>>>(cur.end, cur.key, cur.cnt, start, off, nstart,
+                                                                  cur.nch, bnd, cur.cbeg, nx.beg, nx.end, nx.par,
+                                                                  nx.key);
         FMM_HIP(hipGetLastError());
         al.free(off);
+        al.free(bnd);
         start = nstart;
         if (total == 0) break;
         L.push_back(nx);
