@@ -190,6 +190,7 @@ struct fmm_plan {
     int G = 1;                       // chunks per launch (partial sums when > 1)
     int TPC = 0;                     // tile slots per octant class in the interleaved order
     int32_t *tile_order = nullptr;   // [8*TPC] tile in slot i (class i % 8) or -1
+    std::vector<int32_t> h_tile_cls, h_tile_order;  // host copies (sources of async copies)
     int64_t ntile = 0;
     int32_t *tile_tgt = nullptr;     // [ntile*TW] target cell or -1
     int32_t *tile_cls = nullptr;     // [ntile] octant class

@@ -857,20 +857,18 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
         P->m2l_part = plan_alloc(P, esz * (size_t)P->G * P->ntile * P->TW * P->P2pad);
 
     // class-interleaved order: slot 8 i + c holds the i-th tile of class c
-    std::vector<int32_t> cls(P->ntile);
-    FMM_HIP(hipMemcpyAsync(cls.data(), P->tile_cls, sizeof(int32_t) * P->ntile, hipMemcpyDeviceToHost, s));
-    FMM_HIP(hipStreamSynchronize(s));
+    const std::vector<int32_t> &cls = P->h_tile_cls;
     std::vector<std::vector<int32_t>> by(8);
     for (int64_t t = 0; t < P->ntile; ++t) by[cls[t] & 7].push_back((int32_t)t);
     size_t tpc = 0;
     for (auto &v : by) tpc = std::max(tpc, v.size());
     P->TPC = (int)tpc;
-    std::vector<int32_t> order(8 * tpc, -1);
+    std::vector<int32_t> &order = P->h_tile_order;  // kept: the copy's source
+    order.assign(std::max<size_t>(1, 8 * tpc), -1);
     for (int c = 0; c < 8; ++c)
         for (size_t i = 0; i < by[c].size(); ++i) order[8 * i + c] = by[c][i];
     P->tile_order = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * order.size()));
     FMM_HIP(hipMemcpyAsync(P->tile_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, s));
-    FMM_HIP(hipStreamSynchronize(s));
 }
 
 void m2l_same(fmm_plan *P, hipStream_t s)

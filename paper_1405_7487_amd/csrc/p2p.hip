@@ -379,7 +379,8 @@ __global__ __launch_bounds__(256) void k_items_fill(const int32_t *leaves, int64
     if (i >= nl) return;
     const int A = leaves[i];
     const int64_t k0 = off[A], k1 = off[A + 1], nch = item_count(k1 - k0);
-    const int64_t o = si[i];
+    // one scan covers the three count arrays back to back
+    const int64_t o = si[i] - si[0];
     if (nch == 1) {
         it_leaf[o] = A;
         it_k0[o] = k0;
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(256) void k_items_fill(const int32_t *leaves, int64
         return;
     }
     const int nt = end[A] - beg[A];
-    const int64_t part = sp[i], c0 = scut[i];
+    const int64_t part = sp[i] - sp[0], c0 = scut[i] - scut[0];
     cl_leaf[c0] = A;
     cl_part[c0] = part;
     cl_n[c0] = (int32_t)nch;
@@ -397,6 +398,18 @@ __global__ __launch_bounds__(256) void k_items_fill(const int32_t *leaves, int64
         it_k0[o + c] = k0 + c * kItemEntries;
         it_k1[o + c] = min(k1, k0 + (c + 1) * kItemEntries);
         it_out[o + c] = -(part + c * nt) - 1;
+    }
+}
+
+// Totals of the three item arrays from the scan over their concatenated
+// counts (m entries each).
+__global__ void k_items_totals(const int64_t *sc, int64_t m, int64_t *tot)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t all = tot[3];
+        tot[0] = sc[m];
+        tot[1] = sc[2 * m] - sc[m];
+        tot[2] = all - sc[2 * m];
     }
 }
 
@@ -445,12 +458,13 @@ void p2p_prepare(fmm_plan *P, hipStream_t s)
     Allocator &al = P->al;
     int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 3 * (nl + 1)));
     int64_t *sc = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3 * (nl + 1)));
-    int64_t *tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3));
+    int64_t *tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 4));
     k_items_count<<<grid1(nl + 1, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->c_beg, P->c_end, cnt,
                                                       cnt + (nl + 1), cnt + 2 * (nl + 1));
     FMM_HIP(hipGetLastError());
-    for (int j = 0; j < 3; ++j)
-        scan_exclusive_i32to64(cnt + j * (nl + 1), sc + j * (nl + 1), nl + 1, tot + j, al, s);
+    scan_exclusive_i32to64(cnt, sc, 3 * (nl + 1), tot + 3, al, s);
+    k_items_totals<<<1, 64, 0, s>>>(sc, nl + 1, tot);
+    FMM_HIP(hipGetLastError());
     int64_t h[3];
     FMM_HIP(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
     FMM_HIP(hipStreamSynchronize(s));

@@ -584,12 +584,14 @@ void traverse(fmm_plan *P, hipStream_t s)
     k_fill_tiles<<<grid1(nc, 256), 256, 0, s>>>(ck, idx, nc, d_gs, d_gs + G, P->TW, P->tile_tgt, tile_pos);
     FMM_HIP(hipGetLastError());
     {
-        std::vector<int32_t> tc(std::max<int64_t>(1, tiles), 0);
+        // the plan keeps the host copy: it is the copy's source and the M2L
+        // schedule reads it
+        std::vector<int32_t> &tc = P->h_tile_cls;
+        tc.assign(std::max<int64_t>(1, tiles), 0);
         for (int g = 0; g < G; ++g)
             if (gtile[g] >= 0)
                 for (int64_t t = 0; t < (hcnt[g] + P->TW - 1) / P->TW; ++t) tc[gtile[g] + t] = g % 8;
         FMM_HIP(hipMemcpyAsync(P->tile_cls, tc.data(), sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice, s));
-        FMM_HIP(hipStreamSynchronize(s));
     }
     al.free(d_gs);
     al.free(gcnt);
@@ -630,22 +632,18 @@ void traverse(fmm_plan *P, hipStream_t s)
     int *d_err = static_cast<int *>(al.alloc(sizeof(int)));
     FMM_HIP(hipMemsetAsync(d_err, 0, sizeof(int), s));
 
-    int32_t h_root_nch = 0;
-    FMM_HIP(hipMemcpyAsync(&h_root_nch, P->c_nch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    FMM_HIP(hipStreamSynchronize(s));
     int2 *F = nullptr;
     int64_t nf = 0;
-    if (h_root_nch == 0) {
-        // single leaf: the only pair is P2P(root, root)
+    if (P->depth == 0) {
+        // the root is a leaf: the only pair is P2P(root, root)
         uint64_t *pp = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t)));
-        uint64_t zero = 0;
-        FMM_HIP(hipMemcpy(pp, &zero, sizeof(uint64_t), hipMemcpyHostToDevice));
+        FMM_HIP(hipMemsetAsync(pp, 0, sizeof(uint64_t), s));
         p2p_parts.push_back({pp, 1});
         np2p = 1;
     } else {
+        // the frontier starts from (root, root) = (0, 0)
         F = static_cast<int2 *>(al.alloc(sizeof(int2)));
-        int2 r0 = make_int2(0, 0);
-        FMM_HIP(hipMemcpy(F, &r0, sizeof(int2), hipMemcpyHostToDevice));
+        FMM_HIP(hipMemsetAsync(F, 0, sizeof(int2), s));
         nf = 1;
     }
     int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 4));

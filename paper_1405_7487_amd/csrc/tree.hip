@@ -268,6 +268,16 @@ __global__ __launch_bounds__(256) void k_gather_levels(const LevelSrc *src, int 
     key[c] = b.key[i];
 }
 
+__global__ void k_root_cell(int32_t *beg, int32_t *end, int32_t *par, uint64_t *key, int32_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        beg[0] = 0;
+        end[0] = n;
+        par[0] = -1;
+        key[0] = 0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_leaf_flags(const int32_t *nch, int64_t ncell, int32_t *flag)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -367,8 +377,6 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s)
         int64_t cnt;
     };
     std::vector<LvlBufs> L;
-    int32_t h_root[3] = {0, (int32_t)n, -1};  // outlives the copies (synchronised below)
-    uint64_t k0 = 0;
     {
         LvlBufs r{};
         r.cnt = 1;
@@ -376,11 +384,8 @@ void tree_build(fmm_plan *P, const void *x, hipStream_t s)
         r.end = static_cast<int32_t *>(al.alloc(sizeof(int32_t)));
         r.par = static_cast<int32_t *>(al.alloc(sizeof(int32_t)));
         r.key = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t)));
-        int32_t *h = h_root;
-        FMM_HIP(hipMemcpyAsync(r.beg, &h[0], sizeof(int32_t), hipMemcpyHostToDevice, s));
-        FMM_HIP(hipMemcpyAsync(r.end, &h[1], sizeof(int32_t), hipMemcpyHostToDevice, s));
-        FMM_HIP(hipMemcpyAsync(r.par, &h[2], sizeof(int32_t), hipMemcpyHostToDevice, s));
-        FMM_HIP(hipMemcpyAsync(r.key, &k0, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        k_root_cell<<<1, 64, 0, s>>>(r.beg, r.end, r.par, r.key, (int32_t)n);
+        FMM_HIP(hipGetLastError());
         L.push_back(r);
     }
     int64_t *d_total = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
