@@ -32,6 +32,37 @@ namespace {
 
 __host__ __device__ __forceinline__ int ridx_re(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
 
+// Constants of the regular recurrences, 1 / (n^2 - m^2) and -1 / (2m), for
+// n, m < 16, rounded once each (compile-time IEEE division), so per-body code
+// reads them instead of dividing.
+struct RecTab {
+    float inv_f[16][16];
+    double inv_d[16][16];
+    float half_f[16];
+    double half_d[16];
+};
+constexpr RecTab make_rec_tab()
+{
+    RecTab t{};
+    for (int n = 0; n < 16; ++n)
+        for (int m = 0; m < 16; ++m) {
+            t.inv_f[n][m] = n > m ? 1.0f / (float)(n * n - m * m) : 0.0f;
+            t.inv_d[n][m] = n > m ? 1.0 / (double)(n * n - m * m) : 0.0;
+        }
+    for (int m = 0; m < 16; ++m) {
+        t.half_f[m] = m > 0 ? -0.5f / (float)m : 0.0f;
+        t.half_d[m] = m > 0 ? -0.5 / (double)m : 0.0;
+    }
+    return t;
+}
+__constant__ RecTab c_rec = make_rec_tab();
+template <class T> __device__ __forceinline__ T rec_inv(int n, int m);
+template <> __device__ __forceinline__ float rec_inv<float>(int n, int m) { return c_rec.inv_f[n][m]; }
+template <> __device__ __forceinline__ double rec_inv<double>(int n, int m) { return c_rec.inv_d[n][m]; }
+template <class T> __device__ __forceinline__ T rec_half(int m);
+template <> __device__ __forceinline__ float rec_half<float>(int m) { return c_rec.half_f[m]; }
+template <> __device__ __forceinline__ double rec_half<double>(int m) { return c_rec.half_d[m]; }
+
 struct cd {
     double re, im;
 };
@@ -214,10 +245,10 @@ __global__ __launch_bounds__(256) void k_d2f(const double *a, float *b, int64_t 
 }
 
 // ------------------------------------------------------------------ P2M
-// One wave per leaf.  Each lane takes one body of a chunk (<= 64), writes the
-// p^2 real components of q conj(R(u / h)) to its LDS row (rolling Cartesian
-// recurrence), then each lane sums coefficient columns over the chunk in body
-// order.  Deterministic; no atomics.
+// One wave per leaf.  Each body of a chunk (<= 32) gets an LDS row of the p^2
+// real components of q conj(R(u / h)) (rolling Cartesian recurrence, its
+// orders split between two lanes), then each lane sums coefficient columns
+// over the chunk in body order.  Deterministic; no atomics.
 template <class T, class V4>
 __global__ __launch_bounds__(64) void k_p2m(const int32_t *leaves, const int32_t *beg, const int32_t *end,
                                             const int32_t *lvl, const V4 *ub, double S, int p, int P2pad, int chunk,
@@ -230,17 +261,36 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t *leaves, const int32_t
     const int P2 = p * p, stride = P2 + 1;
     const T ih = (T)ldexp(1.0 / S, lvl[c]);
     T acc[4] = {0, 0, 0, 0};  // coefficients lane + 64 q, q < 4 (p <= 16)
+    // Chunks of at most 32 bodies: the two halves of the wave take the same
+    // bodies and split the orders m, the first half m < ms and the second
+    // m >= ms, ms balancing the (p - m) terms of each.
+    const bool halves = chunk <= 32;
+    int ms = p;
+    if (halves) {
+        int w = 0;
+        ms = 0;
+        while (ms < p && 2 * (w + p - ms) <= p * (p + 1) / 2) w += p - ms++;
+    }
+    const int h = halves ? lane >> 5 : 0, bl = halves ? lane & 31 : lane;
+    const int mlo = h ? ms : 0, mhi = halves && !h ? ms : p;
     for (int32_t b0 = beg[c]; b0 < end[c]; b0 += chunk) {
         const int nb = min(chunk, end[c] - b0);
-        if (lane < nb) {
-            const V4 u = ub[b0 + lane];
+        if (bl < nb) {
+            const V4 u = ub[b0 + bl];
             const T x = u.x * ih, y = u.y * ih, z = u.z * ih, q = u.w;
             const T r2 = x * x + y * y + z * z;
-            T *row = rows + lane * stride;
+            T *row = rows + bl * stride;
             T mre = q, mim = 0;  // q R_m^m
-            for (int m = 0; m < p; ++m) {
+            for (int m = 1; m < mlo; ++m) {
+                const T f = rec_half<T>(m);
+                const T nr = (mre * x - mim * y) * f;
+                const T ni = (mre * y + mim * x) * f;
+                mre = nr;
+                mim = ni;
+            }
+            for (int m = mlo; m < mhi; ++m) {
                 if (m > 0) {
-                    const T f = (T)(-0.5) / (T)m;
+                    const T f = rec_half<T>(m);
                     const T nr = (mre * x - mim * y) * f;
                     const T ni = (mre * y + mim * x) * f;
                     mre = nr;
@@ -252,7 +302,7 @@ __global__ __launch_bounds__(64) void k_p2m(const int32_t *leaves, const int32_t
                     if (n == m) { cr = mre; ci = mim; }
                     else if (n == m + 1) { cr = z * mre; ci = z * mim; }
                     else {
-                        const T a = (T)(2 * n - 1), inv = (T)1 / (T)(n * n - m * m);
+                        const T a = (T)(2 * n - 1), inv = rec_inv<T>(n, m);
                         cr = (a * z * p1r - r2 * p2r) * inv;
                         ci = (a * z * p1i - r2 * p2i) * inv;
                     }
@@ -378,7 +428,7 @@ __device__ __forceinline__ void l2p_one(const TL *L, int p, const V4 u, T ih, T 
     T mre = 1, mim = 0;
     for (int m = 0; m < p; ++m) {
         if (m > 0) {
-            const T fct = (T)(-0.5) / (T)m;
+            const T fct = rec_half<T>(m);
             const T nr = (mre * x - mim * y) * fct;
             const T ni = (mre * y + mim * x) * fct;
             mre = nr;
@@ -391,7 +441,7 @@ __device__ __forceinline__ void l2p_one(const TL *L, int p, const V4 u, T ih, T 
             if (n == m) { cr = mre; ci = mim; }
             else if (n == m + 1) { cr = z * mre; ci = z * mim; }
             else {
-                const T a = (T)(2 * n - 1), inv = (T)1 / (T)(n * n - m * m);
+                const T a = (T)(2 * n - 1), inv = rec_inv<T>(n, m);
                 cr = (a * z * p1r - r2 * p2r) * inv;
                 ci = (a * z * p1i - r2 * p2i) * inv;
             }
@@ -532,7 +582,9 @@ void upward(fmm_plan *P, const void *ub, hipStream_t s)
     if (P->nleaf > 0) {
         const unsigned nb = (unsigned)P->nleaf;
         const size_t esz = f64 ? sizeof(double) : sizeof(float);
-        const int chunk = (int)std::min<size_t>(64, (60 * 1024) / ((P2 + 1) * esz));
+        // 32 bodies per chunk (both half-waves on the same bodies) keeps the
+        // rows small enough for many resident blocks
+        const int chunk = (int)std::min<size_t>(32, (60 * 1024) / ((P2 + 1) * esz));
         const size_t smem = (size_t)chunk * (P2 + 1) * esz;
         if (f64)
             k_p2m<double, double4><<<nb, 64, smem, s>>>(P->leaves, P->c_beg, P->c_end, P->c_lvl,
