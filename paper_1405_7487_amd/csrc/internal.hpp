@@ -247,10 +247,12 @@ namespace fmm {
 // sort.hip
 void scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s);
 void scan_exclusive_i32to64(const int32_t *in, int64_t *out, int64_t n, int64_t *total_dev, Allocator &al, hipStream_t s);
-// stable LSD radix sort of 64-bit keys (optionally with 32-bit values) on bits [0, bits)
 // Stable LSD sort of keys (and vals, when given) by key bits [lo_bit, bits).
+// The result lands in keys, unless sorted is given and there are no values:
+// then *sorted points at the sorted keys, either keys or a buffer from al
+// that the caller frees.
 void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s,
-                    int lo_bit = 0);
+                    int lo_bit = 0, uint64_t **sorted = nullptr);
 
 // tree.hip
 void tree_build(fmm_plan *P, const void *x, hipStream_t s);

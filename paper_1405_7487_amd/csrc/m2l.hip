@@ -523,6 +523,7 @@ __global__ __launch_bounds__(256) void k_gx_fill(const int64_t *off, const int64
 
 constexpr int kXMaxDl = 2;
 constexpr int kXMinPairs = 64;
+constexpr int kXStripes = 8;
 
 // Code of the key (dl, D), or -1 when the pair is left to the generic kernel.
 struct XCodes {
@@ -561,10 +562,22 @@ __global__ __launch_bounds__(256) void k_x_codes(const int32_t *tgt, const int32
         }
         if (ok) {
             cd = xc.base[dl + kXMaxDl] + (int)(((D[0] + R) * W + (D[1] + R)) * W + (D[2] + R));
-            atomicAdd(&cnt[cd], 1);
+            // one of kXStripes copies of the histogram: popular keys take
+            // millions of increments, which one counter would serialise
+            atomicAdd(&cnt[(int64_t)(blockIdx.x % kXStripes) * xc.ncode + cd], 1);
         }
     }
     code[k] = cd;
+}
+
+// cnt[c] = the sum of the kXStripes histogram copies.
+__global__ __launch_bounds__(256) void k_x_sum_stripes(int32_t *cnt, int64_t ncode)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncode) return;
+    int32_t t = cnt[c];
+    for (int k = 1; k < kXStripes; ++k) t += cnt[k * ncode + c];
+    cnt[c] = t;
 }
 
 // Sort key (key id, target) for batched pairs; generic pairs get id = nk and
@@ -915,10 +928,12 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
 
     int32_t *tgt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nx));
     int32_t *code = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nx));
-    int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * xc.ncode));
-    FMM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * xc.ncode, s));
+    int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * kXStripes * xc.ncode));
+    FMM_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * kXStripes * xc.ncode, s));
     k_x_targets<<<grid1(nc, 256), 256, 0, s>>>(P->m2lx_off, nc, tgt);
     k_x_codes<<<grid1(nx, 256), 256, 0, s>>>(tgt, P->m2lx_src, nx, P->c_lvl, P->c_ix, xc, code, cnt);
+    FMM_HIP(hipGetLastError());
+    k_x_sum_stripes<<<grid1(xc.ncode, 256), 256, 0, s>>>(cnt, xc.ncode);
     FMM_HIP(hipGetLastError());
     std::vector<int32_t> hc(xc.ncode);
     FMM_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * xc.ncode, hipMemcpyDeviceToHost, s));

@@ -239,8 +239,10 @@ void scan_exclusive_i32to64(const int32_t *in, int64_t *out, int64_t n, int64_t 
     scan_impl<int32_t>(in, out, n, total_dev, al, s);
 }
 
-void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s, int lo_bit)
+void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocator &al, hipStream_t s, int lo_bit,
+                    uint64_t **sorted)
 {
+    if (sorted) *sorted = keys;
     if (n <= 1 || bits <= lo_bit) return;
     const int npass = (bits - lo_bit + 7) / 8;
     const int64_t nb = (n + kRadixTile - 1) / kRadixTile;
@@ -267,14 +269,20 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, int64_t n, int bits, Allocato
         std::swap(ka, kb);
         std::swap(va, vb);
     }
+    bool keep_k2 = false;
     if (ka != keys) {
-        FMM_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-        if (vals) FMM_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        if (sorted && !vals) {
+            *sorted = ka;  // the caller takes the scratch buffer instead of a copy
+            keep_k2 = true;
+        } else {
+            FMM_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+            if (vals) FMM_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        }
     }
     al.free(offs);
     al.free(hist);
     if (v2) al.free(v2);
-    al.free(k2);
+    if (!keep_k2) al.free(k2);
 }
 
 }  // namespace fmm

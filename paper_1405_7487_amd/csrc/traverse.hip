@@ -454,7 +454,10 @@ static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int6
 {
     // grouped by target only (the target bits): within a target the pairs keep
     // the traversal's order, which is fixed, so the lists are deterministic
-    radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s, cbits);
+    uint64_t *const in = keys;
+    uint64_t *sk = nullptr;  // the sorted keys: keys, or the sort's own buffer
+    radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s, cbits, &sk);
+    keys = sk;
     *off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (P->ncell + 1)));
     *src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, np)));
     k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits, P->ncell, *off);
@@ -472,6 +475,7 @@ static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int6
         P->al.free(scn);
         P->al.free(per);
     }
+    if (sk != in) P->al.free(sk);
 }
 
 // Sum over P2P pairs of |A| |B| (a statistic; computed when asked for).
@@ -688,8 +692,14 @@ void traverse(fmm_plan *P, hipStream_t s)
     P->n_m2l_cross = ncross;
     P->n_p2p = np2p;
 
-    // Concatenate, sort and convert to CSR.
+    // Concatenate (unless one generation produced the whole list), sort and
+    // convert to CSR.
     auto concat = [&](std::vector<std::pair<uint64_t *, int64_t>> &parts, int64_t tot) {
+        if (parts.size() == 1) {
+            uint64_t *only = parts[0].first;
+            parts.clear();  // the caller frees it as the whole list
+            return only;
+        }
         uint64_t *all = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * std::max<int64_t>(1, tot)));
         int64_t o = 0;
         for (auto &pr : parts) {
