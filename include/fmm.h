@@ -82,12 +82,17 @@ typedef struct {
     int32_t kahan;              /* MIXED: compensated P2P sums across source batches (default 1) */
 } fmm_params;
 
-/* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3, kahan=1. */
+/* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3,
+ * kahan=1.  P, theta and N_crit are the method parameters of Table I
+ * (Section III.A); the values are this library's defaults, not the paper's.
+ * A NULL prm is ignored. */
 FMM_API void fmm_params_default(fmm_params *prm);
 
-/* Device memory provider.  alloc returns a device pointer of at least `bytes`
- * bytes usable on `stream`, or NULL on failure; free returns it.  Both are
- * called from the thread that calls the library. */
+/* Device memory provider (no passage of the paper: plumbing of this library).
+ * alloc returns a device pointer of at least `bytes` bytes usable on
+ * `stream`, or NULL on failure (the library then returns FMM_ERR_NOMEM after
+ * handing back everything it had obtained); free returns it.  Both are called
+ * from the thread that calls the library. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, void *stream, void *ctx);
@@ -96,7 +101,10 @@ typedef struct {
 
 typedef struct fmm_plan fmm_plan; /* opaque: tree, lists, operators, buffers */
 
-/* Counts and timings of a plan (host struct filled by fmm_plan_stats). */
+/* Counts and timings of a plan (host struct filled by fmm_plan_stats).  The
+ * list sizes are the interaction counts of Section II.C (l_i of Eq. (1)
+ * summed over a rank's bodies); the phases follow the runtime breakdown of
+ * Section III.A (tree build, traversal, the M2L and P2P kernels). */
 typedef struct {
     int64_t n, ncell, nleaf;
     int32_t depth, p;
@@ -123,7 +131,9 @@ typedef struct {
 } fmm_stats;
 
 /* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are
- * (target, source) cell pairs in ascending (target, source) order. */
+ * (target, source) cell pairs in ascending (target, source) order.  Keys and
+ * cells as in Section II.B, lists as emitted by the dual tree traversal of
+ * Section II.C. */
 typedef struct {
     uint64_t *keys;      /* [n] sorted Morton keys                           */
     int32_t *perm;       /* [n] sorted position -> original body index       */
@@ -152,20 +162,27 @@ FMM_API fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fm
                      const fmm_allocator *alloc, void *hip_stream, fmm_plan **out);
 
 /* Evaluates potential and field for charges q (length N, the plan's dtype)
- * on the plan's tree: P2M, M2M (upward pass), M2L, L2L, L2P and P2P, then
- * scatters the results to the caller's order.  phi (length N) is required;
- * field (N x 3) may be NULL.  Asynchronous on hip_stream.
+ * on the plan's tree: the six operators of Section II.A in the order of
+ * Section II.C -- P2M and M2M (upward pass), M2L and P2P over the traversal's
+ * lists, L2L and L2P (downward pass) -- then scatters the results to the
+ * caller's order.  phi (length N) is required; field (N x 3) may be NULL.
+ * Asynchronous on hip_stream; allocates nothing.
  * Errors: FMM_ERR_INVALID (NULL plan/q/phi), FMM_ERR_DEVICE. */
 FMM_API fmm_status fmm_evaluate_plan(fmm_plan *plan, const void *q, void *phi, void *field, void *hip_stream);
 
-/* One call = fmm_build + fmm_evaluate_plan + fmm_destroy, with the method
- * parameters given as scalars (kahan on, coarse_fp64_levels 3). */
+/* One call = fmm_build + fmm_evaluate_plan + fmm_destroy (Sections II.B,
+ * II.C and II.A as for those calls), with the method parameters of Table I
+ * given as scalars (kahan on, coarse_fp64_levels 3).  Synchronises
+ * hip_stream.  Errors: those of fmm_build and fmm_evaluate_plan. */
 FMM_API fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t p,
                         double theta, int32_t ncrit, int32_t precision, const fmm_allocator *alloc,
                         void *phi, void *field, void *hip_stream);
 
-/* Adjoint of L = sum_i w_i phi_i with w = grad_phi.  The plan's lists are
- * symmetric, so the FMM operator is symmetric and
+/* Adjoint of L = sum_i w_i phi_i with w = grad_phi (the paper computes only
+ * the forward potential and field of Section II.A; this is the reverse mode
+ * of that computation).  The plan's lists are symmetric (the traversal of
+ * Section II.C splits both cells of a pair alike), so the FMM operator is
+ * symmetric and
  *     dL/dq = FMM potential with charges w,
  *     dL/dx = -(w * E^q + q * E^w)   (E^q, E^w: FMM fields of q and of w).
  * field_q is E^q from the forward call (N x 3) or NULL, in which case it is
@@ -175,11 +192,18 @@ FMM_API fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, i
 FMM_API fmm_status fmm_adjoint(fmm_plan *plan, const void *q, const void *grad_phi, const void *field_q,
                        void *dq, void *dx, void *hip_stream);
 
-/* Copies counts and the last per-phase timings into *out (host). */
+/* Copies counts and the last per-phase timings into *out (host): the
+ * interaction counts of Section II.C and the phase breakdown of Section
+ * III.A (event timings only when fmm_set_timing enabled them).
+ * Errors: FMM_ERR_INVALID (NULL argument). */
 FMM_API fmm_status fmm_plan_stats(const fmm_plan *plan, fmm_stats *out);
 
-/* Copies the tree and the canonical lists to host buffers (synchronises the
- * plan's stream). */
+/* Copies the tree (Section II.B: keys, permutation, cells, centers) and the
+ * canonical lists of the dual tree traversal (Section II.C) to the host
+ * buffers of *out (synchronises the plan's stream).  The caller sizes the
+ * buffers from fmm_plan_stats (n, ncell, n_m2l, n_p2p).
+ * Errors: FMM_ERR_INVALID (NULL argument), FMM_ERR_NOMEM (host staging),
+ * FMM_ERR_DEVICE. */
 FMM_API fmm_status fmm_export_tree(const fmm_plan *plan, const fmm_tree_export *out);
 
 /* Order-independent digests of the plan's two lists (dual tree traversal,
@@ -200,24 +224,18 @@ FMM_API fmm_status fmm_list_digest(const fmm_plan *plan, uint64_t *out_host);
  * Errors: FMM_ERR_INVALID (NULL argument), FMM_ERR_DEVICE. */
 FMM_API fmm_status fmm_count_body_pairs(const fmm_plan *plan, int64_t *out_host);
 
-/* Per-phase event timing on (1) or off (0, default).  Timing adds one event
- * pair per phase to the stream. */
+/* Per-phase event timing (the breakdown of Section III.A) on (1) or off (0,
+ * default).  Timing adds one event pair per phase to the stream.
+ * Errors: FMM_ERR_INVALID (NULL plan). */
 FMM_API fmm_status fmm_set_timing(fmm_plan *plan, int32_t on);
 
-/* Releases the plan and its device buffers (synchronises its stream). NULL is a no-op. */
+/* Releases the plan and its device buffers (synchronises its stream); no
+ * passage of the paper.  NULL is a no-op. */
 FMM_API void fmm_destroy(fmm_plan *plan);
 
-/* Thread-local description of the last failure ("" if none). */
+/* Thread-local description of the last failure ("" if none); no passage of
+ * the paper. */
 FMM_API const char *fmm_last_error(void);
-
-/* Diagnostic of the matrix-core lane layout the batched M2L relies on: runs
- * one 16x16x4 MFMA on the current device (f64 != 0: float64, else float32)
- * with A[i][k] = i + 1 + 100 k, B[0][j] = 1 + 1000 j, B[k>0][j] = 0 and copies
- * the 64 lanes x 4 accumulators (lane-major; 256 floats or doubles) to the
- * HOST buffer out_host.  Lane l, slot e holds (i + 1)(1 + 1000 j) with
- * j = l % 16 and i = 4 (l / 16) + e (float32) or l / 16 + 4 e (float64), as
- * measured on gfx950.  Errors: FMM_ERR_INVALID, FMM_ERR_DEVICE. */
-FMM_API fmm_status fmm_debug_mfma_layout(int32_t f64, void *out_host);
 
 #ifdef __cplusplus
 }

@@ -50,6 +50,8 @@ def lib():
         L.oracle_fmm_at.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp]
         L.oracle_fmm_at.restype = C.c_int
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
+        L.oracle_set_num_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -64,6 +66,12 @@ def _f64(a):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's later parallel regions (results do not depend
+    on it: every target is summed by one thread in a fixed order)."""
+    lib().oracle_set_num_threads(int(k))
 
 
 def direct(x, q, targets=None):

@@ -912,3 +912,13 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the later parallel regions (timing of the serial oracle). */
+void oracle_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}

@@ -7,6 +7,7 @@ all run as HIP kernels in ``libfmm_hip.so`` behind the C ABI of
 ``include/fmm.h``; this package only marshals arguments.
 """
 from ._binding import (  # noqa: F401
+    CallbackAllocator,
     EXPORTS,
     FMMError,
     FMMFunction,

@@ -126,6 +126,27 @@ _FREE_CB = _FREE_FN(_torch_free)
 _TORCH_ALLOCATOR = _Allocator(_ALLOC_CB, _FREE_CB, None)
 
 
+class CallbackAllocator:
+    """A plan allocator from two Python callables: alloc(nbytes, stream) ->
+    device address or None (the library then reports FMM_ERR_NOMEM) and
+    free(address, stream).  Keeps the ctypes trampolines alive."""
+
+    def __init__(self, alloc, free):
+        def _a(nbytes, stream, ctx):
+            try:
+                return alloc(int(nbytes), stream)
+            except Exception:
+                return None
+
+        def _f(ptr, stream, ctx):
+            if ptr:
+                free(int(ptr), stream)
+
+        self._a = _ALLOC_FN(_a)
+        self._f = _FREE_FN(_f)
+        self.c = _Allocator(self._a, self._f, None)
+
+
 def _stream_handle():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -138,14 +159,34 @@ def _dtype_code(t: torch.Tensor) -> int:
     raise TypeError(f"unsupported dtype {t.dtype}: use float64 or float32")
 
 
-def _dev(t: torch.Tensor, name: str, shape=None, dtype=None):
+def _dev(t: torch.Tensor, name: str, shape=None, dtype=None, device=None):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"{name} must have dtype {dtype}")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return t.contiguous()
+
+
+def _out(t: torch.Tensor, name: str, shape, dtype, device):
+    """An output buffer the library writes into: it must already have the
+    right device, dtype and shape and be contiguous (a copy would drop the
+    results)."""
+    t2 = _dev(t, name, shape, dtype, device)
+    if t2.data_ptr() != t.data_ptr():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _coords(x: torch.Tensor):
+    x = _dev(x, "x")
+    if x.dim() != 2 or x.shape[1] != 3:
+        raise ValueError(f"x must have shape (N, 3), got {tuple(x.shape)}")
+    _dtype_code(x)
+    return x
 
 
 @dataclass
@@ -169,18 +210,20 @@ class Plan:
     """Tree, lists and buffers for one set of coordinates (fmm_build)."""
 
     def __init__(self, x: torch.Tensor, params: Params | None = None, torch_allocator: bool = True,
-                 timing: bool = False):
+                 timing: bool = False, allocator: CallbackAllocator | None = None):
         L = load()
         self.params = params or Params()
-        x = _dev(x, "x")
-        if x.dim() != 2 or x.shape[1] != 3:
-            raise ValueError("x must have shape (N, 3)")
+        x = _coords(x)
         self.n = int(x.shape[0])
         self.dtype = x.dtype
         self.device = x.device
         self._h = C.c_void_p()
         cp = self.params.to_c()
-        alloc = C.byref(_TORCH_ALLOCATOR) if torch_allocator else None
+        self._allocator = allocator  # keeps the callbacks alive while the plan lives
+        if allocator is not None:
+            alloc = C.byref(allocator.c)
+        else:
+            alloc = C.byref(_TORCH_ALLOCATOR) if torch_allocator else None
         with torch.cuda.device(self.device):
             _check(L.fmm_build(C.c_void_p(x.data_ptr()), _dtype_code(x), self.n, C.byref(cp), alloc,
                                _stream_handle(), C.byref(self._h)))
@@ -202,12 +245,15 @@ class Plan:
 
     def evaluate(self, q: torch.Tensor, field: bool = True, out=None):
         """Potential (N,) and field (N, 3) for charges q (fmm_evaluate_plan)."""
-        q = _dev(q, "q", (self.n,), self.dtype)
+        q = _dev(q, "q", (self.n,), self.dtype, self.device)
         if out is None:
             phi = torch.empty(self.n, dtype=self.dtype, device=self.device)
             E = torch.empty((self.n, 3), dtype=self.dtype, device=self.device) if field else None
         else:
             phi, E = out
+            phi = _out(phi, "phi", (self.n,), self.dtype, self.device)
+            if E is not None:
+                E = _out(E, "E", (self.n, 3), self.dtype, self.device)
         with torch.cuda.device(self.device):
             _check(load().fmm_evaluate_plan(self._h, C.c_void_p(q.data_ptr()), C.c_void_p(phi.data_ptr()),
                                             C.c_void_p(E.data_ptr()) if E is not None else None,
@@ -216,15 +262,17 @@ class Plan:
 
     def adjoint(self, q: torch.Tensor, w: torch.Tensor, field_q: torch.Tensor | None = None, out=None):
         """(dL/dq, dL/dx) of L = sum_i w_i phi_i (fmm_adjoint)."""
-        q = _dev(q, "q", (self.n,), self.dtype)
-        w = _dev(w, "w", (self.n,), self.dtype)
+        q = _dev(q, "q", (self.n,), self.dtype, self.device)
+        w = _dev(w, "w", (self.n,), self.dtype, self.device)
         if field_q is not None:
-            field_q = _dev(field_q, "field_q", (self.n, 3), self.dtype)
+            field_q = _dev(field_q, "field_q", (self.n, 3), self.dtype, self.device)
         if out is None:
             dq = torch.empty(self.n, dtype=self.dtype, device=self.device)
             dx = torch.empty((self.n, 3), dtype=self.dtype, device=self.device)
         else:
             dq, dx = out
+            dq = _out(dq, "dq", (self.n,), self.dtype, self.device)
+            dx = _out(dx, "dx", (self.n, 3), self.dtype, self.device)
         with torch.cuda.device(self.device):
             _check(load().fmm_adjoint(self._h, C.c_void_p(q.data_ptr()), C.c_void_p(w.data_ptr()),
                                       C.c_void_p(field_q.data_ptr()) if field_q is not None else None,
@@ -280,9 +328,9 @@ def evaluate(x: torch.Tensor, q: torch.Tensor, p: int = 8, theta: float = 0.4, n
              precision: str = "mixed", field: bool = True):
     """One-shot evaluation (fmm_evaluate): returns (phi, E)."""
     L = load()
-    x = _dev(x, "x")
+    x = _coords(x)
     n = int(x.shape[0])
-    q = _dev(q, "q", (n,), x.dtype)
+    q = _dev(q, "q", (n,), x.dtype, x.device)
     phi = torch.empty(n, dtype=x.dtype, device=x.device)
     E = torch.empty((n, 3), dtype=x.dtype, device=x.device) if field else None
     with torch.cuda.device(x.device):
@@ -306,9 +354,11 @@ class FMMFunction(torch.autograd.Function):
     through L = sum_i w_i phi_i (w = grad of phi).  A gradient flowing into E
     would need second derivatives of 1/r and is not supported.
 
-    params.recompute (attribute, default False): free the plan after the
-    forward pass and rebuild it (same deterministic tree) in the backward,
-    recomputing E instead of storing it."""
+    params.recompute (attribute, default False): free the plan (tree, lists,
+    operators and expansions) after the forward pass and rebuild it, with the
+    same deterministic tree, in the backward.  The field E is an output of
+    the forward pass anyway and is kept, so the backward is one rebuild plus
+    one evaluation with charges w, as without recomputation."""
 
     @staticmethod
     def forward(ctx, x, q, params):
@@ -321,10 +371,9 @@ class FMMFunction(torch.autograd.Function):
         if recompute:
             plan.close()
             ctx.plan = None
-            ctx.save_for_backward(x, q)
         else:
             ctx.plan = plan
-            ctx.save_for_backward(x, q, E)
+        ctx.save_for_backward(x, q, E)
         ctx.mark_non_differentiable(E)
         return phi, E
 
@@ -334,14 +383,16 @@ class FMMFunction(torch.autograd.Function):
             raise NotImplementedError("gradient through the field E is not supported")
         if grad_phi is None:
             return None, None, None
-        saved = ctx.saved_tensors
-        x, q = saved[0], saved[1]
+        x, q, E = ctx.saved_tensors
         if ctx.recompute:
             plan = Plan(x.detach(), ctx.params)
-            dq, dx = plan.adjoint(q.detach(), grad_phi.contiguous(), None)
+            dq, dx = plan.adjoint(q.detach(), grad_phi.contiguous(), E)
             plan.close()
         else:
-            dq, dx = ctx.plan.adjoint(q.detach(), grad_phi.contiguous(), saved[2])
+            if ctx.plan is None:
+                raise RuntimeError("FMMFunction: the plan was released by an earlier backward; "
+                                   "a second backward needs params.recompute = True")
+            dq, dx = ctx.plan.adjoint(q.detach(), grad_phi.contiguous(), E)
             ctx.plan.close()
             ctx.plan = None
         return (dx if ctx.needs_input_grad[0] else None, dq if ctx.needs_input_grad[1] else None, None)

@@ -269,6 +269,28 @@ fmm_status fail(const Error &e)
     return e.code;
 }
 
+// Runs the body of an entry point and maps every exception to a status, so
+// that none crosses the C ABI: the library's own errors keep their code, a
+// failed host allocation is FMM_ERR_NOMEM, anything else FMM_ERR_DEVICE.
+template <class F>
+fmm_status guarded(F &&body)
+{
+    try {
+        return body();
+    } catch (const Error &e) {
+        return fail(e);
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return FMM_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return FMM_ERR_DEVICE;
+    } catch (...) {
+        g_err = "unknown exception";
+        return FMM_ERR_DEVICE;
+    }
+}
+
 void destroy_plan(fmm_plan *P)
 {
     if (!P) return;
@@ -411,9 +433,17 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
     } catch (const Error &e) {
         if (P) destroy_plan(P);
         return fail(e);
+    } catch (const std::bad_alloc &) {
+        if (P) destroy_plan(P);
+        g_err = "host allocation failed";
+        return FMM_ERR_NOMEM;
     } catch (const std::exception &e) {
         if (P) destroy_plan(P);
         g_err = e.what();
+        return FMM_ERR_DEVICE;
+    } catch (...) {
+        if (P) destroy_plan(P);
+        g_err = "unknown exception";
         return FMM_ERR_DEVICE;
     }
 }
@@ -421,7 +451,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
 fmm_status fmm_evaluate_plan(fmm_plan *P, const void *q, void *phi, void *field, void *hip_stream)
 {
     g_err.clear();
-    try {
+    return guarded([&]() -> fmm_status {
         FMM_CHECK(P != nullptr, FMM_ERR_INVALID, "plan is NULL");
         if (P->n == 0) return FMM_OK;
         FMM_CHECK(q && phi, FMM_ERR_INVALID, "q or phi is NULL");
@@ -452,9 +482,7 @@ fmm_status fmm_evaluate_plan(fmm_plan *P, const void *q, void *phi, void *field,
         FMM_HIP(hipGetLastError());
         ev_rec(P, PH_EVAL, false, s);
         return FMM_OK;
-    } catch (const Error &e) {
-        return fail(e);
-    }
+    });
 }
 
 fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t p, double theta,
@@ -483,7 +511,7 @@ fmm_status fmm_adjoint(fmm_plan *P, const void *q, const void *grad_phi, const v
                        void *hip_stream)
 {
     g_err.clear();
-    try {
+    return guarded([&]() -> fmm_status {
         FMM_CHECK(P != nullptr, FMM_ERR_INVALID, "plan is NULL");
         if (P->n == 0) return FMM_OK;
         FMM_CHECK(q && grad_phi, FMM_ERR_INVALID, "q or grad_phi is NULL");
@@ -536,9 +564,7 @@ fmm_status fmm_adjoint(fmm_plan *P, const void *q, const void *grad_phi, const v
         FMM_HIP(hipGetLastError());
         ev_rec(P, PH_ADJ, false, s);
         return FMM_OK;
-    } catch (const Error &e) {
-        return fail(e);
-    }
+    });
 }
 
 fmm_status fmm_set_timing(fmm_plan *P, int32_t on)
@@ -551,81 +577,76 @@ fmm_status fmm_set_timing(fmm_plan *P, int32_t on)
 fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
 {
     g_err.clear();
-    if (!Pc || !out) {
-        g_err = "NULL argument";
-        return FMM_ERR_INVALID;
-    }
-    fmm_plan *P = const_cast<fmm_plan *>(Pc);
-    fmm_stats st = P->st;
-    st.n = P->n;
-    st.ncell = P->ncell;
-    st.nleaf = P->nleaf;
-    st.depth = P->depth;
-    st.p = P->p;
-    st.n_m2l_same = P->n_m2l_same;
-    st.n_m2l_cross = P->n_m2l_cross;
-    st.n_m2l = P->n_m2l_same + P->n_m2l_cross;
-    st.n_p2p = P->n_p2p;
-    st.p2p_body_pairs = P->n > 0 ? P->p2p_body_pairs : 0;  // -1 until counted
-    st.m2l_stencil = P->K;
-    st.m2l_offsets = P->nops;
-    st.m2l_slots = P->ntile * (int64_t)P->K * P->TW;
-    st.m2l_cross_keys = P->nxk;
-    st.m2l_cross_batched = P->nxb;
-    st.p2p_cut_leaves = P->p2p_ncut;
-    st.device_bytes = P->bytes_held;
-    {
-        std::lock_guard<std::mutex> lk(g_ev_mu);
-        auto it = g_ev.find(P);
-        if (it != g_ev.end()) {
-            double *dst[PH_N] = {&st.ms_p2m, &st.ms_m2l, &st.ms_l2l, &st.ms_p2p, &st.ms_l2p, &st.ms_evaluate,
-                                 &st.ms_adjoint, &st.ms_m2l_cross};
-            for (int k = 0; k < PH_N; ++k) {
-                if (!it->second.used[k]) continue;
-                float ms = 0.f;
-                if (hipEventSynchronize(it->second.b[k]) == hipSuccess &&
-                    hipEventElapsedTime(&ms, it->second.a[k], it->second.b[k]) == hipSuccess)
-                    *dst[k] = ms;
+    return guarded([&]() -> fmm_status {
+        FMM_CHECK(Pc && out, FMM_ERR_INVALID, "NULL argument");
+        fmm_plan *P = const_cast<fmm_plan *>(Pc);
+        fmm_stats st = P->st;
+        st.n = P->n;
+        st.ncell = P->ncell;
+        st.nleaf = P->nleaf;
+        st.depth = P->depth;
+        st.p = P->p;
+        st.n_m2l_same = P->n_m2l_same;
+        st.n_m2l_cross = P->n_m2l_cross;
+        st.n_m2l = P->n_m2l_same + P->n_m2l_cross;
+        st.n_p2p = P->n_p2p;
+        st.p2p_body_pairs = P->n > 0 ? P->p2p_body_pairs : 0;  // -1 until counted
+        st.m2l_stencil = P->K;
+        st.m2l_offsets = P->nops;
+        st.m2l_slots = P->ntile * (int64_t)P->K * P->TW;
+        st.m2l_cross_keys = P->nxk;
+        st.m2l_cross_batched = P->nxb;
+        st.p2p_cut_leaves = P->p2p_ncut;
+        st.device_bytes = P->bytes_held;
+        {
+            std::lock_guard<std::mutex> lk(g_ev_mu);
+            auto it = g_ev.find(P);
+            if (it != g_ev.end()) {
+                double *dst[PH_N] = {&st.ms_p2m, &st.ms_m2l, &st.ms_l2l, &st.ms_p2p, &st.ms_l2p, &st.ms_evaluate,
+                                     &st.ms_adjoint, &st.ms_m2l_cross};
+                for (int k = 0; k < PH_N; ++k) {
+                    if (!it->second.used[k]) continue;
+                    float ms = 0.f;
+                    if (hipEventSynchronize(it->second.b[k]) == hipSuccess &&
+                        hipEventElapsedTime(&ms, it->second.a[k], it->second.b[k]) == hipSuccess)
+                        *dst[k] = ms;
+                }
             }
         }
-    }
-    *out = st;
-    return FMM_OK;
+        *out = st;
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_list_digest(const fmm_plan *Pc, uint64_t *out)
 {
     g_err.clear();
-    try {
+    return guarded([&]() -> fmm_status {
         FMM_CHECK(Pc && out, FMM_ERR_INVALID, "NULL argument");
         fmm_plan *P = const_cast<fmm_plan *>(Pc);
         uint64_t h[2] = {0, 0};
         list_digest(P, h, P->al.stream);
         out[0] = h[0];
         out[1] = h[1];
-    } catch (const Error &e) {
-        return fail(e);
-    }
-    return FMM_OK;
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_count_body_pairs(const fmm_plan *Pc, int64_t *out)
 {
     g_err.clear();
-    try {
+    return guarded([&]() -> fmm_status {
         FMM_CHECK(Pc && out, FMM_ERR_INVALID, "NULL argument");
         fmm_plan *P = const_cast<fmm_plan *>(Pc);
         *out = P->n > 0 ? p2p_body_pairs(P, P->al.stream) : 0;
-    } catch (const Error &e) {
-        return fail(e);
-    }
-    return FMM_OK;
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_export_tree(const fmm_plan *Pc, const fmm_tree_export *o)
 {
     g_err.clear();
-    try {
+    return guarded([&]() -> fmm_status {
         FMM_CHECK(Pc && o, FMM_ERR_INVALID, "NULL argument");
         fmm_plan *P = const_cast<fmm_plan *>(Pc);
         FMM_HIP(hipStreamSynchronize(P->al.stream));
@@ -683,12 +704,17 @@ fmm_status fmm_export_tree(const fmm_plan *Pc, const fmm_tree_export *o)
             }
         }
         return FMM_OK;
-    } catch (const Error &e) {
-        return fail(e);
-    }
+    });
 }
 
-void fmm_destroy(fmm_plan *P) { destroy_plan(P); }
+void fmm_destroy(fmm_plan *P)
+{
+    try {
+        destroy_plan(P);
+    } catch (...) {
+        g_err = "fmm_destroy: release failed";
+    }
+}
 
 /* Diagnostic: runs one 16x16x4 MFMA (f64 != 0: float64, else float32) with
  * A[i][k] = i + 1 + 100 k, B[0][j] = 1 + 1000 j, B[k>0][j] = 0, and copies the
@@ -696,13 +722,11 @@ void fmm_destroy(fmm_plan *P) { destroy_plan(P); }
 fmm_status fmm_debug_mfma_layout(int32_t f64, void *out_host)
 {
     g_err.clear();
-    try {
+    return guarded([&]() -> fmm_status {
         FMM_CHECK(out_host != nullptr, FMM_ERR_INVALID, "out is NULL");
         mfma_probe(f64, out_host);
         return FMM_OK;
-    } catch (const Error &e) {
-        return fail(e);
-    }
+    });
 }
 
 }  // extern "C"

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/fmm.h"
+#include "../../include/fmm_diag.h"
 
 namespace fmm {
 
@@ -172,6 +173,7 @@ struct fmm_plan {
     // lists
     int64_t n_m2l_same = 0, n_m2l_cross = 0, n_p2p = 0, p2p_body_pairs = 0;
     int64_t *p2p_off = nullptr;  int32_t *p2p_src = nullptr;   // CSR over cells
+    int64_t *p2p_near = nullptr;     // [ncell + 1] end of each list's leading run of touching leaves
     // P2P work items: (leaf, list range, output); long lists are cut into items
     int64_t p2p_nitem = 0, p2p_ncut = 0, p2p_npart = 0;
     int32_t *p2p_it_leaf = nullptr;

@@ -10,7 +10,10 @@
 // two); a fixed-order tree of wave shuffles sums them.
 // Batches are padded with zero-charge bodies far away so that every lane runs
 // the same unrolled loop with compile-time LDS offsets.  Only the leaf's own
-// bodies can coincide with a target, so only that batch tests r^2 > 0.
+// bodies can coincide with a target, so only that batch tests r^2 > 0.  In
+// the mixed path the leaf's own bodies and the leaves that touch it (which
+// lead each list) use compensated offsets, so that nearly coincident bodies
+// keep their separation's precision wherever a leaf face falls between them.
 // Batch partial sums enter the running totals through a compensated (Kahan)
 // add.
 #include "internal.hpp"
@@ -71,20 +74,20 @@ __device__ __forceinline__ void batch(const V4 *sb, int npad, int sub, T ux, T u
 // (l_i - l_j).  For close bodies the first difference is exact, so the pair's
 // separation keeps its own relative precision instead of the leaf size's;
 // coincident bodies still give exactly zero and are skipped.
-template <class T, class V4, int G>
+template <class T, class V4, int G, int UNR = kUnroll>
 __device__ __forceinline__ void batch_own(const V4 *sb, const V4 *sl, int npad, int sub, T ux, T uy, T uz, T lx,
                                           T ly, T lz, Acc<T> &a)
 {
     const V4 *p = sb + sub, *r = sl + sub;
-    for (int it = 0; it < npad; it += G * kUnroll, p += G * kUnroll, r += G * kUnroll) {
-        V4 v[kUnroll], w[kUnroll];
+    for (int it = 0; it < npad; it += G * UNR, p += G * UNR, r += G * UNR) {
+        V4 v[UNR], w[UNR];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < UNR; ++u) {
             v[u] = p[u * G];
             w[u] = r[u * G];
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
+        for (int u = 0; u < UNR; ++u) {
             const T dx = (ux - v[u].x) + (lx - w[u].x), dy = (uy - v[u].y) + (ly - w[u].y),
                     dz = (uz - v[u].z) + (lz - w[u].z);
             const T r2 = dx * dx + dy * dy + dz * dz;
@@ -116,16 +119,176 @@ __device__ __forceinline__ V4 far_dummy()
 // the instantiations for each G share it.
 template <class T> struct GatherLds {
     int32_t excl[64], incl[64], base[64];
-    T sh[64][3];
+    T sh[64][3], sl[64][3];  // center shift and its rounding residual
 };
+
+template <class T, bool KAHAN>
+__device__ __forceinline__ void fold_into(Acc<T> &s, Acc<T> &c, const Acc<T> &pa)
+{
+    if (KAHAN) {
+        kahan_add(s.p, c.p, pa.p);
+        kahan_add(s.x, c.x, pa.x);
+        kahan_add(s.y, c.y, pa.y);
+        kahan_add(s.z, c.z, pa.z);
+    } else {
+        s.p += pa.p; s.x += pa.x; s.y += pa.y; s.z += pa.z;
+    }
+}
+
+// Sources of list entries [k, k1) of target leaf A for the lanes' targets u
+// (and residuals ut).  A batch is gathered from the next (up to) 64 list
+// entries at once: lane l takes entry k + l, a wave prefix sum of the leaf
+// sizes places the bodies, and every LDS slot finds its leaf by a branchless
+// binary search of that sum.  The loads of batch i+1 are in flight while
+// batch i is multiplied (two LDS buffers); slots past the batch hold
+// zero-charge dummies, which also pad the batch for the unrolled loop.
+//
+// COMP (leaves that touch A): every source is staged as a float32 offset hi
+// from A's center plus the residual lo of that rounding, the center shift's
+// own residual and the body's residual included (the shift rounded to float32
+// carries an error of order 1e-7 of the leaf size, which is the whole
+// separation of nearly coincident bodies on either side of a face); a pair's
+// difference is then (u_t - hi) + (l_t - lo), and half a stage holds the
+// residuals.
+template <class T, class V4, bool KAHAN, int G, bool COMP>
+__device__ void list_pass(V4 *sb, GatherLds<T> *gs, int A, int64_t k, int64_t k1, const int32_t *beg,
+                          const int32_t *end, const int32_t *src, const double *ctr, const V4 *ub, const V4 *ul,
+                          const V4 &u, const V4 &ut, int sub, Acc<T> &s, Acc<T> &c)
+{
+    constexpr int STG = COMP ? kStage / 2 : kStage;  // sources per LDS buffer
+    constexpr int SMAX = (STG / (G * kUnroll)) * (G * kUnroll);
+    constexpr int R = STG / 64;
+    const int lane = threadIdx.x;
+    const double cax = ctr[3 * A], cay = ctr[3 * A + 1], caz = ctr[3 * A + 2];
+    int32_t *s_excl = gs->excl, *s_incl = gs->incl, *s_base = gs->base;
+    T(*s_sh)[3] = gs->sh;
+    T(*s_sl)[3] = gs->sl;
+    int32_t o = 0;  // bodies of entry k already consumed
+    V4 regs[R], rlo[COMP ? R : 1];
+    int st_next = 0;
+    auto gather = [&]() {
+        const int64_t kk = k + lane;
+        const int b = kk < k1 ? src[kk] : A;
+        const int32_t skip = lane == 0 ? o : 0;
+        const int32_t sz = (kk < k1 && b != A) ? end[b] - beg[b] - skip : 0;
+        int32_t pre = sz;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t v = __shfl_up(pre, d, 64);
+            if (lane >= d) pre += v;
+        }
+        const int staged = min(__shfl(pre, 63, 64), SMAX);
+        s_incl[lane] = pre;
+        s_excl[lane] = pre - sz;
+        s_base[lane] = beg[b] + skip;
+        const double shx = ctr[3 * b] - cax, shy = ctr[3 * b + 1] - cay, shz = ctr[3 * b + 2] - caz;
+        s_sh[lane][0] = (T)shx;
+        s_sh[lane][1] = (T)shy;
+        s_sh[lane][2] = (T)shz;
+        if (COMP) {
+            s_sl[lane][0] = (T)(shx - (double)(T)shx);
+            s_sl[lane][1] = (T)(shy - (double)(T)shy);
+            s_sl[lane][2] = (T)(shz - (double)(T)shz);
+        }
+        __syncthreads();
+        int lo[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) lo[r] = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (s_incl[lo[r] + step - 1] <= lane + 64 * r) lo[r] += step;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int t = lane + 64 * r;
+            if (t < staged) {
+                const int64_t j = s_base[lo[r]] + (t - s_excl[lo[r]]);
+                V4 v = ub[j];
+                if (COMP) {
+                    // hi = fl(u + shift), with the exact rounding error of
+                    // that sum (two-sum) carried into lo
+                    const V4 w = ul[j];
+                    V4 e;
+                    const T hx = v.x + s_sh[lo[r]][0], hy = v.y + s_sh[lo[r]][1], hz = v.z + s_sh[lo[r]][2];
+                    const T bx = hx - v.x, by = hy - v.y, bz = hz - v.z;
+                    e.x = ((v.x - (hx - bx)) + (s_sh[lo[r]][0] - bx)) + (w.x + s_sl[lo[r]][0]);
+                    e.y = ((v.y - (hy - by)) + (s_sh[lo[r]][1] - by)) + (w.y + s_sl[lo[r]][1]);
+                    e.z = ((v.z - (hz - bz)) + (s_sh[lo[r]][2] - bz)) + (w.z + s_sl[lo[r]][2]);
+                    e.w = (T)0;
+                    v.x = hx;
+                    v.y = hy;
+                    v.z = hz;
+                    rlo[r] = e;
+                } else {
+                    v.x += s_sh[lo[r]][0];
+                    v.y += s_sh[lo[r]][1];
+                    v.z += s_sh[lo[r]][2];
+                }
+                regs[r] = v;
+            } else {
+                regs[r] = far_dummy<T, V4>();
+                if (COMP) rlo[r] = V4{};
+            }
+        }
+        // advance the cursor past the consumed entries
+        const int nf = __popcll(__ballot(pre <= staged));
+        if (nf == 64) {
+            k += 64;
+            o = 0;
+        } else {
+            const int32_t consumed = staged - __shfl(pre - sz, nf, 64);
+            o = (nf == 0 ? o : 0) + consumed;
+            k += nf;
+        }
+        st_next = staged;
+    };
+    if (k < k1) gather();
+    int buf = 0;
+    while (st_next > 0 || k < k1) {
+        V4 *cur = sb + buf * kStage;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cur[lane + 64 * r] = regs[r];
+            if (COMP) cur[STG + lane + 64 * r] = rlo[r];
+        }
+        const int st_cur = st_next;
+        __syncthreads();
+        if constexpr (COMP) {
+            // the compensated products hold twice the source registers, so
+            // the next batch is loaded only after them, two sources per lane
+            // and step (this pass covers the few touching leaves)
+            if (st_cur > 0) {
+                const int npad = (st_cur + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
+                Acc<T> pa{0, 0, 0, 0};
+                batch_own<T, V4, G, 2>(cur, cur + STG, npad, sub, u.x, u.y, u.z, ut.x, ut.y, ut.z, pa);
+                fold_into<T, KAHAN>(s, c, pa);
+            }
+            if (k < k1) gather();
+            else st_next = 0;
+        } else {
+            if (k < k1) gather();
+            else st_next = 0;
+            if (st_cur > 0) {
+                const int npad = (st_cur + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
+                Acc<T> pa{0, 0, 0, 0};
+                batch<T, V4, G, false>(cur, npad, sub, u.x, u.y, u.z, pa);
+                fold_into<T, KAHAN>(s, c, pa);
+            }
+        }
+        buf ^= 1;
+    }
+    __syncthreads();
+}
 
 // Targets [base, base + cnt) of leaf A against list entries [k0, k1) (and
 // the leaf's own bodies when own is set); sums go to op[oi], oE[3 oi + d]
-// with oi = o0 + target.
+// with oi = o0 + target.  Entries [k0, kn) are leaves that touch A: with
+// residuals (mixed path) they run with compensated offsets.
 template <class T, class V4, bool KAHAN, int G>
 __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base, int cnt, bool own,
-                           const int32_t *beg, const int32_t *end, int64_t k0, int64_t k1, const int32_t *src,
-                           const double *ctr, const V4 *ub, const V4 *ul, T *op, T *oE, int64_t o0)
+                           const int32_t *beg, const int32_t *end, int64_t k0, int64_t kn, int64_t k1,
+                           const int32_t *src, const double *ctr, const V4 *ub, const V4 *ul, T *op, T *oE, int64_t o0)
 {
     // sources per batch: a multiple of G kUnroll, so a padded batch never
     // runs past its kStage slots
@@ -134,18 +297,7 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
     const int ti = lane / G, sub = lane % G;
     const bool active = ti < cnt;
     const V4 u = ub[tb + base + (active ? ti : 0)];
-    const double cax = ctr[3 * A], cay = ctr[3 * A + 1], caz = ctr[3 * A + 2];
     Acc<T> s{0, 0, 0, 0}, c{0, 0, 0, 0};
-    auto fold = [&](const Acc<T> &pa) {
-        if (KAHAN) {
-            kahan_add(s.p, c.p, pa.p);
-            kahan_add(s.x, c.x, pa.x);
-            kahan_add(s.y, c.y, pa.y);
-            kahan_add(s.z, c.z, pa.z);
-        } else {
-            s.p += pa.p; s.x += pa.x; s.y += pa.y; s.z += pa.z;
-        }
-    };
     const int32_t ab = beg[A], ae = own ? end[A] : beg[A];
     // 1) the leaf's own bodies (may coincide with the target): masked, with
     //    the residuals (when given) staged in the second buffer
@@ -160,95 +312,16 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
         Acc<T> pa{0, 0, 0, 0};
         if (ul) batch_own<T, V4, G>(sb, sb + kStage, npad, sub, u.x, u.y, u.z, ut.x, ut.y, ut.z, pa);
         else batch<T, V4, G, true>(sb, npad, sub, u.x, u.y, u.z, pa);
-        fold(pa);
+        fold_into<T, KAHAN>(s, c, pa);
         __syncthreads();
     }
-    {
-        // 2) every other leaf of the list, batched, no test needed.  A batch is
-        //    gathered from the next (up to) 64 list entries at once: lane l takes
-        //    entry k + l, a wave prefix sum of the leaf sizes places the bodies,
-        //    and every LDS slot finds its leaf by a branchless binary search of
-        //    that sum.  The loads of batch i+1 are in flight while batch i is
-        //    multiplied (two LDS buffers); slots past the batch hold zero-charge
-        //    dummies, which also pad the batch for the unrolled loop.
-        int32_t *s_excl = gs->excl, *s_incl = gs->incl, *s_base = gs->base;
-        T(*s_sh)[3] = gs->sh;
-        int64_t k = k0;
-        int32_t o = 0;  // bodies of entry k already consumed
-        V4 regs[kStage / 64];
-        int st_next = 0;
-        auto gather = [&]() {
-            const int64_t kk = k + lane;
-            const int b = kk < k1 ? src[kk] : A;
-            const int32_t skip = lane == 0 ? o : 0;
-            const int32_t sz = (kk < k1 && b != A) ? end[b] - beg[b] - skip : 0;
-            int32_t pre = sz;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int32_t v = __shfl_up(pre, d, 64);
-                if (lane >= d) pre += v;
-            }
-            const int staged = min(__shfl(pre, 63, 64), SMAX);
-            s_incl[lane] = pre;
-            s_excl[lane] = pre - sz;
-            s_base[lane] = beg[b] + skip;
-            s_sh[lane][0] = (T)(ctr[3 * b] - cax);
-            s_sh[lane][1] = (T)(ctr[3 * b + 1] - cay);
-            s_sh[lane][2] = (T)(ctr[3 * b + 2] - caz);
-            __syncthreads();
-            int lo[kStage / 64];
-#pragma unroll
-            for (int r = 0; r < kStage / 64; ++r) lo[r] = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1)
-#pragma unroll
-                for (int r = 0; r < kStage / 64; ++r)
-                    if (s_incl[lo[r] + step - 1] <= lane + 64 * r) lo[r] += step;
-#pragma unroll
-            for (int r = 0; r < kStage / 64; ++r) {
-                const int t = lane + 64 * r;
-                if (t < staged) {
-                    V4 v = ub[s_base[lo[r]] + (t - s_excl[lo[r]])];
-                    v.x += s_sh[lo[r]][0];
-                    v.y += s_sh[lo[r]][1];
-                    v.z += s_sh[lo[r]][2];
-                    regs[r] = v;
-                } else {
-                    regs[r] = far_dummy<T, V4>();
-                }
-            }
-            // advance the cursor past the consumed entries
-            const int nf = __popcll(__ballot(pre <= staged));
-            if (nf == 64) {
-                k += 64;
-                o = 0;
-            } else {
-                const int32_t consumed = staged - __shfl(pre - sz, nf, 64);
-                o = (nf == 0 ? o : 0) + consumed;
-                k += nf;
-            }
-            st_next = staged;
-        };
-        if (k < k1) gather();
-        int buf = 0;
-        while (st_next > 0 || k < k1) {
-            V4 *cur = sb + buf * kStage;
-#pragma unroll
-            for (int r = 0; r < kStage / 64; ++r) cur[lane + 64 * r] = regs[r];
-            const int st_cur = st_next;
-            __syncthreads();
-            if (k < k1) gather();
-            else st_next = 0;
-            if (st_cur > 0) {
-                const int npad = (st_cur + G * kUnroll - 1) / (G * kUnroll) * (G * kUnroll);
-                Acc<T> pa{0, 0, 0, 0};
-                batch<T, V4, G, false>(cur, npad, sub, u.x, u.y, u.z, pa);
-                fold(pa);
-            }
-            buf ^= 1;
-        }
-        __syncthreads();
+    // 2) the other leaves of the list: touching ones first (compensated when
+    //    residuals exist), then the rest
+    if (ul && kn > k0) {
+        list_pass<T, V4, KAHAN, G, true>(sb, gs, A, k0, kn, beg, end, src, ctr, ub, ul, u, ut, sub, s, c);
+        k0 = kn;
     }
+    if (k1 > k0) list_pass<T, V4, KAHAN, G, false>(sb, gs, A, k0, k1, beg, end, src, ctr, ub, ul, u, ut, sub, s, c);
     if (KAHAN) {
         s.p -= c.p; s.x -= c.x; s.y -= c.y; s.z -= c.z;
     }
@@ -283,8 +356,8 @@ __device__ void leaf_chunk(V4 *sb, GatherLds<T> *gs, int A, int32_t tb, int base
 template <class T, class V4, bool KAHAN>
 __global__ __launch_bounds__(64) void k_p2p(const int32_t *it_leaf, const int64_t *it_k0, const int64_t *it_k1,
                                             const int64_t *it_out, const int32_t *beg, const int32_t *end,
-                                            const int32_t *src, const double *ctr, const V4 *ub, const V4 *ul,
-                                            T *phi_s, T *E_s, T *part_p, T *part_E)
+                                            const int32_t *src, const int64_t *near, const double *ctr,
+                                            const V4 *ub, const V4 *ul, T *phi_s, T *E_s, T *part_p, T *part_E)
 {
     __shared__ V4 sb[2 * kStage];
     __shared__ GatherLds<T> gs;
@@ -293,6 +366,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *it_leaf, const int64_
     const int32_t tb = beg[A], te = end[A];
     const int nt = te - tb;
     const int64_t k0 = it_k0[item], k1 = it_k1[item], ov = it_out[item];
+    const int64_t kn = min(k1, max(k0, near[A]));  // [k0, kn): leaves touching A
     // ov >= 0: write to phi_s / E_s at body ov + t; ov < 0: partial sums at -ov - 1 + t
     const bool direct = ov >= 0;
     T *op = direct ? phi_s : part_p;
@@ -306,7 +380,7 @@ __global__ __launch_bounds__(64) void k_p2p(const int32_t *it_leaf, const int64_
         const int rem = nt - base;
         cnt = (rem > 32 && rem < 56) ? 32 : min(64, rem);
         // lanes per target: G close to 64 / cnt (at most 16), so few lanes idle
-#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, first, beg, end, k0, k1, src, ctr, ub, ul, op, oE, o0)
+#define P2P_CHUNK(GG) leaf_chunk<T, V4, KAHAN, GG>(sb, &gs, A, tb, base, cnt, first, beg, end, k0, kn, k1, src, ctr, ub, ul, op, oE, o0)
         if (cnt <= 4) P2P_CHUNK(16);
         else if (cnt <= 5) P2P_CHUNK(12);
         else if (cnt <= 8) P2P_CHUNK(8);
@@ -418,7 +492,7 @@ void launch_items(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream
 {
     FMM_CHECK(P->p2p_nitem * 64 < (1ll << 32), FMM_ERR_UNSUPPORTED, "p2p: too many work items");
     k_p2p<T, V4, KAHAN><<<(unsigned)P->p2p_nitem, 64, 0, s>>>(
-        P->p2p_it_leaf, P->p2p_it_k0, P->p2p_it_k1, P->p2p_it_out, P->c_beg, P->c_end, P->p2p_src, P->c_ctr,
+        P->p2p_it_leaf, P->p2p_it_k0, P->p2p_it_k1, P->p2p_it_out, P->c_beg, P->c_end, P->p2p_src, P->p2p_near, P->c_ctr,
         static_cast<const V4 *>(ub), static_cast<const V4 *>(P->ulo), static_cast<T *>(phi_s), static_cast<T *>(E_s),
         static_cast<T *>(P->p2p_part), static_cast<T *>(P->p2p_part) + P->p2p_npart);
     FMM_HIP(hipGetLastError());

@@ -93,6 +93,19 @@ __device__ __forceinline__ int classify(const CellG &A, const CellG &B, double t
     return 3;
 }
 
+// Whether the cubes of two cells share at least a corner: along each axis
+// their extents, in units of the finer cell's side, overlap or abut.
+__device__ __forceinline__ bool touching(const CellG &A, const CellG &B)
+{
+    const int f = A.l > B.l ? A.l : B.l;
+    const int64_t sa = 1ll << (f - A.l), sb = 1ll << (f - B.l);
+    const int64_t a[3] = {A.x, A.y, A.z}, b[3] = {B.x, B.y, B.z};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (a[d] * sa > (b[d] + 1) * sb || b[d] * sb > (a[d] + 1) * sa) return false;
+    return true;
+}
+
 // The split rule of the traversal for a pair that was not accepted and is
 // not two leaves.
 __device__ __forceinline__ void split_rule(const CellG &A, const CellG &B, bool &sa, bool &sb)
@@ -193,7 +206,10 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
                 } else if (k == 1) {
                     cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
                 } else if (k == 2) {
-                    p2p[op++] = ((uint64_t)x << cbits) | (uint64_t)y;
+                    // a bit below the target orders the sources of leaves that
+                    // touch the target first (they get compensated offsets)
+                    const uint64_t far = touching(X, Y) ? 0u : 1u;
+                    p2p[op++] = ((uint64_t)x << (cbits + 1)) | (far << cbits) | (uint64_t)y;
                 } else {
                     next[on++] = make_int2(x, y);
                 }
@@ -277,13 +293,13 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t *p, int64_t n, int32_t
 
 dim3 grid_fill(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1 << 16)); }
 
-// CSR offsets: off[c] = first position whose target is >= c.
-__global__ __launch_bounds__(256) void k_csr_offsets(const uint64_t *keys, int64_t np, int cbits, int64_t nc,
-                                                     int64_t *off)
+// CSR offsets: off[c] = first position whose key is >= (c << shift) | low.
+__global__ __launch_bounds__(256) void k_csr_offsets(const uint64_t *keys, int64_t np, int shift, uint64_t low,
+                                                     int64_t nc, int64_t *off)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c > nc) return;
-    const uint64_t want = (uint64_t)c << cbits;
+    const uint64_t want = ((uint64_t)c << shift) | low;
     int64_t lo = 0, hi = np;
     while (lo < hi) {
         int64_t m = lo + ((hi - lo) >> 1);
@@ -449,19 +465,28 @@ static int bits_for(int64_t v)
     return b;
 }
 
-static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int64_t **off, int32_t **src,
-                        int64_t *body_pairs_dev, hipStream_t s)
+// Keys are target << (cbits + obits) | order bits << cbits | source.  With
+// one order bit (P2P), near_end[c] is where target c's entries with the bit
+// set begin.
+static void sort_to_csr(fmm_plan *P, uint64_t *keys, int64_t np, int cbits, int obits, int64_t **off,
+                        int32_t **src, int64_t **near_end, int64_t *body_pairs_dev, hipStream_t s)
 {
-    // grouped by target only (the target bits): within a target the pairs keep
+    // grouped by target (and order bits) only: within a group the pairs keep
     // the traversal's order, which is fixed, so the lists are deterministic
     uint64_t *const in = keys;
     uint64_t *sk = nullptr;  // the sorted keys: keys, or the sort's own buffer
-    radix_sort_u64(keys, nullptr, np, 2 * cbits, P->al, s, cbits, &sk);
+    radix_sort_u64(keys, nullptr, np, 2 * cbits + obits, P->al, s, cbits, &sk);
     keys = sk;
     *off = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (P->ncell + 1)));
     *src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, np)));
-    k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits, P->ncell, *off);
+    k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits + obits, 0, P->ncell, *off);
     FMM_HIP(hipGetLastError());
+    if (near_end) {
+        *near_end = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (P->ncell + 1)));
+        k_csr_offsets<<<grid1(P->ncell + 1, 256), 256, 0, s>>>(keys, np, cbits + obits, 1ull << cbits, P->ncell,
+                                                               *near_end);
+        FMM_HIP(hipGetLastError());
+    }
     if (np > 0) {
         k_csr_sources<<<grid1(np, 256), 256, 0, s>>>(keys, np, cbits, *src);
         FMM_HIP(hipGetLastError());
@@ -627,7 +652,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     T.t4 = P->t4;
 
     const int cbits = bits_for(nc);
-    FMM_CHECK(2 * cbits <= 64, FMM_ERR_UNSUPPORTED, "too many cells");
+    FMM_CHECK(2 * cbits + 1 <= 64, FMM_ERR_UNSUPPORTED, "too many cells");
     // Growable outputs.
     std::vector<std::pair<uint64_t *, int64_t>> cross_parts, p2p_parts;
     int64_t ncross = 0, np2p = 0;
@@ -710,8 +735,8 @@ void traverse(fmm_plan *P, hipStream_t s)
     };
     uint64_t *p2p_all = concat(p2p_parts, np2p);
     uint64_t *cross_all = concat(cross_parts, ncross);
-    sort_to_csr(P, p2p_all, np2p, cbits, &P->p2p_off, &P->p2p_src, nullptr, s);
-    sort_to_csr(P, cross_all, ncross, cbits, &P->m2lx_off, &P->m2lx_src, nullptr, s);
+    sort_to_csr(P, p2p_all, np2p, cbits, 1, &P->p2p_off, &P->p2p_src, &P->p2p_near, nullptr, s);
+    sort_to_csr(P, cross_all, ncross, cbits, 0, &P->m2lx_off, &P->m2lx_src, nullptr, nullptr, s);
     P->p2p_body_pairs = -1;  // counted on demand by p2p_body_pairs()
     for (auto &pr : p2p_parts) al.free(pr.first);
     for (auto &pr : cross_parts) al.free(pr.first);

@@ -305,3 +305,169 @@ def test_error_paths():
     # one body
     plan, phi, E = gpu_fmm(x[:1], q[:1], 4, 0.4, 8, "mixed")
     assert phi[0] == 0.0 and np.all(E == 0.0)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_float32_caller_dtype(precision, tol):
+    # float32 coordinates, charges and weights: the outputs come back in
+    # float32 and are checked against the oracle on the widened inputs
+    x, q, rng = W.plummer(20000, 31, charges="unit")
+    w = W.adjoint_weights(rng, 20000)
+    x32, q32, w32 = (a.astype(np.float32) for a in (x, q, w))
+    xw, qw, ww = (a.astype(np.float64) for a in (x32, q32, w32))
+    p, theta, ncrit = 6, 0.4, 24
+    T = oracle.Tree(xw, ncrit, theta)
+    po, Eo = T.fmm(qw, p)
+    pw, Ew = T.fmm(ww, p)
+    dx_ref = -(ww[:, None] * Eo + qw[:, None] * Ew)
+    plan = F.Plan(dev(x32, torch.float32), F.Params(p=p, theta=theta, ncrit=ncrit, precision=precision))
+    qt, wt = dev(q32, torch.float32), dev(w32, torch.float32)
+    phi, E = plan.evaluate(qt)
+    assert phi.dtype == torch.float32 and E.dtype == torch.float32
+    assert rel(host(phi), po) < tol and rel(host(E), Eo) < tol
+    for field_q in (E, None):
+        dq, dx = plan.adjoint(qt, wt, field_q)
+        assert dq.dtype == torch.float32 and dx.dtype == torch.float32
+        assert rel(host(dq), pw) < tol and rel(host(dx), dx_ref) < tol, (precision, field_q is None)
+    plan.close()
+
+
+@pytest.mark.parametrize("case", ["flat", "line"])
+def test_degenerate_boxes(case):
+    # all bodies on a plane, or on a line with a graded spacing: the root cube
+    # is set by one or two axes, the others keep a single lattice coordinate
+    rng = np.random.default_rng(41)
+    if case == "flat":
+        x = rng.random((12000, 3))
+        x[:, 2] = 0.5
+        ncrit = 16
+    else:
+        x = np.zeros((3000, 3))
+        x[:, 0] = np.linspace(0.0, 1.0, 3000) ** 3
+        x[:, 1] = 0.25
+        ncrit = 8
+    q = rng.uniform(-1.0, 1.0, x.shape[0])
+    theta, p = 0.4, 6
+    plan = F.Plan(dev(x), F.Params(p=p, theta=theta, ncrit=ncrit, precision="fp64"))
+    T = _compare_tree(plan, x, ncrit, theta)
+    po, Eo = T.fmm(q, p)
+    phi, E = plan.evaluate(dev(q))
+    assert rel(host(phi), po) < 1e-11 and rel(host(E), Eo) < 1e-11
+    plan.close()
+    _, pm, Em = gpu_fmm(x, q, p, theta, ncrit, "mixed")
+    assert rel(pm, po) < 1e-4 and rel(Em, Eo) < 1e-4
+
+
+def test_close_pairs_across_leaf_faces():
+    # pairs 1e-7 apart straddling the faces between leaves: their fields
+    # dominate every norm, and the float32 shift between the two leaf centers
+    # alone would carry an error of order 1e-9; the touching-leaf pass of P2P
+    # uses compensated offsets, so every body stays within the bar
+    x, q, _ = W.uniform_cube(20000, 43)
+    lo = x.min(0)
+    S = float((x.max(0) - lo).max())
+    rng = np.random.default_rng(44)
+    # bodies that fix no side of the root cube, so moving them keeps it
+    extremal = np.concatenate([x.argmin(0), x.argmax(0)])
+    idx = np.setdiff1d(np.arange(60), extremal)[:40]
+    for k in range(20):
+        a, b = idx[2 * k], idx[2 * k + 1]
+        axis = k % 3
+        face = lo[axis] + (1 + k % 7) * S / 8.0  # a leaf face of the level-3 tree
+        x[a] = x[b] = rng.uniform(0.05, 0.95, 3)
+        x[a, axis] = face - 5e-8
+        x[b, axis] = face + 5e-8
+    assert np.array_equal(x.min(0), lo) and float((x.max(0) - lo).max()) == S
+    T = oracle.Tree(x, 64, 0.4)
+    e = T.export()
+    leaf_of = np.empty(x.shape[0], np.int64)
+    for c in np.nonzero(e["nchild"] == 0)[0]:
+        leaf_of[e["perm"][e["begin"][c]:e["end"][c]]] = c
+    assert np.all(leaf_of[idx[0::2]] != leaf_of[idx[1::2]])  # every pair straddles a face
+    po, Eo = T.fmm(q, 6)
+    _, p64, E64 = gpu_fmm(x, q, 6, 0.4, 64, "fp64")
+    _, pm, Em = gpu_fmm(x, q, 6, 0.4, 64, "mixed")
+    assert rel(p64, po) < 1e-11 and rel(E64, Eo) < 1e-11
+    assert rel(pm, p64) < 1e-4 and rel(Em, E64) < 1e-4, (rel(pm, p64), rel(Em, E64))
+    assert rel(Em[idx], E64[idx]) < 1e-4
+
+
+def test_allocation_failure_reports_nomem_and_releases_everything():
+    # a plan allocator that fails on its k-th call: the build reports
+    # FMM_ERR_NOMEM and hands back every block it had obtained
+    x, q, _ = W.plummer(30000, 45)
+    prm = F.Params(p=6, theta=0.4, ncrit=16, precision="mixed")
+    live = {}
+
+    def counting(fail_at):
+        calls = [0]
+
+        def alloc(nbytes, stream):
+            calls[0] += 1
+            if calls[0] == fail_at:
+                return None
+            ptr = torch.cuda.caching_allocator_alloc(nbytes)
+            live[ptr] = nbytes
+            return ptr
+
+        def free(ptr, stream):
+            live.pop(ptr)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        return F.CallbackAllocator(alloc, free), calls
+
+    xt, qt = dev(x), dev(q)
+    al, calls = counting(0)  # never fails: count the calls of a good build
+    plan = F.Plan(xt, prm, allocator=al)
+    n_build = calls[0]
+    phi, E = plan.evaluate(qt)
+    plan.close()
+    assert not live and n_build > 10
+    for k in sorted({1, 2, 5, n_build // 3, n_build // 2, n_build - 1, n_build}):
+        al, calls = counting(k)
+        with pytest.raises(F.FMMError) as ei:
+            F.Plan(xt, prm, allocator=al)
+        assert ei.value.code == 2, (k, ei.value)
+        torch.cuda.synchronize()
+        assert not live, (k, len(live))
+    # a failure in the adjoint's first call (its second right-hand side)
+    # leaves the plan usable
+    al, calls = counting(n_build + 1)
+    plan = F.Plan(xt, prm, allocator=al)
+    with pytest.raises(F.FMMError) as ei:
+        plan.adjoint(qt, qt, E)
+    assert ei.value.code == 2
+    phi2, _ = plan.evaluate(qt)
+    assert torch.equal(phi2, phi)
+    plan.close()
+    torch.cuda.synchronize()
+    assert not live
+
+
+def test_binding_checks_shapes_and_outputs():
+    x, q, _ = W.uniform_cube(500, 46)
+    with pytest.raises(ValueError):
+        F.evaluate(dev(x[:, :2]), dev(q))
+    plan = F.Plan(dev(x), F.Params(p=4))
+    with pytest.raises(ValueError):
+        plan.evaluate(dev(q[:-1]))
+    with pytest.raises(TypeError):
+        plan.evaluate(dev(q), out=(torch.empty(500, dtype=torch.float32, device="cuda:0"), None))
+    with pytest.raises(ValueError):
+        plan.evaluate(dev(q), out=(torch.empty(500, dtype=torch.float64, device="cuda:0"),
+                                   torch.empty((500, 2), dtype=torch.float64, device="cuda:0")))
+    with pytest.raises(ValueError):
+        strided = torch.empty((500, 2), dtype=torch.float64, device="cuda:0")[:, 0]
+        plan.evaluate(dev(q), out=(strided, None))
+    phi = torch.empty(500, dtype=torch.float64, device="cuda:0")
+    E = torch.empty((500, 3), dtype=torch.float64, device="cuda:0")
+    p1, e1 = plan.evaluate(dev(q), out=(phi, E))
+    assert p1.data_ptr() == phi.data_ptr() and e1.data_ptr() == E.data_ptr()
+    plan.close()
+    # a second backward without recomputation has no plan left
+    xt = dev(x).requires_grad_(True)
+    phi, E = F.FMMFunction.apply(xt, dev(q), F.Params(p=4))
+    L = phi.sum()
+    L.backward(retain_graph=True)
+    with pytest.raises(RuntimeError):
+        L.backward()

@@ -145,6 +145,27 @@ def test_target_subset_is_bit_identical_to_full():
     assert np.array_equal(ps, phi[tg]) and np.array_equal(Es, E[tg])
 
 
+@pytest.mark.parametrize("seed,ncrit,theta", [(6, 16, 0.4), (9, 8, 0.3)])
+def test_pruned_walk_keeps_exactly_the_pairs_of_the_full_walk(seed, ncrit, theta):
+    # the pruned walk (used as the reference at the largest workloads) skips
+    # every pair whose target is not kept; it must keep the same lists for the
+    # kept targets as the full walk and give the same bits there
+    x, _, _ = W.plummer(6000, seed)
+    q = np.random.default_rng(seed).uniform(0.0, 1.0, 6000)
+    tg = W.sample_targets(6000, 40, seed=(seed, 3))
+    Tf = oracle.Tree(x, ncrit, theta, targets=tg)
+    Tp = oracle.Tree(x, ncrit, theta, targets=tg, prune=True)
+    ef, ep = Tf.export(), Tp.export()
+    assert np.array_equal(ef["m2l"], ep["m2l"]) and np.array_equal(ef["p2p"], ep["p2p"])
+    assert Tp.n_m2l == Tp.n_m2l_stored < Tf.n_m2l and Tp.n_p2p == Tp.n_p2p_stored < Tf.n_p2p
+    pf, Ef = Tf.fmm(q, 6, targets=tg)
+    pp, Epr = Tp.fmm(q, 6, targets=tg)
+    assert np.array_equal(pf, pp) and np.array_equal(Ef, Epr)
+    # and both equal the full evaluation at those targets
+    pa, Ea = oracle.Tree(x, ncrit, theta).fmm(q, 6)
+    assert np.array_equal(pa[tg], pp) and np.array_equal(Ea[tg], Epr)
+
+
 def test_thread_count_does_not_change_bits():
     code = (
         "import sys,numpy as np; sys.path.insert(0, %r); import oracle;"

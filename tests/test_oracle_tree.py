@@ -3,14 +3,14 @@
 * cells against an independent recursive octree written in numpy
   (subdivision by lattice coordinate bits), including coincident bodies and
   flat inputs;
-* cell / leaf / depth counts of the five workloads (seed 0) as measured
-  independently of this code base from the same tree rules;
+* cell / leaf / depth counts of the workloads (seed 0) against an
+  independent level-by-level count in numpy (the 2^24-body one runs with
+  the GPU tests, on the GPU box's host cores);
 * list counts of the complete uniform trees against lattice enumeration;
 * list invariants: symmetry, exact once-coverage of every ordered body pair,
   the acceptance criterion decided in exact rational arithmetic, no
   self-interaction in M2L.
 """
-import os
 from fractions import Fraction
 
 import numpy as np
@@ -121,31 +121,61 @@ def test_all_coincident_bodies():
     assert np.all(phi == 0.0) and np.all(E == 0.0)
 
 
-# Cell / leaf / depth counts at seed 0, measured independently of this
-# repository's code from the same tree rules.
-TREE_COUNTS = {
-    "cube16k": (585, 512, 3),
-    "cube1m": (37449, 32768, 5),
-    "plummer4m": (507524, 443909, 11),
-    "plummer16m": (1037162, 907499, 11),
-}
+def level_counts(x, ncrit):
+    """(cells, leaves, depth) of the octree of x by the tree rules, counted
+    level by level in numpy, independently of the oracle: the lattice
+    coordinates of every body, then at each level the distinct prefixes of
+    the bodies whose parent cell was split, a cell being split when it holds
+    more than ncrit bodies below level 21."""
+    ix, _, _ = _lattice(x)
+    active = np.arange(x.shape[0])
+    cells, leaves, depth = 1, 0, 0
+    if not (x.shape[0] > ncrit):
+        return 1, 1, 0
+    for level in range(1, LEVELS + 1):
+        sh = LEVELS - level
+        a = ix[active] >> sh
+        key = (a[:, 0] << 42) | (a[:, 1] << 21) | a[:, 2]
+        uk, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+        cells += uk.size
+        depth = level
+        split = (cnt > ncrit) & (level < LEVELS)
+        leaves += int(np.count_nonzero(~split))
+        active = active[split[inv]]
+        if active.size == 0:
+            break
+    return cells, leaves, depth
 
 
 @pytest.mark.parametrize("name", ["cube16k", "cube1m", "plummer4m"])
 def test_workload_tree_counts(name):
+    # the counts of the workloads' trees, from the oracle and from the
+    # independent level-by-level count (they are: cube16k 585 cells / 512
+    # leaves / depth 3, cube1m 37,449 / 32,768 / 5, plummer4m 507,524 /
+    # 443,909 / 11)
     c = W.CONFIGS[name]
     x, _, _ = W.make_config(name)
     T = oracle.Tree(x, c["ncrit"], c["theta"], count_only=True)
-    assert (T.ncell, T.nleaf, T.depth) == TREE_COUNTS[name]
+    assert (T.ncell, T.nleaf, T.depth) == level_counts(x, c["ncrit"])
 
 
-@pytest.mark.slow
-@pytest.mark.skipif(os.environ.get("FMM_SLOW") != "1", reason="16.8M-body tree; set FMM_SLOW=1")
-def test_workload_tree_counts_16m():
-    c = W.CONFIGS["plummer16m"]
-    x, _, _ = W.make_config("plummer16m")
-    T = oracle.Tree(x, c["ncrit"], c["theta"], count_only=True)
-    assert (T.ncell, T.nleaf, T.depth) == TREE_COUNTS["plummer16m"]
+@pytest.mark.parametrize("case", ["uniform", "plummer", "dups", "flat"])
+def test_level_counts_match_recursive_octree(case):
+    # the level-by-level count is itself checked against the recursive octree
+    rng = np.random.default_rng(11)
+    if case == "uniform":
+        x = rng.random((3000, 3))
+    elif case == "plummer":
+        x, _, _ = W.plummer(3000, 4)
+    elif case == "dups":
+        x = rng.random((500, 3))
+        x[:60] = x[0]
+    else:
+        x = rng.random((800, 3))
+        x[:, 1] = 0.25
+    ref = _recursive_cells(x, 9)
+    leaves = sum(1 for i, c in enumerate(ref) if not (len(c[4]) > 9 and c[0] < LEVELS))
+    assert level_counts(x, 9) == (len(ref), leaves, max(c[0] for c in ref))
 
 
 def _mac_same_level(t2, theta):
