@@ -110,7 +110,18 @@ def main():
                     help="targets of the single-thread oracle run (-1: an eighth of the sample, 0: skip)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 GPU forward runs (0 = skip)")
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (the reference for HBM counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy > 0:
+        import torch
+        a = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes": a.numel() * 4}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library evaluates one rank's share on one GPU; --gpus must be 1 "
               "(the multi-GPU LET exchange is out of scope)", file=sys.stderr)

@@ -178,6 +178,30 @@ FMM_API fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, i
                         double theta, int32_t ncrit, int32_t precision, const fmm_allocator *alloc,
                         void *phi, void *field, void *hip_stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * evaluation as fmm_evaluate (build, evaluate, release), but every device
+ * buffer of the plan, including the operator and stencil tables that other
+ * plans cache per device, comes from one static array of
+ * FMM_NOALLOC_SCRATCH_BYTES bytes that the library holds on each GPU it runs
+ * on until the process ends.  The call allocates no device memory (host-side
+ * bookkeeping uses the C++ heap) and returns after its work on hip_stream is
+ * complete.  Calls on one device share that array and are serialised by the
+ * library; calls from several threads on one device therefore never overlap,
+ * but each waits for the previous one to finish.
+ * Limits: n <= FMM_NOALLOC_MAX_N, else FMM_ERR_UNSUPPORTED; a tree whose plan
+ * does not fit the array (deep adaptive trees, large p with small theta)
+ * fails with FMM_ERR_NOMEM and a message giving the bytes needed.  Uniform
+ * bodies at p <= 8, theta >= 0.4, ncrit >= 64 fit up to the maximum n in
+ * the mixed precision, and up to about 100,000 bodies in float64 (whose
+ * coefficients and operators take twice the bytes).
+ * Other errors: those of fmm_evaluate (without the allocator's). */
+#define FMM_NOALLOC_MAX_N (1 << 18)
+#define FMM_NOALLOC_SCRATCH_BYTES (512ull << 20)
+FMM_API fmm_status fmm_evaluate_noalloc(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t p,
+                                        double theta, int32_t ncrit, int32_t precision, void *phi, void *field,
+                                        void *hip_stream);
+
 /* Adjoint of L = sum_i w_i phi_i with w = grad_phi (the paper computes only
  * the forward potential and field of Section II.A; this is the reverse mode
  * of that computation).  The plan's lists are symmetric (the traversal of
@@ -191,6 +215,66 @@ FMM_API fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, i
  * Errors: FMM_ERR_INVALID (NULL plan/q/grad_phi), FMM_ERR_DEVICE. */
 FMM_API fmm_status fmm_adjoint(fmm_plan *plan, const void *q, const void *grad_phi, const void *field_q,
                        void *dq, void *dx, void *hip_stream);
+
+/* Statistics of fmm_let_evaluate (host struct), summed over the ordered rank
+ * pairs (receiver r, sender s != r) unless stated.  let_bytes is what the
+ * LETs would occupy as messages: per cell its center, side and structure
+ * (40 B) and its p^2 multipole coefficients (compute type), per body its
+ * coordinates and charge (32 B). */
+typedef struct {
+    int32_t nrank;
+    int64_t let_cells;        /* cells sent                                        */
+    int64_t let_far;          /* ... of them accepted against the receiver's cube   */
+    int64_t let_body_leaves;  /* ... leaves sent with their bodies                  */
+    int64_t let_bodies;       /* bodies sent                                       */
+    int64_t let_bytes;        /* message bytes as above                             */
+    int64_t n_m2l_local, n_p2p_local;                  /* each rank's own lists      */
+    int64_t n_m2l_remote, n_p2p_remote, n_m2p_remote;  /* lists against grafted LETs */
+    int64_t device_bytes;     /* bytes held by the ranks' plans                      */
+    double ms_partition, ms_build, ms_let, ms_evaluate, ms_total;  /* host wall clock */
+} fmm_let_stats;
+
+/* The evaluation split over nrank virtual ranks on one GPU, as the paper's
+ * distributed code splits it over processes (Section II.B: orthogonal
+ * recursive bisection weighted by the work of Eq. (1); Section II.C: local
+ * trees from local bounding boxes, the local essential tree (LET), Fig.
+ * `tree').
+ *   Partition: the box of a set of bodies is split across its longest side
+ *   (the first of the longest on a tie), bodies taken in ascending
+ *   (coordinate, index) order, the lower part getting the fewest bodies
+ *   whose weight reaches floor(m/2)/m of the box's weight for m ranks (at
+ *   least one body a side when there are two), recursively; weights
+ *   (device, int64, 0 <= w < 2^40; NULL = all 1; all 0 in a box = 1 each)
+ *   are typically l_i + alpha r_i from a previous call's work outputs.
+ *   Each rank builds its own tree from its own bodies (fmm_build rules).
+ *   LET of sender s for receiver r: top-down over s's cells, a cell meeting
+ *   the acceptance criterion against r's whole root cube (R_B < theta d, d
+ *   the distance from the cell's center to the cube) is sent with its
+ *   multipole only, a leaf that does not with its bodies, any other cell is
+ *   sent and opened.  Receiver r walks its tree against each grafted LET:
+ *   accepted pairs (R_A + R_B < theta |c_A - c_B|) are M2L, a leaf against
+ *   a sent leaf is P2P (bodies) or M2P (multipole only, evaluated at the
+ *   leaf's bodies), otherwise the sent leaf splits A, a leaf A splits B, or
+ *   the larger cube is split (both when equal).  Remote work is float64.
+ * Outputs (device, caller's order; all but phi may be NULL): phi (N), field
+ * (N x 3); rank (N, int32) of every body; work_local / work_remote (N,
+ * int64) the l_i / r_i of Eq. (1) -- bodies of the leaves in the body's
+ * P2P list plus cells in the M2L lists of its leaf and its leaf's
+ * ancestors, over the local lists / the remote lists (M2P cells included).
+ * pair_stats (HOST, nrank^2 x 11 int64, receiver-major): per (r, s != r)
+ * [cells sent, multipole-only cells, body leaves, bodies, remote M2L, remote
+ * P2P, M2P, three list digests, LET digest], per (r, r) [0, 0, 0, 0, local
+ * M2L, local P2P, 0, local M2L digest, local P2P digest, 0, 0] (digests as
+ * in fmm_list_digest; the LET digest sums mix64(cell << 8 | kind) with kind
+ * 1 opened, 2 multipole only, 3 leaf with bodies).  Synchronises hip_stream.
+ * Errors: FMM_ERR_INVALID (NULL x/q/phi with n > 0, nrank outside
+ * [1, 1024], bad params or weights), FMM_ERR_UNSUPPORTED (n >= 2^31),
+ * FMM_ERR_NONFINITE, FMM_ERR_NOMEM, FMM_ERR_DEVICE. */
+FMM_API fmm_status fmm_let_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t nrank,
+                                    const int64_t *weights, const fmm_params *prm, const fmm_allocator *alloc,
+                                    void *phi, void *field, int32_t *rank, int64_t *work_local,
+                                    int64_t *work_remote, int64_t *pair_stats, fmm_let_stats *stats,
+                                    void *hip_stream);
 
 /* Copies counts and the last per-phase timings into *out (host): the
  * interaction counts of Section II.C and the phase breakdown of Section

@@ -49,6 +49,18 @@ def lib():
                                          _i32p, _i32p, _i32p, _dp, _i32p, _i32p]
         L.oracle_fmm_at.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp]
         L.oracle_fmm_at.restype = C.c_int
+        L.oracle_let_new.argtypes = [C.c_int64, _dp, _i64p, C.c_int32, C.c_int32, C.c_double, C.c_int]
+        L.oracle_let_new.restype = C.c_void_p
+        L.oracle_let_free.argtypes = [C.c_void_p]
+        L.oracle_let_partition.argtypes = [C.c_void_p, _i32p, _i64p, _i64p, _i64p]
+        L.oracle_let_rank_tree.argtypes = [C.c_void_p, C.c_int32]
+        L.oracle_let_rank_tree.restype = C.c_void_p
+        L.oracle_let_counts.argtypes = [C.c_void_p, _i64p]
+        L.oracle_let_kind.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_uint8)]
+        L.oracle_let_lists.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _i32p, _i32p, _i32p]
+        L.oracle_let_work.argtypes = [C.c_void_p, _i64p, _i64p]
+        L.oracle_let_fmm.argtypes = [C.c_void_p, _dp, C.c_int, _dp, _dp]
+        L.oracle_let_fmm.restype = C.c_int
         L.oracle_num_threads.restype = C.c_int
         L.oracle_set_num_threads.argtypes = [C.c_int]
         L.oracle_set_num_threads.restype = None
@@ -158,7 +170,11 @@ class Tree:
     counts then cover only the kept lists (for very large trees).
     """
 
-    def __init__(self, x, ncrit, theta, targets=None, count_only=False, prune=False):
+    def __init__(self, x, ncrit, theta, targets=None, count_only=False, prune=False, _handle=None, _owner=None):
+        if _handle is not None:
+            # a tree owned by another object (a rank of a LET): no build, no free
+            self._adopt(_handle, x, ncrit, theta, _owner)
+            return
         self.x = _f64(x).reshape(-1, 3)
         self.n = self.x.shape[0]
         self.ncrit, self.theta = int(ncrit), float(theta)
@@ -175,6 +191,21 @@ class Tree:
         if not h:
             raise ValueError("oracle_tree_new: invalid input")
         self._h = h
+        self._owned = True
+        self._read_info()
+
+    def _adopt(self, h, x, ncrit, theta, owner):
+        self.x = _f64(x).reshape(-1, 3)
+        self.n = self.x.shape[0]
+        self.ncrit, self.theta = int(ncrit), float(theta)
+        self.targets = None
+        self._h = h
+        self._owned = False
+        self._owner = owner  # keeps the owner (and the tree) alive
+        self._read_info()
+
+    def _read_info(self):
+        h = self._h
         info = np.zeros(7, dtype=np.int64)
         box = np.zeros(5)
         lib().oracle_tree_info(h, info.ctypes.data_as(_i64p), _d(box))
@@ -189,9 +220,9 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and getattr(self, "_owned", True):
             lib().oracle_tree_free(h)
-            self._h = None
+        self._h = None
 
     def export(self):
         n, nc = self.n, self.ncell
@@ -228,4 +259,82 @@ class Tree:
         rc = lib().oracle_fmm_at(self._h, _d(xp), _d(q), int(p), nt, tp, _d(phi), _d(E))
         if rc:
             raise ValueError(f"oracle_fmm failed ({rc})")
+        return phi, E
+
+
+class Let:
+    """The evaluation split over R virtual ranks (ORB partition with integer
+    weights, local trees, LET selection, the remote traversal), FP64.
+
+    count_only=True keeps no local list (counts and digests only)."""
+
+    NSTAT = 11
+
+    def __init__(self, x, R, ncrit, theta, weights=None, count_only=False):
+        self.x = _f64(x).reshape(-1, 3)
+        self.n = self.x.shape[0]
+        self.R, self.ncrit, self.theta = int(R), int(ncrit), float(theta)
+        wp = None
+        if weights is not None:
+            self._w = np.ascontiguousarray(weights, dtype=np.int64)
+            wp = self._w.ctypes.data_as(_i64p)
+        h = lib().oracle_let_new(self.n, _d(self.x), wp, self.R, self.ncrit, self.theta, 1 if count_only else 0)
+        if not h:
+            raise ValueError("oracle_let_new: invalid input")
+        self._h = h
+        self.rank = np.zeros(self.n, np.int32)
+        self.members = np.zeros(self.n, np.int64)
+        self.rstart = np.zeros(self.R, np.int64)
+        self.rcount = np.zeros(self.R, np.int64)
+        lib().oracle_let_partition(h, self.rank.ctypes.data_as(_i32p), self.members.ctypes.data_as(_i64p),
+                                   self.rstart.ctypes.data_as(_i64p), self.rcount.ctypes.data_as(_i64p))
+        st = np.zeros(self.R * self.R * self.NSTAT, np.int64)
+        lib().oracle_let_counts(h, st.ctypes.data_as(_i64p))
+        self.pair_stats = st.reshape(self.R, self.R, self.NSTAT)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().oracle_let_free(h)
+            self._h = None
+
+    def tree(self, r):
+        """The local tree of rank r (an oracle Tree view), or None."""
+        h = lib().oracle_let_rank_tree(self._h, int(r))
+        if not h:
+            return None
+        m = self.members[self.rstart[r]:self.rstart[r] + self.rcount[r]]
+        return Tree(self.x[m], self.ncrit, self.theta, _handle=h, _owner=self)
+
+    def kind(self, r, s):
+        """LET kind of sender s's cells for receiver r (0 not sent, 1 opened,
+        2 multipole only, 3 leaf with bodies)."""
+        t = self.tree(s)
+        out = np.zeros(t.ncell, np.uint8)
+        lib().oracle_let_kind(self._h, int(r), int(s), out.ctypes.data_as(C.POINTER(C.c_uint8)))
+        return out
+
+    def lists(self, r, s):
+        """Remote (M2L, P2P, M2P) pairs (A of r, B of s), ascending."""
+        n = self.pair_stats[r, s, 4:7]
+        out = [np.zeros((int(k), 2), np.int32) for k in n]
+        ptr = lambda a: a.ctypes.data_as(_i32p) if a.size else None
+        lib().oracle_let_lists(self._h, int(r), int(s), *(ptr(a) for a in out))
+        return tuple(out)
+
+    def work(self):
+        """(l, r) work counts of every body (input order)."""
+        lw = np.zeros(self.n, np.int64)
+        rw = np.zeros(self.n, np.int64)
+        lib().oracle_let_work(self._h, lw.ctypes.data_as(_i64p), rw.ctypes.data_as(_i64p))
+        return lw, rw
+
+    def fmm(self, q, p):
+        """FP64 potential and field at every body (input order)."""
+        q = _f64(q)
+        phi = np.zeros(self.n)
+        E = np.zeros((self.n, 3))
+        rc = lib().oracle_let_fmm(self._h, _d(q), int(p), _d(phi), _d(E))
+        if rc:
+            raise ValueError(f"oracle_let_fmm failed ({rc})")
         return phi, E

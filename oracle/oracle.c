@@ -894,6 +894,576 @@ int oracle_fmm_at(const void *h, const double *xpos, const double *q, int p,
     return bad ? 3 : 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Virtual ranks (Section II.B: orthogonal recursive bisection weighted by   */
+/* the work of Eq. (1); Section II.C: local trees from local bounding boxes, */
+/* the local essential tree sent by each rank and grafted by the receiver).  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double c; int64_t i; } okey;
+
+static int cmp_okey(const void *a, const void *b)
+{
+    const okey *x = (const okey *)a, *y = (const okey *)b;
+    if (x->c != y->c) return x->c < y->c ? -1 : 1;
+    return (x->i > y->i) - (x->i < y->i);
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* ORB of the bodies mem[0..cnt) (ascending input indices) over the m ranks
+ * r0 .. r0+m-1.  The box is split across its longest side (the first of the
+ * longest when several tie): bodies in ascending (coordinate, index) order,
+ * the lower part taking the first k bodies with k the smallest count whose
+ * weight reaches the share floor(m/2)/m of the box's weight (unit weights
+ * when the box weighs nothing), and at least one body on each side when
+ * there are two or more.  Each part keeps ascending input order.           */
+static void orb_split(const double *x, const int64_t *w, int64_t *mem, int64_t cnt, int m, int r0, int32_t *rank)
+{
+    if (cnt == 0) return;
+    if (m <= 1) {
+        for (int64_t k = 0; k < cnt; ++k) rank[mem[k]] = r0;
+        return;
+    }
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = x[3 * mem[0] + d];
+    for (int64_t k = 1; k < cnt; ++k)
+        for (int d = 0; d < 3; ++d) {
+            double v = x[3 * mem[k] + d];
+            if (v < lo[d]) lo[d] = v;
+            if (v > hi[d]) hi[d] = v;
+        }
+    int axis = 0;
+    for (int d = 1; d < 3; ++d)
+        if (hi[d] - lo[d] > hi[axis] - lo[axis]) axis = d;
+    okey *ks = (okey *)malloc((size_t)cnt * sizeof(okey));
+    for (int64_t k = 0; k < cnt; ++k) { ks[k].c = x[3 * mem[k] + axis]; ks[k].i = mem[k]; }
+    qsort(ks, (size_t)cnt, sizeof(okey), cmp_okey);
+    __int128 W = 0;
+    for (int64_t k = 0; k < cnt; ++k) W += w ? w[ks[k].i] : 1;
+    const int unit = (!w || W == 0);
+    if (unit) W = cnt;
+    const int mL = m / 2;
+    /* smallest k with P(k) m >= W mL, P(k) the weight of the first k bodies */
+    int64_t k = 0;
+    __int128 P = 0;
+    const __int128 goal = W * mL;
+    while (k < cnt && P * m < goal) {
+        P += unit ? 1 : w[ks[k].i];
+        ++k;
+    }
+    if (cnt >= 2) {
+        if (k < 1) k = 1;
+        if (k > cnt - 1) k = cnt - 1;
+    }
+    for (int64_t j = 0; j < cnt; ++j) mem[j] = ks[j].i;
+    free(ks);
+    qsort(mem, (size_t)k, sizeof(int64_t), cmp_i64);
+    qsort(mem + k, (size_t)(cnt - k), sizeof(int64_t), cmp_i64);
+    orb_split(x, w, mem, k, mL, r0, rank);
+    orb_split(x, w, mem + k, cnt - k, m - mL, r0 + mL, rank);
+}
+
+typedef struct {
+    int64_t n;
+    int R;
+    int32_t ncrit;
+    double theta, t4;
+    double *x;                /* [3n] coordinates (input order)                     */
+    int32_t *rank;            /* [n] rank of every body                            */
+    int64_t *rstart, *rcount; /* [R] members of rank r: mem[rstart[r] .. + rcount[r]) */
+    int64_t *mem;             /* [n] input indices grouped by rank, ascending inside */
+    otree **T;                /* [R] local trees (NULL for an empty rank)           */
+    uint8_t **kind;           /* [R*R] (receiver r, sender s): kind of s's cells      */
+    pbuf *rm2l, *rp2p, *rm2p; /* [R*R] remote pairs (A of r) << 32 | (B of s), sorted */
+    int64_t *cnt;             /* [R*R*4] LET cells, multipole-only leaves, body leaves, bodies */
+} olet;
+
+/* Side of a cell's cube: h_l = S 2^-l. */
+static double cell_h(const otree *t, int c) { return ldexp(t->S, -t->lvl[c]); }
+
+/* The sender's test against the receiver's root cube (lo, lo + S): the
+ * acceptance criterion with the whole cube on the target side, R_B < theta d
+ * with d the distance from the cell's center to the cube (0 inside), in the
+ * form 3 h_B^2 < 4 theta^2 d^2 (R = sqrt(3)/2 h).                        */
+static int let_far(const otree *s, int b, const otree *r, double t4)
+{
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        const double c = s->ctr[3 * b + k], lo = r->lo[k], hi = r->lo[k] + r->S;
+        d[k] = c < lo ? lo - c : (c > hi ? c - hi : 0.0);
+    }
+    const double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double h = cell_h(s, b);
+    return 3.0 * h * h < t4 * d2;
+}
+
+/* Acceptance criterion between cells of two different trees (no common
+ * lattice): R_A + R_B < theta |c_A - c_B| as 3 (h_A + h_B)^2 < 4 theta^2 D^2. */
+static int mac_cross(const otree *ta, int a, const otree *tb, int b, double t4)
+{
+    const double dx = ta->ctr[3 * a] - tb->ctr[3 * b], dy = ta->ctr[3 * a + 1] - tb->ctr[3 * b + 1],
+                 dz = ta->ctr[3 * a + 2] - tb->ctr[3 * b + 2];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double sh = cell_h(ta, a) + cell_h(tb, b);
+    return 3.0 * sh * sh < t4 * d2;
+}
+
+/* LET of sender s for receiver r, top-down over s's cells (a parent precedes
+ * its children in (level, key) order): kind 0 = not sent, 1 = sent with its
+ * multipole and its children, 2 = sent with its multipole only (accepted
+ * against the receiver's cube), 3 = a leaf sent with its multipole and its
+ * bodies.  cnt: cells sent, kind-2 cells, kind-3 leaves, bodies sent.      */
+static void let_select(const otree *s, const otree *r, double t4, uint8_t *kind, int64_t *cnt)
+{
+    cnt[0] = cnt[1] = cnt[2] = cnt[3] = 0;
+    for (int64_t c = 0; c < s->ncell; ++c) {
+        const int32_t pa = s->par[c];
+        if (pa >= 0 && kind[pa] != 1) { kind[c] = 0; continue; }
+        if (let_far(s, (int)c, r, t4)) kind[c] = 2;
+        else if (s->nch[c] == 0) kind[c] = 3;
+        else kind[c] = 1;
+        cnt[0]++;
+        if (kind[c] == 2) cnt[1]++;
+        if (kind[c] == 3) { cnt[2]++; cnt[3] += s->end[c] - s->beg[c]; }
+    }
+}
+
+typedef struct {
+    const otree *ta, *tb;
+    const uint8_t *kind;
+    double t4;
+    pbuf *m2l, *p2p, *m2p;
+} lctx;
+
+/* The receiver's dual traversal of its tree (A) against the grafted remote
+ * tree (B): accepted pairs are M2L; a leaf against a sent leaf is P2P (bodies
+ * sent) or M2P (multipole only, evaluated at the leaf's bodies, which all lie
+ * in the receiver's cube where the sender found the series convergent);
+ * otherwise a sent leaf splits A, a leaf A splits B, and else the larger cube
+ * is split (both when equal).                                             */
+static void let_interact(lctx *c, int a, int b)
+{
+    const uint64_t pr = ((uint64_t)a << 32) | (uint32_t)b;
+    if (mac_cross(c->ta, a, c->tb, b, c->t4)) { pb_push(c->m2l, pr); return; }
+    const int aleaf = c->ta->nch[a] == 0, bk = c->kind[b], bleaf = (bk == 2 || bk == 3);
+    if (aleaf && bleaf) {
+        pb_push(bk == 3 ? c->p2p : c->m2p, pr);
+        return;
+    }
+    int sa, sb;
+    if (bleaf) { sa = 1; sb = 0; }
+    else if (aleaf) { sa = 0; sb = 1; }
+    else {
+        const double ha = cell_h(c->ta, a), hb = cell_h(c->tb, b);
+        sa = ha >= hb;
+        sb = hb >= ha;
+    }
+    const int na = sa ? c->ta->nch[a] : 1, nb = sb ? c->tb->nch[b] : 1;
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j)
+            let_interact(c, sa ? c->ta->cbeg[a] + i : a, sb ? c->tb->cbeg[b] + j : b);
+}
+
+static void pb_sort(pbuf *b) { qsort(b->v, (size_t)b->n, sizeof(uint64_t), cmp_u64); }
+
+/* Partition, local trees, LETs and remote lists.  w (nullable) holds integer
+ * weights >= 0; count_only != 0 keeps no local list (counts only).  Returns
+ * NULL on invalid input.                                                   */
+void *oracle_let_new(int64_t n, const double *x, const int64_t *w, int32_t R, int32_t ncrit, double theta,
+                     int count_only)
+{
+    if (n <= 0 || !x || R < 1 || ncrit < 1 || !(theta > 0.0 && theta < 1.0)) return NULL;
+    if (w)
+        for (int64_t i = 0; i < n; ++i)
+            if (w[i] < 0 || w[i] >= ((int64_t)1 << 40)) return NULL;
+    olet *L = (olet *)calloc(1, sizeof(olet));
+    L->n = n;
+    L->R = R;
+    L->ncrit = ncrit;
+    L->theta = theta;
+    L->t4 = 4.0 * theta * theta;
+    L->x = (double *)malloc((size_t)n * 3 * sizeof(double));
+    memcpy(L->x, x, (size_t)n * 3 * sizeof(double));
+    L->rank = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    L->mem = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) L->mem[i] = i;
+    orb_split(x, w, L->mem, n, R, 0, L->rank);
+    /* members grouped by rank, ascending input index inside a rank */
+    L->rstart = (int64_t *)calloc((size_t)R, sizeof(int64_t));
+    L->rcount = (int64_t *)calloc((size_t)R, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) L->rcount[L->rank[i]]++;
+    for (int r = 1; r < R; ++r) L->rstart[r] = L->rstart[r - 1] + L->rcount[r - 1];
+    {
+        int64_t *fill = (int64_t *)calloc((size_t)R, sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i) {
+            const int r = L->rank[i];
+            L->mem[L->rstart[r] + fill[r]++] = i;
+        }
+        free(fill);
+    }
+    L->T = (otree **)calloc((size_t)R, sizeof(otree *));
+    double *xr = (double *)malloc((size_t)n * 3 * sizeof(double));
+    for (int64_t k = 0; k < n; ++k)
+        for (int d = 0; d < 3; ++d) xr[3 * k + d] = x[3 * L->mem[k] + d];
+    for (int r = 0; r < R; ++r)
+        if (L->rcount[r] > 0)
+            L->T[r] = (otree *)oracle_tree_new2(L->rcount[r], xr + 3 * L->rstart[r], ncrit, theta,
+                                                count_only ? -1 : 0, NULL, 0);
+    free(xr);
+    const int64_t RR = (int64_t)R * R;
+    L->kind = (uint8_t **)calloc((size_t)RR, sizeof(uint8_t *));
+    L->rm2l = (pbuf *)calloc((size_t)RR, sizeof(pbuf));
+    L->rp2p = (pbuf *)calloc((size_t)RR, sizeof(pbuf));
+    L->rm2p = (pbuf *)calloc((size_t)RR, sizeof(pbuf));
+    L->cnt = (int64_t *)calloc((size_t)RR * 4, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t rs = 0; rs < RR; ++rs) {
+        const int r = (int)(rs / R), s = (int)(rs % R);
+        if (r == s || !L->T[r] || !L->T[s]) continue;
+        L->kind[rs] = (uint8_t *)malloc((size_t)L->T[s]->ncell);
+        let_select(L->T[s], L->T[r], L->t4, L->kind[rs], L->cnt + 4 * rs);
+        lctx c = {L->T[r], L->T[s], L->kind[rs], L->t4, &L->rm2l[rs], &L->rp2p[rs], &L->rm2p[rs]};
+        let_interact(&c, 0, 0);
+        pb_sort(&L->rm2l[rs]);
+        pb_sort(&L->rp2p[rs]);
+        pb_sort(&L->rm2p[rs]);
+    }
+    return L;
+}
+
+void oracle_let_free(void *h)
+{
+    olet *L = (olet *)h;
+    if (!L) return;
+    const int64_t RR = (int64_t)L->R * L->R;
+    for (int r = 0; r < L->R; ++r) oracle_tree_free(L->T[r]);
+    for (int64_t k = 0; k < RR; ++k) {
+        free(L->kind[k]);
+        free(L->rm2l[k].v);
+        free(L->rp2p[k].v);
+        free(L->rm2p[k].v);
+    }
+    free(L->T); free(L->kind); free(L->rm2l); free(L->rp2p); free(L->rm2p); free(L->cnt);
+    free(L->x); free(L->rank); free(L->rstart); free(L->rcount); free(L->mem);
+    free(L);
+}
+
+/* rank of every body; members (input indices grouped by rank); rstart, rcount */
+void oracle_let_partition(const void *h, int32_t *rank, int64_t *mem, int64_t *rstart, int64_t *rcount)
+{
+    const olet *L = (const olet *)h;
+    if (rank) memcpy(rank, L->rank, (size_t)L->n * sizeof(int32_t));
+    if (mem) memcpy(mem, L->mem, (size_t)L->n * sizeof(int64_t));
+    if (rstart) memcpy(rstart, L->rstart, (size_t)L->R * sizeof(int64_t));
+    if (rcount) memcpy(rcount, L->rcount, (size_t)L->R * sizeof(int64_t));
+}
+
+/* the local tree of rank r (owned by the LET; NULL for an empty rank) */
+void *oracle_let_rank_tree(const void *h, int32_t r)
+{
+    const olet *L = (const olet *)h;
+    return (r >= 0 && r < L->R) ? L->T[r] : NULL;
+}
+
+/* per (receiver r, sender s), r-major, 11 values: [LET cells, multipole-only
+ * leaves, body leaves, bodies, remote M2L, remote P2P, M2P, digest M2L, digest
+ * P2P, digest M2P, digest of the LET] -- digests are mix64 sums like the
+ * local lists' (of (A << 32 | B) for the lists, of (cell << 8 | kind) over the
+ * cells sent for the LET).  For r == s: [0, 0, 0, 0, local M2L, local P2P, 0,
+ * local M2L digest, local P2P digest, 0, 0].                              */
+void oracle_let_counts(const void *h, int64_t *out)
+{
+    const olet *L = (const olet *)h;
+    const int64_t RR = (int64_t)L->R * L->R;
+    for (int64_t rs = 0; rs < RR; ++rs) {
+        int64_t *o = out + 11 * rs;
+        const int r = (int)(rs / L->R), s = (int)(rs % L->R);
+        for (int k = 0; k < 11; ++k) o[k] = 0;
+        if (r == s) {
+            if (L->T[r]) {
+                o[4] = L->T[r]->n_m2l;
+                o[5] = L->T[r]->n_p2p;
+                o[7] = (int64_t)L->T[r]->h_m2l;
+                o[8] = (int64_t)L->T[r]->h_p2p;
+            }
+            continue;
+        }
+        for (int k = 0; k < 4; ++k) o[k] = L->cnt[4 * rs + k];
+        o[4] = L->rm2l[rs].n;
+        o[5] = L->rp2p[rs].n;
+        o[6] = L->rm2p[rs].n;
+        const pbuf *b[3] = {&L->rm2l[rs], &L->rp2p[rs], &L->rm2p[rs]};
+        for (int k = 0; k < 3; ++k) {
+            uint64_t d = 0;
+            for (int64_t j = 0; j < b[k]->n; ++j) d += mix64(b[k]->v[j]);
+            o[7 + k] = (int64_t)d;
+        }
+        uint64_t dk = 0;
+        if (L->kind[rs])
+            for (int64_t c = 0; c < L->T[s]->ncell; ++c)
+                if (L->kind[rs][c]) dk += mix64(((uint64_t)c << 8) | L->kind[rs][c]);
+        o[10] = (int64_t)dk;
+    }
+}
+
+/* kind of sender s's cells in the LET for receiver r (s's cell order)     */
+void oracle_let_kind(const void *h, int32_t r, int32_t s, uint8_t *kind)
+{
+    const olet *L = (const olet *)h;
+    const int64_t rs = (int64_t)r * L->R + s;
+    if (L->kind[rs]) memcpy(kind, L->kind[rs], (size_t)L->T[s]->ncell);
+}
+
+/* the remote lists of (r, s) as (A, B) pairs in ascending order           */
+void oracle_let_lists(const void *h, int32_t r, int32_t s, int32_t *m2l, int32_t *p2p, int32_t *m2p)
+{
+    const olet *L = (const olet *)h;
+    const int64_t rs = (int64_t)r * L->R + s;
+    int32_t *dst[3] = {m2l, p2p, m2p};
+    const pbuf *b[3] = {&L->rm2l[rs], &L->rp2p[rs], &L->rm2p[rs]};
+    for (int k = 0; k < 3; ++k)
+        if (dst[k])
+            for (int64_t j = 0; j < b[k]->n; ++j) {
+                dst[k][2 * j] = (int32_t)(b[k]->v[j] >> 32);
+                dst[k][2 * j + 1] = (int32_t)(b[k]->v[j] & 0xffffffffu);
+            }
+}
+
+/* Work of every body (input order), the l_i and r_i of Eq. (1): bodies of the
+ * leaves in its leaf's P2P list plus cells in the M2L lists of its leaf and
+ * the leaf's ancestors, for the local lists (l) and the remote ones (r, M2P
+ * cells of its leaf included).  Needs the local lists (not count_only).    */
+void oracle_let_work(const void *h, int64_t *lw, int64_t *rw)
+{
+    const olet *L = (const olet *)h;
+    const int R = L->R;
+    for (int r = 0; r < R; ++r) {
+        const otree *t = L->T[r];
+        if (!t) continue;
+        int64_t *own = (int64_t *)calloc((size_t)t->ncell, sizeof(int64_t));
+        int64_t *rem = (int64_t *)calloc((size_t)t->ncell, sizeof(int64_t));
+        for (int64_t c = 0; c < t->ncell; ++c) {
+            own[c] = t->m2l_off[c + 1] - t->m2l_off[c];
+            if (t->nch[c] == 0)
+                for (int64_t k = t->p2p_off[c]; k < t->p2p_off[c + 1]; ++k)
+                    own[c] += t->end[t->p2p_src[k]] - t->beg[t->p2p_src[k]];
+        }
+        for (int s = 0; s < R; ++s) {
+            const int64_t rs = (int64_t)r * R + s;
+            if (s == r || !L->T[s]) continue;
+            const otree *ts = L->T[s];
+            for (int64_t j = 0; j < L->rm2l[rs].n; ++j) rem[L->rm2l[rs].v[j] >> 32] += 1;
+            for (int64_t j = 0; j < L->rm2p[rs].n; ++j) rem[L->rm2p[rs].v[j] >> 32] += 1;
+            for (int64_t j = 0; j < L->rp2p[rs].n; ++j) {
+                const int b = (int)(L->rp2p[rs].v[j] & 0xffffffffu);
+                rem[L->rp2p[rs].v[j] >> 32] += ts->end[b] - ts->beg[b];
+            }
+        }
+        /* down the tree: a cell's count includes its ancestors' */
+        for (int64_t c = 1; c < t->ncell; ++c) {
+            own[c] += own[t->par[c]];
+            rem[c] += rem[t->par[c]];
+        }
+        for (int64_t c = 0; c < t->ncell; ++c)
+            if (t->nch[c] == 0)
+                for (int32_t i = t->beg[c]; i < t->end[c]; ++i) {
+                    const int64_t orig = L->mem[L->rstart[r] + t->perm[i]];
+                    if (lw) lw[orig] = own[c];
+                    if (rw) rw[orig] = rem[c];
+                }
+        free(own);
+        free(rem);
+    }
+}
+
+/* Multipole series of a cell evaluated at x, with its field: the local
+ * expansion about x itself of the truncated multipole series (the M2L of
+ * the pinned operator, degrees j <= 1 kept) gives the value and gradient of
+ * that series exactly at its center.                                      */
+static void m2p_add(const cplx *M, const double cB[3], int p, const double *x, double *phi, double E[3])
+{
+    cplx Lx[ORC_MAXP * ORC_MAXP] = {0};
+    cplx Ih[(2 * ORC_MAXP) * (2 * ORC_MAXP)];
+    double D[3] = {x[0] - cB[0], x[1] - cB[1], x[2] - cB[2]};
+    harmonics(D, p + 1, NULL, Ih);
+    const int jmax = p > 1 ? 2 : 1;
+    for (int j = 0; j < jmax; ++j) {
+        double sj = (j & 1) ? -1.0 : 1.0;
+        for (int s = -j; s <= j; ++s) {
+            cplx acc = 0.0;
+            for (int nn = 0; nn < p; ++nn)
+                for (int m = -nn; m <= nn; ++m) acc += M[HIDX(nn, m)] * hget(Ih, nn + j, m + s);
+            Lx[HIDX(j, s)] += sj * acc;
+        }
+    }
+    double ph, Ev[3];
+    l2p_eval(Lx, x, jmax, x, &ph, Ev);
+    *phi += ph;
+    E[0] += Ev[0];
+    E[1] += Ev[1];
+    E[2] += Ev[2];
+}
+
+/* The FMM over the virtual ranks at every body (input order): each rank's
+ * upward pass; local expansions from the local M2L list and then from each
+ * sender's remote M2L pairs (senders ascending, pairs in order); the
+ * downward pass; at every body L2P, the local P2P list, the remote P2P
+ * pairs and the M2P pairs (senders ascending).  Needs the local lists.     */
+int oracle_let_fmm(const void *h, const double *q, int p, double *phi, double *field)
+{
+    const olet *L = (const olet *)h;
+    if (!L || !q || p < 1 || p > ORC_MAXP) return 1;
+    const int R = L->R, P2 = p * p;
+    for (int r = 0; r < R; ++r)
+        if (L->T[r] && L->T[r]->n_m2l_stored != L->T[r]->n_m2l) return 2;  /* built count_only */
+    cplx **M = (cplx **)calloc((size_t)R, sizeof(cplx *));
+    cplx **Lc = (cplx **)calloc((size_t)R, sizeof(cplx *));
+    double **xs = (double **)calloc((size_t)R, sizeof(double *));
+    double **qs = (double **)calloc((size_t)R, sizeof(double *));
+    for (int r = 0; r < R; ++r) {
+        const otree *t = L->T[r];
+        if (!t) continue;
+        const int64_t nc = t->ncell;
+        xs[r] = (double *)malloc((size_t)t->n * 3 * sizeof(double));
+        qs[r] = (double *)malloc((size_t)t->n * sizeof(double));
+        for (int64_t i = 0; i < t->n; ++i) {
+            const int64_t o = L->mem[L->rstart[r] + t->perm[i]];
+            for (int d = 0; d < 3; ++d) xs[r][3 * i + d] = L->x[3 * o + d];
+            qs[r][i] = q[o];
+        }
+        /* upward pass of rank r */
+        cplx *Mr = M[r] = (cplx *)calloc((size_t)nc * P2, sizeof(cplx));
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t c = 0; c < nc; ++c)
+            if (t->nch[c] == 0)
+                for (int32_t i = t->beg[c]; i < t->end[c]; ++i)
+                    p2m_add(xs[r] + 3 * (int64_t)i, qs[r][i], t->ctr + 3 * c, p, Mr + c * P2);
+        for (int l = t->depth - 1; l >= 0; --l) {
+#pragma omp parallel for schedule(dynamic, 8)
+            for (int64_t c = 0; c < nc; ++c) {
+                if (t->lvl[c] != l || t->nch[c] == 0) continue;
+                for (int k = 0; k < t->nch[c]; ++k) {
+                    int64_t ch = t->cbeg[c] + k;
+                    m2m_add(Mr + ch * P2, t->ctr + 3 * ch, t->ctr + 3 * c, p, Mr + c * P2);
+                }
+            }
+        }
+    }
+    for (int r = 0; r < R; ++r) {
+        const otree *t = L->T[r];
+        if (!t) continue;
+        const int64_t nc = t->ncell;
+        cplx *Lr = Lc[r] = (cplx *)calloc((size_t)nc * P2, sizeof(cplx));
+        /* remote pairs of each sender as CSR over the receiver's cells */
+        int64_t **off = (int64_t **)calloc((size_t)R * 3, sizeof(int64_t *));
+        for (int s = 0; s < R; ++s) {
+            const int64_t rs = (int64_t)r * R + s;
+            const pbuf *b[3] = {&L->rm2l[rs], &L->rp2p[rs], &L->rm2p[rs]};
+            for (int k = 0; k < 3; ++k) {
+                int64_t *o = off[3 * s + k] = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+                for (int64_t j = 0; j < b[k]->n; ++j) o[(b[k]->v[j] >> 32) + 1]++;
+                for (int64_t c = 0; c < nc; ++c) o[c + 1] += o[c];
+            }
+        }
+        /* M2L: the local list, then the senders in order */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t c = 0; c < nc; ++c) {
+            for (int64_t k = t->m2l_off[c]; k < t->m2l_off[c + 1]; ++k) {
+                int64_t s = t->m2l_src[k];
+                m2l_add(M[r] + s * P2, t->ctr + 3 * s, t->ctr + 3 * c, p, Lr + c * P2);
+            }
+            for (int s = 0; s < R; ++s) {
+                const int64_t rs = (int64_t)r * R + s;
+                const int64_t *o = off[3 * s];
+                for (int64_t k = o[c]; k < o[c + 1]; ++k) {
+                    const int64_t b = (int64_t)(L->rm2l[rs].v[k] & 0xffffffffu);
+                    m2l_add(M[s] + b * P2, L->T[s]->ctr + 3 * b, t->ctr + 3 * c, p, Lr + c * P2);
+                }
+            }
+        }
+        /* downward pass */
+        for (int l = 1; l <= t->depth; ++l) {
+#pragma omp parallel for schedule(dynamic, 8)
+            for (int64_t c = 0; c < nc; ++c) {
+                if (t->lvl[c] != l) continue;
+                int64_t pa = t->par[c];
+                l2l_add(Lr + pa * P2, t->ctr + 3 * pa, t->ctr + 3 * c, p, Lr + c * P2);
+            }
+        }
+        /* bodies */
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t c = 0; c < nc; ++c) {
+            if (t->nch[c] != 0) continue;
+            for (int32_t i = t->beg[c]; i < t->end[c]; ++i) {
+                const double *xi = xs[r] + 3 * (int64_t)i;
+                double pp = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+                /* local P2P, then the senders' bodies */
+                for (int s = -1; s < R; ++s) {
+                    const otree *ts = s < 0 ? t : L->T[s];
+                    const double *xsrc = s < 0 ? xs[r] : xs[s];
+                    const double *qsrc = s < 0 ? qs[r] : qs[s];
+                    int64_t k0, k1;
+                    const uint64_t *pv = NULL;
+                    if (s < 0) { k0 = t->p2p_off[c]; k1 = t->p2p_off[c + 1]; }
+                    else {
+                        const int64_t *o = off[3 * s + 1];
+                        k0 = o[c];
+                        k1 = o[c + 1];
+                        pv = L->rp2p[(int64_t)r * R + s].v;
+                    }
+                    for (int64_t k = k0; k < k1; ++k) {
+                        const int64_t b = pv ? (int64_t)(pv[k] & 0xffffffffu) : t->p2p_src[k];
+                        for (int32_t j = ts->beg[b]; j < ts->end[b]; ++j) {
+                            double dx = xi[0] - xsrc[3 * (int64_t)j], dy = xi[1] - xsrc[3 * (int64_t)j + 1],
+                                   dz = xi[2] - xsrc[3 * (int64_t)j + 2];
+                            double r2 = dx * dx + dy * dy + dz * dz;
+                            if (r2 == 0.0) continue;
+                            double rr = sqrt(r2);
+                            double qr = qsrc[j] / rr;
+                            double qr3 = qr / r2;
+                            pp += qr;
+                            ex += qr3 * dx;
+                            ey += qr3 * dy;
+                            ez += qr3 * dz;
+                        }
+                    }
+                }
+                /* M2P of the multipole-only cells of the senders */
+                double mp = 0.0, Em[3] = {0.0, 0.0, 0.0};
+                for (int s = 0; s < R; ++s) {
+                    const int64_t rs = (int64_t)r * R + s;
+                    const int64_t *o = off[3 * s + 2];
+                    for (int64_t k = o[c]; k < o[c + 1]; ++k) {
+                        const int64_t b = (int64_t)(L->rm2p[rs].v[k] & 0xffffffffu);
+                        m2p_add(M[s] + b * P2, L->T[s]->ctr + 3 * b, p, xi, &mp, Em);
+                    }
+                }
+                double lp, E[3];
+                l2p_eval(Lr + c * P2, t->ctr + 3 * c, p, xi, &lp, E);
+                const int64_t orig = L->mem[L->rstart[r] + t->perm[i]];
+                if (phi) phi[orig] = lp + pp + mp;
+                if (field) {
+                    field[3 * orig] = E[0] + ex + Em[0];
+                    field[3 * orig + 1] = E[1] + ey + Em[1];
+                    field[3 * orig + 2] = E[2] + ez + Em[2];
+                }
+            }
+        }
+        for (int k = 0; k < 3 * R; ++k) free(off[k]);
+        free(off);
+    }
+    for (int r = 0; r < R; ++r) {
+        free(M[r]); free(Lc[r]); free(xs[r]); free(qs[r]);
+    }
+    free(M); free(Lc); free(xs); free(qs);
+    return 0;
+}
+
 /* Convenience: one-shot FMM at the coordinates the tree was built from.   */
 int oracle_fmm(const void *h, const double *x, const double *q, int p, int64_t nt,
                const int64_t *targets, double *phi, double *field)

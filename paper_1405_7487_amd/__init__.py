@@ -16,6 +16,8 @@ from ._binding import (  # noqa: F401
     Plan,
     build,
     evaluate,
+    evaluate_noalloc,
+    let_evaluate,
     load,
     mfma_layout,
 )

@@ -24,7 +24,8 @@ PREC = {"fp64": 0, "mixed": 1}
 EXPORTS = (
     "fmm_params_default", "fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_adjoint",
     "fmm_plan_stats", "fmm_export_tree", "fmm_set_timing", "fmm_destroy", "fmm_last_error",
-    "fmm_debug_mfma_layout", "fmm_list_digest", "fmm_count_body_pairs",
+    "fmm_debug_mfma_layout", "fmm_list_digest", "fmm_count_body_pairs", "fmm_evaluate_noalloc",
+    "fmm_let_evaluate",
 )
 
 
@@ -61,6 +62,15 @@ class _Stats(C.Structure):
                 ("p2p_cut_leaves", C.c_int64)]
 
 
+class _LetStats(C.Structure):
+    _fields_ = [("nrank", C.c_int32), ("let_cells", C.c_int64), ("let_far", C.c_int64),
+                ("let_body_leaves", C.c_int64), ("let_bodies", C.c_int64), ("let_bytes", C.c_int64),
+                ("n_m2l_local", C.c_int64), ("n_p2p_local", C.c_int64), ("n_m2l_remote", C.c_int64),
+                ("n_p2p_remote", C.c_int64), ("n_m2p_remote", C.c_int64), ("device_bytes", C.c_int64),
+                ("ms_partition", C.c_double), ("ms_build", C.c_double), ("ms_let", C.c_double),
+                ("ms_evaluate", C.c_double), ("ms_total", C.c_double)]
+
+
 class _Export(C.Structure):
     _fields_ = [("keys", C.c_void_p), ("perm", C.c_void_p), ("level", C.c_void_p), ("cell_key", C.c_void_p),
                 ("begin", C.c_void_p), ("end", C.c_void_p), ("parent", C.c_void_p), ("child_begin", C.c_void_p),
@@ -85,6 +95,10 @@ def load():
     L.fmm_evaluate.argtypes = [vp, vp, C.c_int, C.c_int64, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                C.POINTER(_Allocator), vp, vp, vp]
     L.fmm_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.fmm_let_evaluate.argtypes = [vp, vp, C.c_int, C.c_int64, C.c_int32, vp, C.POINTER(_Params),
+                                   C.POINTER(_Allocator), vp, vp, vp, vp, vp, vp, C.POINTER(_LetStats), vp]
+    L.fmm_evaluate_noalloc.argtypes = [vp, vp, C.c_int, C.c_int64, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                       vp, vp, vp]
     L.fmm_plan_stats.argtypes = [vp, C.POINTER(_Stats)]
     L.fmm_export_tree.argtypes = [vp, C.POINTER(_Export)]
     L.fmm_set_timing.argtypes = [vp, C.c_int32]
@@ -94,7 +108,9 @@ def load():
     L.fmm_debug_mfma_layout.argtypes = [C.c_int32, vp]
     L.fmm_list_digest.argtypes = [vp, C.POINTER(C.c_uint64)]
     L.fmm_count_body_pairs.argtypes = [vp, C.POINTER(C.c_int64)]
-    for name in ("fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_adjoint", "fmm_plan_stats",
+    for name in ("fmm_build", "fmm_evaluate_plan", "fmm_evaluate", "fmm_evaluate_noalloc", "fmm_let_evaluate",
+                 "fmm_adjoint",
+                 "fmm_plan_stats",
                  "fmm_export_tree", "fmm_set_timing", "fmm_debug_mfma_layout", "fmm_list_digest",
                  "fmm_count_body_pairs"):
         getattr(L, name).restype = C.c_int
@@ -339,6 +355,61 @@ def evaluate(x: torch.Tensor, q: torch.Tensor, p: int = 8, theta: float = 0.4, n
                               C.c_void_p(phi.data_ptr()), C.c_void_p(E.data_ptr()) if E is not None else None,
                               _stream_handle()))
     return phi, E
+
+
+def evaluate_noalloc(x: torch.Tensor, q: torch.Tensor, p: int = 8, theta: float = 0.4, ncrit: int = 64,
+                     precision: str = "mixed", field: bool = True, out=None):
+    """fmm_evaluate_noalloc: the one-shot evaluation with every device buffer
+    in the library's static scratch (no device allocation by the library).
+    out = (phi, E) writes into existing tensors (E may be None)."""
+    L = load()
+    x = _coords(x)
+    n = int(x.shape[0])
+    q = _dev(q, "q", (n,), x.dtype, x.device)
+    if out is None:
+        phi = torch.empty(n, dtype=x.dtype, device=x.device)
+        E = torch.empty((n, 3), dtype=x.dtype, device=x.device) if field else None
+    else:
+        phi = _out(out[0], "phi", (n,), x.dtype, x.device)
+        E = _out(out[1], "E", (n, 3), x.dtype, x.device) if out[1] is not None else None
+    with torch.cuda.device(x.device):
+        _check(L.fmm_evaluate_noalloc(C.c_void_p(x.data_ptr()), C.c_void_p(q.data_ptr()), _dtype_code(x), n,
+                                      int(p), float(theta), int(ncrit), PREC[precision], C.c_void_p(phi.data_ptr()),
+                                      C.c_void_p(E.data_ptr()) if E is not None else None, _stream_handle()))
+    return phi, E
+
+
+def let_evaluate(x: torch.Tensor, q: torch.Tensor, nrank: int, params: Params | None = None,
+                 weights: torch.Tensor | None = None, field: bool = True, work: bool = False) -> dict:
+    """fmm_let_evaluate: the evaluation over nrank virtual ranks (ORB
+    partition weighted by `weights`, local trees, LETs, remote traversals).
+
+    Returns a dict with phi, E (or None), rank (int32 per body), work_local
+    and work_remote (int64 per body, when work=True), pair_stats (numpy,
+    nrank x nrank x 11) and stats (dict of fmm_let_stats)."""
+    import numpy as np
+    L = load()
+    params = params or Params()
+    x = _coords(x)
+    n = int(x.shape[0])
+    q = _dev(q, "q", (n,), x.dtype, x.device)
+    if weights is not None:
+        weights = _dev(weights, "weights", (n,), torch.int64, x.device)
+    phi = torch.empty(n, dtype=x.dtype, device=x.device)
+    E = torch.empty((n, 3), dtype=x.dtype, device=x.device) if field else None
+    rank = torch.empty(n, dtype=torch.int32, device=x.device)
+    wl = torch.empty(n, dtype=torch.int64, device=x.device) if work else None
+    wr = torch.empty(n, dtype=torch.int64, device=x.device) if work else None
+    ps = np.zeros((nrank, nrank, 11), np.int64)
+    st = _LetStats()
+    cp = params.to_c()
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None else None
+    with torch.cuda.device(x.device):
+        _check(L.fmm_let_evaluate(ptr(x), ptr(q), _dtype_code(x), n, int(nrank), ptr(weights), C.byref(cp),
+                                  C.byref(_TORCH_ALLOCATOR), ptr(phi), ptr(E), ptr(rank), ptr(wl), ptr(wr),
+                                  C.c_void_p(ps.ctypes.data), C.byref(st), _stream_handle()))
+    return dict(phi=phi, E=E, rank=rank, work_local=wl, work_remote=wr, pair_stats=ps,
+                stats={k: getattr(st, k) for k, _ in _LetStats._fields_})
 
 
 def mfma_layout(f64: bool) -> list:

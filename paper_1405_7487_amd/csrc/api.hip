@@ -20,6 +20,14 @@ namespace {
 
 thread_local std::string g_err;
 
+// Set by fmm_evaluate_noalloc around its fmm_build: the plan then takes every
+// device buffer from this range instead of allocating.
+struct ArenaRange {
+    char *base;
+    size_t cap;
+};
+thread_local ArenaRange fmm_plan_arena_ = {nullptr, 0};
+
 // ------------------------------------------------------------ caching pool
 struct Pool {
     std::mutex mu;
@@ -104,6 +112,16 @@ static AllocState &state_of(const Allocator *a)
 void *Allocator::alloc(size_t bytes)
 {
     if (bytes == 0) bytes = 1;
+    if (arena) {
+        const size_t off = (arena_top + 255) / 256 * 256;
+        if (off > arena_cap || bytes > arena_cap - off)
+            throw Error(FMM_ERR_NOMEM, "the static scratch of " + std::to_string(arena_cap >> 20) +
+                                           " MiB is exhausted (" + std::to_string(off + bytes) + " bytes needed so far)");
+        arena_blocks.push_back({off, off + bytes});
+        arena_top = off + bytes;
+        arena_peak = std::max(arena_peak, arena_top);
+        return arena + off;
+    }
     void *p = has_user ? user.alloc(bytes, (void *)stream, user.ctx) : pool_get(bytes);
     if (!p) throw Error(FMM_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     state_of(this).live.insert(p);
@@ -113,6 +131,17 @@ void *Allocator::alloc(size_t bytes)
 void Allocator::free(void *p)
 {
     if (!p) return;
+    if (arena) {
+        const size_t off = (size_t)(static_cast<char *>(p) - arena);
+        for (size_t k = arena_blocks.size(); k-- > 0;)
+            if (arena_blocks[k].first == off && arena_blocks[k].second) {
+                arena_blocks[k].second = 0;
+                break;
+            }
+        while (!arena_blocks.empty() && arena_blocks.back().second == 0) arena_blocks.pop_back();
+        arena_top = arena_blocks.empty() ? 0 : arena_blocks.back().second;
+        return;
+    }
     AllocState &st = state_of(this);
     st.live.erase(p);
     if (has_user) user.free(p, (void *)stream, user.ctx);
@@ -121,6 +150,7 @@ void Allocator::free(void *p)
 
 static void allocator_flush(Allocator &a)
 {
+    if (a.arena) return;
     AllocState &st = state_of(&a);
     for (void *p : st.parked) pool_put(p);
     st.parked.clear();
@@ -128,6 +158,11 @@ static void allocator_flush(Allocator &a)
 
 static void allocator_release_all(Allocator &a)
 {
+    if (a.arena) {
+        a.arena_blocks.clear();
+        a.arena_top = 0;
+        return;
+    }
     AllocState &st = state_of(&a);
     for (void *p : st.live) {
         if (a.has_user) a.user.free(p, (void *)a.stream, a.user.ctx);
@@ -226,8 +261,8 @@ void ev_rec(fmm_plan *P, int ph, bool start, hipStream_t s)
     if (!start) it->second.used[ph] = true;
 }
 
-template <class V4, class TC>
-void run_pipeline(fmm_plan *P, const void *q, void *ub, void *phi_s, void *E_s, hipStream_t s)
+template <class V4>
+void set_charge(fmm_plan *P, const void *q, void *ub, hipStream_t s)
 {
     const int64_t n = P->n;
     if (P->dtype == FMM_F64)
@@ -237,30 +272,13 @@ void run_pipeline(fmm_plan *P, const void *q, void *ub, void *phi_s, void *E_s, 
         k_set_charge<float, V4><<<grid1(n, 256), 256, 0, s>>>(static_cast<const float *>(q), P->perm, n,
                                                                static_cast<V4 *>(ub));
     FMM_HIP(hipGetLastError());
-    ev_rec(P, PH_P2M, true, s);
-    upward(P, ub, s);
-    ev_rec(P, PH_P2M, false, s);
-    ev_rec(P, PH_M2L, true, s);
-    m2l_same(P, s);
-    ev_rec(P, PH_M2L, false, s);
-    ev_rec(P, PH_M2LX, true, s);
-    m2l_cross(P, s);
-    ev_rec(P, PH_M2LX, false, s);
-    ev_rec(P, PH_L2L, true, s);
-    downward_l2l(P, s);
-    ev_rec(P, PH_L2L, false, s);
-    ev_rec(P, PH_P2P, true, s);
-    p2p(P, ub, phi_s, E_s, s);
-    ev_rec(P, PH_P2P, false, s);
-    ev_rec(P, PH_L2P, true, s);
-    l2p(P, ub, phi_s, E_s, s);
-    ev_rec(P, PH_L2P, false, s);
 }
 
 void pipeline(fmm_plan *P, const void *q, void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
-    if (P->precision == FMM_PREC_FP64) run_pipeline<double4, double>(P, q, ub, phi_s, E_s, s);
-    else run_pipeline<float4, float>(P, q, ub, phi_s, E_s, s);
+    eval_up(P, q, ub, s);
+    eval_m2l(P, s);
+    eval_down(P, ub, phi_s, E_s, s);
 }
 
 fmm_status fail(const Error &e)
@@ -320,7 +338,76 @@ void validate_params(const fmm_params &p)
               "coarse_fp64_levels must be in [0, 22]");
 }
 
+// ------------------------------------------------------------ no-alloc scratch
+// Device memory of fmm_evaluate_noalloc: one array per GPU, resident from the
+// library's load until the process ends.  In host code the array's name only
+// stands for the symbol; kernels and copies use the per-device address that
+// hipGetSymbolAddress returns.
+constexpr size_t kScratchBytes = FMM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct ScratchSlot {
+    std::mutex mu;   // calls on one device run one after another
+    char *ptr = nullptr;
+};
+ScratchSlot g_scratch[64];
+std::mutex g_scratch_mu;
+
+// The scratch of the current device (looked up once per device).
+ScratchSlot &scratch_slot()
+{
+    int dev = 0;
+    FMM_HIP(hipGetDevice(&dev));
+    FMM_CHECK(dev >= 0 && dev < 64, FMM_ERR_UNSUPPORTED, "device index beyond 63");
+    ScratchSlot &sl = g_scratch[dev];
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!sl.ptr) {
+        void *ptr = nullptr;
+        FMM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        FMM_CHECK(ptr != nullptr, FMM_ERR_DEVICE, "no address for the scratch array");
+        sl.ptr = static_cast<char *>(ptr);
+    }
+    return sl;
+}
+
 }  // namespace
+
+// The evaluation in three phases (the order of Section II.C): charges into
+// the sorted bodies and the upward pass; M2L over the traversal's lists (the
+// local expansions start from zero here); the downward pass with P2P and L2P.
+void eval_up(fmm_plan *P, const void *q, void *ub, hipStream_t s)
+{
+    if (P->precision == FMM_PREC_FP64) set_charge<double4>(P, q, ub, s);
+    else set_charge<float4>(P, q, ub, s);
+    ev_rec(P, PH_P2M, true, s);
+    upward(P, ub, s);
+    ev_rec(P, PH_P2M, false, s);
+}
+
+void eval_m2l(fmm_plan *P, hipStream_t s)
+{
+    ev_rec(P, PH_M2L, true, s);
+    m2l_same(P, s);
+    ev_rec(P, PH_M2L, false, s);
+    ev_rec(P, PH_M2LX, true, s);
+    m2l_cross(P, s);
+    ev_rec(P, PH_M2LX, false, s);
+}
+
+void eval_down(fmm_plan *P, void *ub, void *phi_s, void *E_s, hipStream_t s)
+{
+    ev_rec(P, PH_L2L, true, s);
+    downward_l2l(P, s);
+    ev_rec(P, PH_L2L, false, s);
+    ev_rec(P, PH_P2P, true, s);
+    p2p(P, ub, phi_s, E_s, s);
+    ev_rec(P, PH_P2P, false, s);
+    ev_rec(P, PH_L2P, true, s);
+    l2p(P, ub, phi_s, E_s, s);
+    ev_rec(P, PH_L2P, false, s);
+}
+
+void allocator_done(Allocator &a) { allocator_release_all(a); }
 
 void mfma_probe(int f64, void *out_host);
 
@@ -375,7 +462,11 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         P->kahan = pr.kahan ? 1 : 0;
         P->dtype = dtype;
         P->al.stream = s;
-        if (alloc) {
+        if (fmm_plan_arena_.base) {
+            P->al.arena = fmm_plan_arena_.base;
+            P->al.arena_cap = fmm_plan_arena_.cap;
+            P->noalloc = true;
+        } else if (alloc) {
             P->al.user = *alloc;
             P->al.has_user = true;
         }
@@ -505,6 +596,63 @@ fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n
     st = fmm_evaluate_plan(P, q, phi, field, hip_stream);
     fmm_destroy(P);
     return st;
+}
+
+fmm_status fmm_evaluate_noalloc(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t p, double theta,
+                                int32_t ncrit, int32_t precision, void *phi, void *field, void *hip_stream)
+{
+    g_err.clear();
+    return guarded([&]() -> fmm_status {
+        FMM_CHECK(n >= 0, FMM_ERR_INVALID, "n < 0");
+        if (n == 0) return FMM_OK;
+        FMM_CHECK(x && q && phi, FMM_ERR_INVALID, "x, q or phi is NULL");
+        FMM_CHECK(n <= FMM_NOALLOC_MAX_N, FMM_ERR_UNSUPPORTED,
+                  "fmm_evaluate_noalloc: n = " + std::to_string(n) + " exceeds its limit of " +
+                      std::to_string((long long)FMM_NOALLOC_MAX_N) + " bodies");
+        ScratchSlot &sl = scratch_slot();
+        std::lock_guard<std::mutex> lk(sl.mu);
+        fmm_plan_arena_ = {sl.ptr, kScratchBytes};
+        fmm_params pr;
+        fmm_params_default(&pr);
+        pr.p = p;
+        pr.theta = theta;
+        pr.ncrit = ncrit;
+        pr.precision = precision;
+        fmm_plan *P = nullptr;
+        fmm_status st = fmm_build(x, dtype, n, &pr, nullptr, hip_stream, &P);
+        fmm_plan_arena_ = {nullptr, 0};
+        if (st != FMM_OK) return st;
+        st = fmm_evaluate_plan(P, q, phi, field, hip_stream);
+        const std::string err = g_err;
+        fmm_destroy(P);  // synchronises the stream: the scratch is free again
+        g_err = err;
+        return st;
+    });
+}
+
+fmm_status fmm_let_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t nrank,
+                            const int64_t *weights, const fmm_params *prm, const fmm_allocator *alloc, void *phi,
+                            void *field, int32_t *rank, int64_t *work_local, int64_t *work_remote,
+                            int64_t *pair_stats, fmm_let_stats *stats, void *hip_stream)
+{
+    g_err.clear();
+    return guarded([&]() -> fmm_status {
+        FMM_CHECK(n >= 0, FMM_ERR_INVALID, "n < 0");
+        FMM_CHECK(nrank >= 1 && nrank <= 1024, FMM_ERR_INVALID, "nrank must be in [1, 1024]");
+        FMM_CHECK(dtype == FMM_F64 || dtype == FMM_F32, FMM_ERR_INVALID, "bad dtype");
+        FMM_CHECK(n < (1ll << 31), FMM_ERR_UNSUPPORTED, "n >= 2^31");
+        FMM_CHECK(!alloc || (alloc->alloc && alloc->free), FMM_ERR_INVALID, "allocator without callbacks");
+        fmm_params pr;
+        fmm_params_default(&pr);
+        if (prm) pr = *prm;
+        validate_params(pr);
+        if (stats) *stats = fmm_let_stats{};
+        if (n == 0) return FMM_OK;
+        FMM_CHECK(x && q && phi, FMM_ERR_INVALID, "x, q or phi is NULL");
+        let_evaluate(x, q, dtype, n, nrank, weights, pr, alloc, phi, field, rank, work_local, work_remote,
+                     pair_stats, stats, static_cast<hipStream_t>(hip_stream));
+        return FMM_OK;
+    });
 }
 
 fmm_status fmm_adjoint(fmm_plan *P, const void *q, const void *grad_phi, const void *field_q, void *dq, void *dx,

@@ -512,10 +512,20 @@ void make_operators(fmm_plan *P, hipStream_t s)
     FMM_HIP(hipGetDevice(&dev));
     uint64_t bits;
     std::memcpy(&bits, &P->t4, sizeof(bits));
-    std::lock_guard<std::mutex> lk(g_ops_mu);
+    std::unique_lock<std::mutex> lk(g_ops_mu, std::defer_lock);
     const auto key = std::make_tuple(dev, P->p, bits, f64 ? 1 : 0);
-    auto it = g_ops.find(key);
-    if (it == g_ops.end()) {
+    // a plan that may not allocate builds its own tables in its own memory
+    auto dmalloc = [&](void **ptr, size_t bytes) {
+        if (P->noalloc) *ptr = plan_alloc(P, bytes);
+        else FMM_HIP(hipMalloc(ptr, bytes));
+    };
+    std::map<std::tuple<int, int, uint64_t, int>, OpCache> own;
+    auto it = own.end();
+    if (!P->noalloc) {
+        lk.lock();
+        it = g_ops.find(key);
+    }
+    if (P->noalloc || it == g_ops.end()) {
         OpCache C;
         const int esz = f64 ? (int)sizeof(double) : (int)sizeof(float);
         const int Q = m2l_q(P->p);
@@ -524,9 +534,9 @@ void make_operators(fmm_plan *P, hipStream_t s)
         for (int k = 0; k < P->nops; ++k)
             tr[k] = make_double4(P->h_ops_t[3 * k], P->h_ops_t[3 * k + 1], P->h_ops_t[3 * k + 2], 0.0);
         double4 *d_ot = nullptr;
-        FMM_HIP(hipMalloc(&d_ot, sizeof(double4) * tr.size()));
-        FMM_HIP(hipMemcpy(d_ot, tr.data(), sizeof(double4) * tr.size(), hipMemcpyHostToDevice));
-        FMM_HIP(hipMalloc(&C.ops, (f64 ? sizeof(double) : sizeof(float)) * opn));
+        dmalloc((void **)&d_ot, sizeof(double4) * tr.size());
+        FMM_HIP(hipMemcpyAsync(d_ot, tr.data(), sizeof(double4) * tr.size(), hipMemcpyHostToDevice, s));
+        dmalloc(&C.ops, (f64 ? sizeof(double) : sizeof(float)) * opn);
         FMM_HIP(hipMemsetAsync(C.ops, 0, (f64 ? sizeof(double) : sizeof(float)) * opn, s));
         if (P->nops > 0) {
             if (f64)
@@ -536,23 +546,27 @@ void make_operators(fmm_plan *P, hipStream_t s)
             FMM_HIP(hipGetLastError());
         }
         const size_t shn = (size_t)8 * P2pad * P2pad;
-        FMM_HIP(hipMalloc(&C.m2m_d, sizeof(double) * shn));
-        FMM_HIP(hipMalloc(&C.l2l_d, sizeof(double) * shn));
+        dmalloc((void **)&C.m2m_d, sizeof(double) * shn);
+        dmalloc((void **)&C.l2l_d, sizeof(double) * shn);
         k_make_shift_ops<<<8, 256, 0, s>>>(P->p, P2pad, C.m2m_d, C.l2l_d);
         FMM_HIP(hipGetLastError());
         if (f64) {
             C.m2m_c = C.m2m_d;
             C.l2l_c = C.l2l_d;
         } else {
-            FMM_HIP(hipMalloc(&C.m2m_c, sizeof(float) * shn));
-            FMM_HIP(hipMalloc(&C.l2l_c, sizeof(float) * shn));
+            dmalloc(&C.m2m_c, sizeof(float) * shn);
+            dmalloc(&C.l2l_c, sizeof(float) * shn);
             k_d2f<<<grid1(shn, 256), 256, 0, s>>>(C.m2m_d, static_cast<float *>(C.m2m_c), shn);
             k_d2f<<<grid1(shn, 256), 256, 0, s>>>(C.l2l_d, static_cast<float *>(C.l2l_c), shn);
             FMM_HIP(hipGetLastError());
         }
         FMM_HIP(hipStreamSynchronize(s));
-        FMM_HIP(hipFree(d_ot));
-        it = g_ops.emplace(key, C).first;
+        if (P->noalloc) {
+            it = own.emplace(key, C).first;  // d_ot stays in the plan's memory
+        } else {
+            FMM_HIP(hipFree(d_ot));
+            it = g_ops.emplace(key, C).first;
+        }
     }
     const OpCache &C = it->second;
     P->ops = C.ops;

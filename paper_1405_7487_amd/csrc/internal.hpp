@@ -108,10 +108,17 @@ __host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (R
 __host__ __device__ constexpr int m2l_wv(int RT, bool f64) { return 4; }
 
 // ---------------------------------------------------------------- memory
+// Device memory of a plan: the caller's callbacks, the library's caching pool,
+// or (for the entry point that allocates nothing) bump allocation inside a
+// fixed device range, where freeing the most recent blocks gives their space
+// back and running past the range is FMM_ERR_NOMEM.
 struct Allocator {
     fmm_allocator user{};
     bool has_user = false;
     hipStream_t stream = nullptr;
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_top = 0, arena_peak = 0;
+    std::vector<std::pair<size_t, size_t>> arena_blocks;  // (offset, end), end 0 once freed
     void *alloc(size_t bytes);
     void free(void *p);
 };
@@ -148,6 +155,7 @@ struct fmm_plan {
     fmm_dtype dtype = FMM_F64;
     int timing = 0;
     fmm::Allocator al;
+    bool noalloc = false;            // tables that are cached per device elsewhere come from al
     std::vector<fmm::Buf> owned;
     int64_t bytes_held = 0;
 
@@ -279,6 +287,17 @@ void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s);
 void p2p_prepare(fmm_plan *P, hipStream_t s);
 // api.hip helpers
 void gather_bodies(fmm_plan *P, const void *q, void *ub, hipStream_t s);
+// the evaluation's phases: charges + upward pass; M2L (local expansions
+// zeroed first); downward pass + P2P + L2P
+void eval_up(fmm_plan *P, const void *q, void *ub, hipStream_t s);
+void eval_m2l(fmm_plan *P, hipStream_t s);
+void eval_down(fmm_plan *P, void *ub, void *phi_s, void *E_s, hipStream_t s);
+// hands back every block an allocator still holds
+void allocator_done(Allocator &a);
+// let.hip: the virtual-rank evaluation behind fmm_let_evaluate
+void let_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int R, const int64_t *w,
+                  const fmm_params &prm, const fmm_allocator *ualloc, void *phi, void *field, int32_t *rank_out,
+                  int64_t *work_l, int64_t *work_r, int64_t *pair_stats, fmm_let_stats *stats, hipStream_t s);
 
 void *plan_alloc(fmm_plan *P, size_t bytes);
 // One work-item per element.  A dispatch counts its work-items in 32 bits, so

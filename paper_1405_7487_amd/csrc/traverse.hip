@@ -384,7 +384,8 @@ struct StencilCache {
 std::mutex g_stencil_mu;
 std::map<std::pair<int, uint64_t>, StencilCache> g_stencils;
 
-StencilCache make_stencils(double t4)
+// Host part: the stencils, and the device tables' contents in op and kidx.
+StencilCache make_stencils(double t4, std::vector<int32_t> &op, std::vector<int32_t> &kidx)
 {
     StencilCache C;
     // parent offsets that fail the criterion satisfy |T|^2 <= 12 / t4
@@ -417,7 +418,8 @@ StencilCache make_stencils(double t4)
     C.nops = id;
     // stencil entries in lexicographic offset order (= operator order), so
     // that all classes sweep the operator table alike
-    std::vector<int32_t> op(std::max<size_t>(1, 8 * K), -1), kidx((size_t)8 * (2 * R + 1) * (2 * R + 1) * (2 * R + 1), -1);
+    op.assign(std::max<size_t>(1, 8 * K), -1);
+    kidx.assign((size_t)8 * (2 * R + 1) * (2 * R + 1) * (2 * R + 1), -1);
     C.st_t.assign(8 * K * 3, 0);
     const int W = 2 * R + 1;
     for (int c = 0; c < 8; ++c) {
@@ -429,6 +431,14 @@ StencilCache make_stencils(double t4)
             kidx[(size_t)c * W * W * W + ((t[0] + R) * W + (t[1] + R)) * W + (t[2] + R)] = (int32_t)k;
         }
     }
+    return C;
+}
+
+// Stencils with their device tables, cached per (device, theta).
+StencilCache make_stencils_cached(double t4)
+{
+    std::vector<int32_t> op, kidx;
+    StencilCache C = make_stencils(t4, op, kidx);
     FMM_HIP(hipMalloc(&C.d_op, sizeof(int32_t) * op.size()));
     FMM_HIP(hipMalloc(&C.d_kidx, sizeof(int32_t) * kidx.size()));
     FMM_HIP(hipMemcpy(C.d_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice));
@@ -437,17 +447,33 @@ StencilCache make_stencils(double t4)
 }
 }  // namespace
 
-static void build_stencils(fmm_plan *P)
+static void build_stencils(fmm_plan *P, hipStream_t s)
 {
     int dev = 0;
     FMM_HIP(hipGetDevice(&dev));
     uint64_t bits;
     std::memcpy(&bits, &P->t4, sizeof(bits));
-    std::lock_guard<std::mutex> lk(g_stencil_mu);
-    auto key = std::make_pair(dev, bits);
-    auto it = g_stencils.find(key);
-    if (it == g_stencils.end()) it = g_stencils.emplace(key, make_stencils(P->t4)).first;
-    const StencilCache &C = it->second;
+    StencilCache own;
+    const StencilCache *Cp = nullptr;
+    std::unique_lock<std::mutex> lk(g_stencil_mu, std::defer_lock);
+    if (P->noalloc) {
+        // a plan that may not allocate keeps its own copy of the tables
+        std::vector<int32_t> op, kidx;
+        own = make_stencils(P->t4, op, kidx);
+        own.d_op = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * op.size()));
+        own.d_kidx = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * kidx.size()));
+        FMM_HIP(hipMemcpyAsync(own.d_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice, s));
+        FMM_HIP(hipMemcpyAsync(own.d_kidx, kidx.data(), sizeof(int32_t) * kidx.size(), hipMemcpyHostToDevice, s));
+        FMM_HIP(hipStreamSynchronize(s));
+        Cp = &own;
+    } else {
+        lk.lock();
+        auto key = std::make_pair(dev, bits);
+        auto it = g_stencils.find(key);
+        if (it == g_stencils.end()) it = g_stencils.emplace(key, make_stencils_cached(P->t4)).first;
+        Cp = &it->second;
+    }
+    const StencilCache &C = *Cp;
     P->K = C.K;
     P->R = C.R;
     P->st_reach = C.reach;
@@ -556,7 +582,7 @@ void traverse(fmm_plan *P, hipStream_t s)
 {
     Allocator &al = P->al;
     const int64_t nc = P->ncell;
-    build_stencils(P);
+    build_stencils(P, s);
 
     // Octant-class tiles per level (levels >= 1).
     const int G = (kLevels + 1) * 8;
