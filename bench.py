@@ -110,6 +110,11 @@ def main():
                     help="targets of the single-thread oracle run (-1: an eighth of the sample, 0: skip)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 GPU forward runs (0 = skip)")
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
+    ap.add_argument("--tight", action="store_true",
+                    help="acceptance also by cell radii tight to the bodies (fewer M2L and P2P pairs)")
+    ap.add_argument("--let-ranks", default="",
+                    help="comma-separated virtual rank counts: also time the evaluation split over that many "
+                         "ranks (ORB + LET on this GPU) and report LET sizes and timings per count")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (the reference for HBM counters) and exit")
     args = ap.parse_args()
@@ -140,7 +145,7 @@ def main():
     x = torch.as_tensor(x_np, device=dev)
     q = torch.as_tensor(q_np, device=dev)
     w = torch.as_tensor(w_np, device=dev)
-    prm = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision=args.precision)
+    prm = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision=args.precision, tight=args.tight)
     log(f"bench: {args.config} n={n} p={cfg['p']} theta={cfg['theta']} ncrit={cfg['ncrit']} {args.precision}")
     stream = torch.cuda.current_stream()
     new_plan = lambda timing=False: F.Plan(x, prm, timing=timing, torch_allocator=not args.pool)
@@ -246,7 +251,7 @@ def main():
     # FP64 GPU baseline (same build + forward), one warm-up run
     fp64_ms, phi64_h, E64_h = None, None, None
     if args.fp64_steps > 0 and args.precision != "fp64":
-        prm64 = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision="fp64")
+        prm64 = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision="fp64", tight=args.tight)
         times = []
         for k in range(args.fp64_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -270,6 +275,29 @@ def main():
     if phi64_h is not None:
         err["mixed_vs_fp64_gpu_all_bodies"] = {"phi": rel(phi_h, phi64_h), "E": rel(E_h, E64_h)}
 
+    let = []
+    for R in [int(v) for v in args.let_ranks.split(",") if v.strip()]:
+        out_l = None
+        times = []
+        for k in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out_l = F.let_evaluate(x, q, R, prm)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        st = out_l["stats"]
+        phl, Eal = out_l["phi"].cpu().numpy(), out_l["E"].cpu().numpy()
+        let.append({"ranks": R, "ms": times[-1], "particles_per_s": n / (times[-1] * 1e-3),
+                    "vs_single_tree_all_bodies": {"phi": float(np.linalg.norm(phl - phi_h) / np.linalg.norm(phi_h)),
+                                                  "E": float(np.linalg.norm(Eal - E_h) / np.linalg.norm(E_h))},
+                    **{k: st[k] for k in ("let_cells", "let_far", "let_body_leaves", "let_bodies", "let_bytes",
+                                          "n_m2l_local", "n_p2p_local", "n_m2l_remote", "n_p2p_remote",
+                                          "n_m2p_remote", "device_bytes", "ms_partition", "ms_build", "ms_let",
+                                          "ms_evaluate")}})
+        log(f"bench: {R} virtual ranks: {times[-1]:.1f} ms, LET {st['let_bytes'] / 2**20:.1f} MiB")
+        del out_l
+
     cpu, bad = None, False
     nt = ORACLE_TARGETS.get(args.config, 256) if args.oracle_targets < 0 else args.oracle_targets
     if nt > 0:
@@ -277,7 +305,7 @@ def main():
         tg = W.sample_targets(n, nt)
         cores = oracle.num_threads()
         c0 = time.perf_counter()
-        T = oracle.Tree(x_np, cfg["ncrit"], cfg["theta"], targets=tg, prune=True)
+        T = oracle.Tree(x_np, cfg["ncrit"], cfg["theta"], targets=tg, prune=True, tight=args.tight)
         po, Eo = T.fmm(q_np, cfg["p"], targets=tg)
         c1 = time.perf_counter()
         del T
@@ -295,7 +323,7 @@ def main():
         if ns > 0:
             oracle.set_num_threads(1)
             s0 = time.perf_counter()
-            T = oracle.Tree(x_np, cfg["ncrit"], cfg["theta"], targets=tg[:ns], prune=True)
+            T = oracle.Tree(x_np, cfg["ncrit"], cfg["theta"], targets=tg[:ns], prune=True, tight=args.tight)
             T.fmm(q_np, cfg["p"], targets=tg[:ns])
             s1 = time.perf_counter()
             del T
@@ -318,9 +346,10 @@ def main():
         "dtype": "f32" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: N={n} {cfg['dist']}, p={cfg['p']}, theta={cfg['theta']}, "
-                               f"ncrit={cfg['ncrit']}; forward (build + evaluate) and backward (plan rebuilt, "
-                               f"adjoint of L = sum w phi)", "n": n, "p": cfg["p"],
-                   "theta": cfg["theta"], "ncrit": cfg["ncrit"], "precision": args.precision},
+                               f"ncrit={cfg['ncrit']}{', tight radii' if args.tight else ''}; forward (build + "
+                               f"evaluate) and backward (plan rebuilt, adjoint of L = sum w phi)", "n": n,
+                   "p": cfg["p"], "theta": cfg["theta"], "ncrit": cfg["ncrit"], "precision": args.precision,
+                   "tight": args.tight},
         "forward_ms": t_fwd,
         "forward_ms_mean": float(np.mean(fwd)),
         "backward_ms": t_bwd,
@@ -337,6 +366,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if let:
+        out["virtual_ranks"] = let
     print(json.dumps(out), flush=True)
     if bad:
         log("bench: the accuracy bar was missed")

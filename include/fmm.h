@@ -80,10 +80,15 @@ typedef struct {
     int32_t coarse_fp64_levels; /* MIXED: levels 0 .. coarse_fp64_levels-1 keep float64
                                    multipole/local coefficients and translations (default 3)    */
     int32_t kahan;              /* MIXED: compensated P2P sums across source batches (default 1) */
+    int32_t tight;              /* 1: a pair is also accepted when the cells' radii about their
+                                   lattice centers, tight to their bodies (boxes squeezed to the
+                                   bodies, Section II.B, Fig. `orb2'), meet the criterion; the radius
+                                   is the farthest corner of a member body's 2^-21 lattice cell,
+                                   rounded up to units of S 2^-22 (default 0: cube radii only)     */
 } fmm_params;
 
 /* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3,
- * kahan=1.  P, theta and N_crit are the method parameters of Table I
+ * kahan=1, tight=0.  P, theta and N_crit are the method parameters of Table I
  * (Section III.A); the values are this library's defaults, not the paper's.
  * A NULL prm is ignored. */
 FMM_API void fmm_params_default(fmm_params *prm);

@@ -42,6 +42,9 @@ def lib():
         L.oracle_tree_new.restype = C.c_void_p
         L.oracle_tree_new2.argtypes = [C.c_int64, _dp, C.c_int32, C.c_double, C.c_int64, _i64p, C.c_int]
         L.oracle_tree_new2.restype = C.c_void_p
+        L.oracle_tree_new3.argtypes = [C.c_int64, _dp, C.c_int32, C.c_double, C.c_int64, _i64p, C.c_int, C.c_int]
+        L.oracle_tree_new3.restype = C.c_void_p
+        L.oracle_tree_radii.argtypes = [C.c_void_p, _i64p]
         L.oracle_tree_free.argtypes = [C.c_void_p]
         L.oracle_tree_info.argtypes = [C.c_void_p, _i64p, _dp]
         L.oracle_tree_digest.argtypes = [C.c_void_p, _u64p]
@@ -170,7 +173,8 @@ class Tree:
     counts then cover only the kept lists (for very large trees).
     """
 
-    def __init__(self, x, ncrit, theta, targets=None, count_only=False, prune=False, _handle=None, _owner=None):
+    def __init__(self, x, ncrit, theta, targets=None, count_only=False, prune=False, tight=False, _handle=None,
+                 _owner=None):
         if _handle is not None:
             # a tree owned by another object (a rank of a LET): no build, no free
             self._adopt(_handle, x, ncrit, theta, _owner)
@@ -187,7 +191,9 @@ class Tree:
         else:
             self.targets = np.ascontiguousarray(targets, dtype=np.int64)
             nt, tp = self.targets.size, self.targets.ctypes.data_as(_i64p)
-        h = lib().oracle_tree_new2(self.n, _d(self.x), self.ncrit, self.theta, nt, tp, 1 if prune else 0)
+        self.tight = bool(tight)
+        h = lib().oracle_tree_new3(self.n, _d(self.x), self.ncrit, self.theta, nt, tp, 1 if prune else 0,
+                                   1 if tight else 0)
         if not h:
             raise ValueError("oracle_tree_new: invalid input")
         self._h = h
@@ -223,6 +229,13 @@ class Tree:
         if h and getattr(self, "_owned", True):
             lib().oracle_tree_free(h)
         self._h = None
+
+    def radii(self):
+        """Radius of every cell tight to its bodies, in units S 2^-22 (zeros
+        unless the tree uses the tight criterion)."""
+        out = np.zeros(self.ncell, np.int64)
+        lib().oracle_tree_radii(self._h, out.ctypes.data_as(_i64p))
+        return out
 
     def export(self):
         n, nc = self.n, self.ncell

@@ -357,6 +357,8 @@ typedef struct {
     int64_t *m2l_off, *p2p_off;
     int32_t *m2l_src, *p2p_src;
     uint8_t *need;    /* target cell is an ancestor of (or is) a sampled leaf */
+    int tight;        /* acceptance also by the cells' own radii (rad)        */
+    int64_t *rad;     /* [ncell] radius in units of S 2^-22, or NULL          */
 } otree;
 
 typedef struct { uint64_t k; int64_t i; } kv;
@@ -410,7 +412,18 @@ static int mac(const otree *t, int a, int b)
         d2 += (ca - cb) * (ca - cb);
     }
     double lhs = (double)(3 * (sa + sb) * (sa + sb));
-    return lhs < t->t4 * (double)d2;
+    if (lhs < t->t4 * (double)d2) return 1;
+    if (!t->tight) return 0;
+    /* the cells' own radii (integers in units u = S 2^-22, centers at
+     * (2 i + 1) 2^(21 - l) u): 4 (r_A + r_B)^2 < (4 theta^2) D^2            */
+    int64_t D2 = 0;
+    for (int d = 0; d < 3; ++d) {
+        int64_t ca = (2 * (int64_t)t->ix[3 * a + d] + 1) << (ORC_LEVELS - la);
+        int64_t cb = (2 * (int64_t)t->ix[3 * b + d] + 1) << (ORC_LEVELS - lb);
+        D2 += (ca - cb) * (ca - cb);
+    }
+    const int64_t rs = t->rad[a] + t->rad[b];
+    return (double)(4 * rs * rs) < t->t4 * (double)D2;
 }
 
 static int is_leaf(const otree *t, int c) { return t->nch[c] == 0; }
@@ -574,11 +587,60 @@ static void csr_from_pairs(pbuf *b, int64_t ncell, int64_t **off, int32_t **src)
  * (count only).  prune != 0 (with targets) walks only pairs whose target is
  * kept; the counts then cover the kept lists only.  Returns NULL on invalid
  * input.                                                                    */
+void *oracle_tree_new3(int64_t n, const double *x, int32_t ncrit, double theta,
+                       int64_t nt, const int64_t *targets, int prune, int tight);
+
+/* Smallest r >= 0 with r^2 >= v (exact integer square root, rounded up). */
+static int64_t isqrt_ceil(int64_t v)
+{
+    int64_t r = (int64_t)sqrt((double)v);
+    while (r * r < v) ++r;
+    while (r > 0 && (r - 1) * (r - 1) >= v) --r;
+    return r;
+}
+
+/* Radius of every cell about its lattice center, tight to its bodies: the
+ * largest distance from the center to a corner of a member body's lattice
+ * cell (the body lies inside that cell), in units u = S 2^-22, rounded up
+ * to an integer.  Never above the cube's own bounding radius by more than
+ * one unit.                                                                */
+static void tight_radii(otree *t)
+{
+    t->rad = (int64_t *)calloc((size_t)t->ncell, sizeof(int64_t));
+    for (int64_t c = 0; c < t->ncell; ++c) {
+        const int l = t->lvl[c];
+        int64_t C[3], best = 0;
+        for (int d = 0; d < 3; ++d) C[d] = (2 * (int64_t)t->ix[3 * c + d] + 1) << (ORC_LEVELS - l);
+        for (int32_t j = t->beg[c]; j < t->end[c]; ++j) {
+            const uint64_t k = t->key[j];
+            int64_t r2 = 0;
+            for (int d = 0; d < 3; ++d) {
+                int64_t v = 0;
+                for (int b = 0; b < ORC_LEVELS; ++b) v |= (int64_t)((k >> (3 * b + 2 - d)) & 1ull) << b;
+                const int64_t lo = 2 * v - C[d], hi = 2 * v + 2 - C[d];
+                const int64_t m = llabs(lo) > llabs(hi) ? llabs(lo) : llabs(hi);
+                r2 += m * m;
+            }
+            if (r2 > best) best = r2;
+        }
+        t->rad[c] = isqrt_ceil(best);
+    }
+}
+
 void *oracle_tree_new2(int64_t n, const double *x, int32_t ncrit, double theta,
                        int64_t nt, const int64_t *targets, int prune)
 {
+    return oracle_tree_new3(n, x, ncrit, theta, nt, targets, prune, 0);
+}
+
+/* As oracle_tree_new2; tight != 0 also accepts a pair when the cells' own
+ * radii about their lattice centers (tight_radii) meet the criterion.      */
+void *oracle_tree_new3(int64_t n, const double *x, int32_t ncrit, double theta,
+                       int64_t nt, const int64_t *targets, int prune, int tight)
+{
     if (n <= 0 || !x || ncrit < 1 || !(theta > 0.0 && theta < 1.0)) return NULL;
     otree *t = (otree *)calloc(1, sizeof(otree));
+    t->tight = tight ? 1 : 0;
     t->n = n;
     t->ncrit = ncrit;
     t->theta = theta;
@@ -675,6 +737,8 @@ void *oracle_tree_new2(int64_t n, const double *x, int32_t ncrit, double theta,
         }
     }
 
+    if (t->tight) tight_radii(t);
+
     /* Which target cells keep lists. */
     t->need = (uint8_t *)calloc((size_t)nc, 1);
     if (!targets && nt >= 0) {
@@ -715,9 +779,16 @@ void oracle_tree_free(void *h)
     if (!t) return;
     free(t->key); free(t->perm);
     free(t->lvl); free(t->beg); free(t->end); free(t->par); free(t->cbeg); free(t->nch); free(t->ckey);
-    free(t->ix); free(t->ctr); free(t->need);
+    free(t->ix); free(t->ctr); free(t->need); free(t->rad);
     free(t->m2l_off); free(t->m2l_src); free(t->p2p_off); free(t->p2p_src);
     free(t);
+}
+
+/* radii of the tight criterion (units S 2^-22); zeros without it          */
+void oracle_tree_radii(const void *h, int64_t *out)
+{
+    const otree *t = (const otree *)h;
+    for (int64_t c = 0; c < t->ncell; ++c) out[c] = t->rad ? t->rad[c] : 0;
 }
 
 /* out: [digest of the M2L list, digest of the P2P list] over every pair the

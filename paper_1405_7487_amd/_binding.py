@@ -37,7 +37,7 @@ class FMMError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int32), ("theta", C.c_double), ("ncrit", C.c_int32), ("precision", C.c_int32),
-                ("coarse_fp64_levels", C.c_int32), ("kahan", C.c_int32)]
+                ("coarse_fp64_levels", C.c_int32), ("kahan", C.c_int32), ("tight", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -214,12 +214,13 @@ class Params:
     precision: str = "mixed"          # "mixed" or "fp64"
     coarse_fp64_levels: int = 3
     kahan: bool = True
+    tight: bool = False               # acceptance also by cell radii tight to the bodies
 
     def to_c(self) -> _Params:
         if self.precision not in PREC:
             raise ValueError("precision must be 'mixed' or 'fp64'")
         return _Params(int(self.p), float(self.theta), int(self.ncrit), PREC[self.precision],
-                       int(self.coarse_fp64_levels), 1 if self.kahan else 0)
+                       int(self.coarse_fp64_levels), 1 if self.kahan else 0, 1 if self.tight else 0)
 
 
 class Plan:

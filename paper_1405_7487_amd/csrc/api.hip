@@ -113,14 +113,22 @@ void *Allocator::alloc(size_t bytes)
 {
     if (bytes == 0) bytes = 1;
     if (arena) {
-        const size_t off = (arena_top + 255) / 256 * 256;
-        if (off > arena_cap || bytes > arena_cap - off)
-            throw Error(FMM_ERR_NOMEM, "the static scratch of " + std::to_string(arena_cap >> 20) +
-                                           " MiB is exhausted (" + std::to_string(off + bytes) + " bytes needed so far)");
-        arena_blocks.push_back({off, off + bytes});
-        arena_top = off + bytes;
-        arena_peak = std::max(arena_peak, arena_top);
-        return arena + off;
+        const size_t need = (bytes + 255) / 256 * 256;
+        if (arena_free.empty() && arena_used.empty()) arena_free[0] = arena_cap;
+        for (auto it = arena_free.begin(); it != arena_free.end(); ++it) {
+            if (it->second < need) continue;
+            const size_t off = it->first, left = it->second - need;
+            arena_free.erase(it);
+            if (left) arena_free[off + need] = left;
+            arena_used[off] = need;
+            arena_peak = std::max(arena_peak, off + need);
+            return arena + off;
+        }
+        size_t used = 0;
+        for (auto &kv : arena_used) used += kv.second;
+        throw Error(FMM_ERR_NOMEM, "the static scratch of " + std::to_string(arena_cap >> 20) +
+                                       " MiB is exhausted (" + std::to_string(used) + " bytes in use, " +
+                                       std::to_string(need) + " more asked for)");
     }
     void *p = has_user ? user.alloc(bytes, (void *)stream, user.ctx) : pool_get(bytes);
     if (!p) throw Error(FMM_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -133,13 +141,24 @@ void Allocator::free(void *p)
     if (!p) return;
     if (arena) {
         const size_t off = (size_t)(static_cast<char *>(p) - arena);
-        for (size_t k = arena_blocks.size(); k-- > 0;)
-            if (arena_blocks[k].first == off && arena_blocks[k].second) {
-                arena_blocks[k].second = 0;
-                break;
+        auto u = arena_used.find(off);
+        if (u == arena_used.end()) return;
+        size_t start = off, len = u->second;
+        arena_used.erase(u);
+        auto nx = arena_free.lower_bound(start);
+        if (nx != arena_free.end() && nx->first == start + len) {  // merge with the next free range
+            len += nx->second;
+            nx = arena_free.erase(nx);
+        }
+        if (nx != arena_free.begin()) {  // and with the previous one
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == start) {
+                start = pv->first;
+                len += pv->second;
+                arena_free.erase(pv);
             }
-        while (!arena_blocks.empty() && arena_blocks.back().second == 0) arena_blocks.pop_back();
-        arena_top = arena_blocks.empty() ? 0 : arena_blocks.back().second;
+        }
+        arena_free[start] = len;
         return;
     }
     AllocState &st = state_of(this);
@@ -159,8 +178,8 @@ static void allocator_flush(Allocator &a)
 static void allocator_release_all(Allocator &a)
 {
     if (a.arena) {
-        a.arena_blocks.clear();
-        a.arena_top = 0;
+        a.arena_used.clear();
+        a.arena_free.clear();  // the whole range is free again
         return;
     }
     AllocState &st = state_of(&a);
@@ -426,6 +445,7 @@ void fmm_params_default(fmm_params *prm)
     prm->precision = FMM_PREC_MIXED;
     prm->coarse_fp64_levels = 3;
     prm->kahan = 1;
+    prm->tight = 0;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -460,6 +480,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         P->TW = m2l_tile_width(pr.p, pr.precision == FMM_PREC_FP64);
         P->cfl = pr.coarse_fp64_levels;
         P->kahan = pr.kahan ? 1 : 0;
+        P->tight = pr.tight ? 1 : 0;
         P->dtype = dtype;
         P->al.stream = s;
         if (fmm_plan_arena_.base) {

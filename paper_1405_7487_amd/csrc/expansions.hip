@@ -501,7 +501,7 @@ struct OpCache {
     double *m2m_d = nullptr, *l2l_d = nullptr;
 };
 std::mutex g_ops_mu;
-std::map<std::tuple<int, int, uint64_t, int>, OpCache> g_ops;
+std::map<std::tuple<int, int, uint64_t, int, int>, OpCache> g_ops;
 }  // namespace
 
 void make_operators(fmm_plan *P, hipStream_t s)
@@ -513,13 +513,13 @@ void make_operators(fmm_plan *P, hipStream_t s)
     uint64_t bits;
     std::memcpy(&bits, &P->t4, sizeof(bits));
     std::unique_lock<std::mutex> lk(g_ops_mu, std::defer_lock);
-    const auto key = std::make_tuple(dev, P->p, bits, f64 ? 1 : 0);
+    const auto key = std::make_tuple(dev, P->p, bits, f64 ? 1 : 0, P->tight);  // the stencil depends on tight
     // a plan that may not allocate builds its own tables in its own memory
     auto dmalloc = [&](void **ptr, size_t bytes) {
         if (P->noalloc) *ptr = plan_alloc(P, bytes);
         else FMM_HIP(hipMalloc(ptr, bytes));
     };
-    std::map<std::tuple<int, int, uint64_t, int>, OpCache> own;
+    std::map<std::tuple<int, int, uint64_t, int, int>, OpCache> own;
     auto it = own.end();
     if (!P->noalloc) {
         lk.lock();

@@ -17,6 +17,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -109,16 +110,17 @@ __host__ __device__ constexpr int m2l_wv(int RT, bool f64) { return 4; }
 
 // ---------------------------------------------------------------- memory
 // Device memory of a plan: the caller's callbacks, the library's caching pool,
-// or (for the entry point that allocates nothing) bump allocation inside a
-// fixed device range, where freeing the most recent blocks gives their space
-// back and running past the range is FMM_ERR_NOMEM.
+// or (for the entry point that allocates nothing) blocks carved from a fixed
+// device range: first fit over the free ranges in address order, freed blocks
+// merged with their free neighbours; no fitting range is FMM_ERR_NOMEM.
 struct Allocator {
     fmm_allocator user{};
     bool has_user = false;
     hipStream_t stream = nullptr;
     char *arena = nullptr;
-    size_t arena_cap = 0, arena_top = 0, arena_peak = 0;
-    std::vector<std::pair<size_t, size_t>> arena_blocks;  // (offset, end), end 0 once freed
+    size_t arena_cap = 0, arena_peak = 0;
+    std::map<size_t, size_t> arena_free;            // offset -> bytes
+    std::map<size_t, size_t> arena_used;            // offset -> bytes
     void *alloc(size_t bytes);
     void free(void *p);
 };
@@ -152,6 +154,7 @@ struct fmm_plan {
     int p = 8, P2 = 64, P2pad = 64;
     double theta = 0.4, t4 = 0.64;
     int ncrit = 64, precision = FMM_PREC_MIXED, cfl = 3, kahan = 1;
+    int tight = 0;                   // acceptance also by the cells' own radii (c_rad)
     fmm_dtype dtype = FMM_F64;
     int timing = 0;
     fmm::Allocator al;
@@ -174,6 +177,7 @@ struct fmm_plan {
     uint64_t *c_key = nullptr;
     int32_t *c_ix = nullptr;       // [3*ncell] lattice coords at own level
     double *c_ctr = nullptr;       // [3*ncell]
+    int64_t *c_rad = nullptr;      // [ncell] radius tight to the bodies, units S 2^-22 (tight only)
     int32_t *leaves = nullptr;     // [nleaf] leaf cell indices (ascending)
     void *ubody = nullptr;         // [n] float4 or double4 (u, q)
     void *ulo = nullptr;           // [n] float4: float32 rounding residuals of ubody (mixed path)

@@ -48,6 +48,7 @@ __device__ __forceinline__ bool mac_dev(int la, int ax, int ay, int az, int lb, 
 
 struct TreeView {
     const int32_t *lvl, *nch, *cbeg, *ix;
+    const int64_t *rad;       // radii tight to the bodies (tight criterion) or null
     const uint64_t *key;
     const int32_t *tile_pos;  // cell -> tile*64 + lane (or -1)
     const int32_t *kidx;      // [8][(2R+1)^3]
@@ -61,6 +62,7 @@ struct TreeView {
 // level and child count.
 struct CellG {
     int l, x, y, z, n;
+    int64_t r;  // tight radius (units S 2^-22), or -1 without the tight criterion
 };
 
 __device__ __forceinline__ CellG load_cell(const TreeView &T, int c)
@@ -71,7 +73,22 @@ __device__ __forceinline__ CellG load_cell(const TreeView &T, int c)
     g.y = T.ix[3 * c + 1];
     g.z = T.ix[3 * c + 2];
     g.n = T.nch[c];
+    g.r = T.rad ? T.rad[c] : -1;
     return g;
+}
+
+// The criterion with the cells' own radii about their lattice centers, in
+// units u = S 2^-22 (centers at (2 i + 1) 2^(21 - l) u):
+// 4 (r_A + r_B)^2 < (4 theta^2) D^2, all integers below 2^53.
+__device__ __forceinline__ bool mac_tight(const CellG &A, const CellG &B, double t4)
+{
+#pragma clang fp contract(off)
+    const int64_t dx = ((2ll * A.x + 1) << (kLevels - A.l)) - ((2ll * B.x + 1) << (kLevels - B.l));
+    const int64_t dy = ((2ll * A.y + 1) << (kLevels - A.l)) - ((2ll * B.y + 1) << (kLevels - B.l));
+    const int64_t dz = ((2ll * A.z + 1) << (kLevels - A.l)) - ((2ll * B.z + 1) << (kLevels - B.l));
+    const int64_t d2 = dx * dx + dy * dy + dz * dz;
+    const int64_t rs = A.r + B.r;
+    return (double)(4 * rs * rs) < t4 * (double)d2;
 }
 
 // Classification of one child pair: 0 = same-level M2L, 1 = cross-level M2L,
@@ -88,6 +105,7 @@ __device__ __forceinline__ int classify(const CellG &A, const CellG &B, double t
     } else {
         acc = mac_dev(A.l, A.x, A.y, A.z, B.l, B.x, B.y, B.z, t4);
     }
+    if (!acc && A.r >= 0) acc = mac_tight(A, B, t4);
     if (acc) return A.l == B.l ? 0 : 1;
     if (A.n == 0 && B.n == 0) return 2;
     return 3;
@@ -226,6 +244,45 @@ __global__ void k_list_totals(const int64_t *offs, int64_t nf, int64_t *tot)
         tot[1] = offs[2 * nf] - offs[nf];
         tot[2] = all - offs[2 * nf];
     }
+}
+
+// Squared radius of every cell tight to its bodies: a body's lattice cell
+// (side 2 in units u = S 2^-22) has its farthest corner from a cell's
+// center (2 i + 1) 2^(21 - l) at sum_d max(|2 v_d - C_d|, |2 v_d + 2 - C_d|)^2;
+// each body raises the maximum of its leaf and of every ancestor.
+__global__ __launch_bounds__(256) void k_tight_r2(const uint64_t *keys, const int32_t *leaf_of, const int32_t *par,
+                                                  const int32_t *lvl, const int32_t *ix, int64_t n,
+                                                  unsigned long long *r2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    int64_t v[3] = {0, 0, 0};
+    for (int b = 0; b < kLevels; ++b)
+        for (int d = 0; d < 3; ++d) v[d] |= (int64_t)((k >> (3 * b + 2 - d)) & 1ull) << b;
+    for (int c = leaf_of[i]; c >= 0; c = par[c]) {
+        const int l = lvl[c];
+        int64_t s = 0;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t C = (2ll * ix[3 * c + d] + 1) << (kLevels - l);
+            const int64_t lo = 2 * v[d] - C, hi = 2 * v[d] + 2 - C;
+            const int64_t m = max(lo < 0 ? -lo : lo, hi < 0 ? -hi : hi);
+            s += m * m;
+        }
+        atomicMax(&r2[c], (unsigned long long)s);
+    }
+}
+
+// r = the smallest integer with r^2 >= r2 (exact; the float64 root is only a start)
+__global__ __launch_bounds__(256) void k_tight_rad(const unsigned long long *r2, int64_t nc, int64_t *rad)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int64_t v = (int64_t)r2[c];
+    int64_t r = (int64_t)sqrt((double)v);
+    while (r * r < v) ++r;
+    while (r > 0 && (r - 1) * (r - 1) >= v) --r;
+    rad[c] = r;
 }
 
 // Tile order keys: level and octant class (the tiles; bits 16 and up), then,
@@ -382,10 +439,13 @@ struct StencilCache {
     int32_t *d_op = nullptr, *d_kidx = nullptr;
 };
 std::mutex g_stencil_mu;
-std::map<std::pair<int, uint64_t>, StencilCache> g_stencils;
+std::map<std::tuple<int, uint64_t, int>, StencilCache> g_stencils;
 
 // Host part: the stencils, and the device tables' contents in op and kidx.
-StencilCache make_stencils(double t4, std::vector<int32_t> &op, std::vector<int32_t> &kidx)
+// An offset t is in S_c when the parents' offset fails the cube criterion
+// (else the pair is never reached) and, without the tight criterion, t itself
+// passes it; with the tight criterion any t != 0 can pass.
+StencilCache make_stencils(double t4, int tight, std::vector<int32_t> &op, std::vector<int32_t> &kidx)
 {
     StencilCache C;
     // parent offsets that fail the criterion satisfy |T|^2 <= 12 / t4
@@ -398,7 +458,8 @@ StencilCache make_stencils(double t4, std::vector<int32_t> &op, std::vector<int3
         for (int tx = -R; tx <= R; ++tx)
             for (int ty = -R; ty <= R; ++ty)
                 for (int tz = -R; tz <= R; ++tz) {
-                    if (!mac_same_level((int64_t)tx * tx + (int64_t)ty * ty + (int64_t)tz * tz, t4)) continue;
+                    const int64_t t2 = (int64_t)tx * tx + (int64_t)ty * ty + (int64_t)tz * tz;
+                    if (tight ? t2 == 0 : !mac_same_level(t2, t4)) continue;
                     const int Tx = ceil_div2(tx - cx), Ty = ceil_div2(ty - cy), Tz = ceil_div2(tz - cz);
                     if (mac_same_level((int64_t)Tx * Tx + (int64_t)Ty * Ty + (int64_t)Tz * Tz, t4)) continue;
                     S[c].push_back({tx, ty, tz});
@@ -435,10 +496,10 @@ StencilCache make_stencils(double t4, std::vector<int32_t> &op, std::vector<int3
 }
 
 // Stencils with their device tables, cached per (device, theta).
-StencilCache make_stencils_cached(double t4)
+StencilCache make_stencils_cached(double t4, int tight)
 {
     std::vector<int32_t> op, kidx;
-    StencilCache C = make_stencils(t4, op, kidx);
+    StencilCache C = make_stencils(t4, tight, op, kidx);
     FMM_HIP(hipMalloc(&C.d_op, sizeof(int32_t) * op.size()));
     FMM_HIP(hipMalloc(&C.d_kidx, sizeof(int32_t) * kidx.size()));
     FMM_HIP(hipMemcpy(C.d_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice));
@@ -459,7 +520,7 @@ static void build_stencils(fmm_plan *P, hipStream_t s)
     if (P->noalloc) {
         // a plan that may not allocate keeps its own copy of the tables
         std::vector<int32_t> op, kidx;
-        own = make_stencils(P->t4, op, kidx);
+        own = make_stencils(P->t4, P->tight, op, kidx);
         own.d_op = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * op.size()));
         own.d_kidx = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * kidx.size()));
         FMM_HIP(hipMemcpyAsync(own.d_op, op.data(), sizeof(int32_t) * op.size(), hipMemcpyHostToDevice, s));
@@ -468,9 +529,9 @@ static void build_stencils(fmm_plan *P, hipStream_t s)
         Cp = &own;
     } else {
         lk.lock();
-        auto key = std::make_pair(dev, bits);
+        auto key = std::make_tuple(dev, bits, P->tight);
         auto it = g_stencils.find(key);
-        if (it == g_stencils.end()) it = g_stencils.emplace(key, make_stencils_cached(P->t4)).first;
+        if (it == g_stencils.end()) it = g_stencils.emplace(key, make_stencils_cached(P->t4, P->tight)).first;
         Cp = &it->second;
     }
     const StencilCache &C = *Cp;
@@ -583,6 +644,16 @@ void traverse(fmm_plan *P, hipStream_t s)
     Allocator &al = P->al;
     const int64_t nc = P->ncell;
     build_stencils(P, s);
+    if (P->tight) {
+        unsigned long long *r2 = static_cast<unsigned long long *>(al.alloc(sizeof(unsigned long long) * nc));
+        FMM_HIP(hipMemsetAsync(r2, 0, sizeof(unsigned long long) * nc, s));
+        k_tight_r2<<<grid1(P->n, 256), 256, 0, s>>>(P->keys, P->leaf_of, P->c_par, P->c_lvl, P->c_ix, P->n, r2);
+        FMM_HIP(hipGetLastError());
+        P->c_rad = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * nc));
+        k_tight_rad<<<grid1(nc, 256), 256, 0, s>>>(r2, nc, P->c_rad);
+        FMM_HIP(hipGetLastError());
+        al.free(r2);
+    }
 
     // Octant-class tiles per level (levels >= 1).
     const int G = (kLevels + 1) * 8;
@@ -667,6 +738,7 @@ void traverse(fmm_plan *P, hipStream_t s)
     T.nch = P->c_nch;
     T.cbeg = P->c_cbeg;
     T.ix = P->c_ix;
+    T.rad = P->tight ? P->c_rad : nullptr;
     T.key = P->c_key;
     T.tile_pos = tile_pos;
     T.kidx = P->st_kidx;
