@@ -351,17 +351,22 @@ __device__ void irregular_cols(double tx, double ty, double tz, int nI, cdd *H)
 
 constexpr int kOutSlots = (kMaxP * (kMaxP + 1) / 2 + 63) / 64;
 
-// Remote M2L: one wave per target cell A of the receiver with pairs from one
-// sender, the sources' multipoles (scaled by h_B^-n) translated to A's local
-// expansion (scaled by h_A^{n+1}) in float64:
-//   L_j^s += (-1)^j sum_{n,m} rho^n M_n^m I_{n+j}^{m+s}(tau),
-// tau = (c_A - c_B) / h_A, rho = h_B / h_A; added to A's coefficients.
+// Remote M2L: one wave per work item, a run of at most kRChunk pairs of one
+// target cell A of the receiver with sources of one sender; the sources'
+// multipoles (scaled by h_B^-n) translated to A's local expansion (scaled by
+// h_A^{n+1}) in float64,
+//   L_j^s = (-1)^j sum_{n,m} rho^n M_n^m I_{n+j}^{m+s}(tau),
+// tau = (c_A - c_B) / h_A, rho = h_B / h_A, into the item's row of part.
+constexpr int kRChunk = 16;
+
 template <class TM>
-__global__ __launch_bounds__(64) void k_m2l_remote(TreeRef A, TreeRef B, const int32_t *tgts, const int64_t *off,
-                                                   const int32_t *src, int p, int P2pad, const TM *MB, TM *LA)
+__global__ __launch_bounds__(64) void k_m2l_remote(TreeRef A, TreeRef B, const int32_t *it_tgt, const int64_t *it_k0,
+                                                   const int64_t *it_k1, const int32_t *src, int p, int P2pad,
+                                                   const TM *MB, double *part)
 {
     const int lane = threadIdx.x;
-    const int c = tgts[blockIdx.x];
+    const int64_t item = blockIdx.x;
+    const int c = it_tgt[item];
     __shared__ cdd H[(2 * kLetMaxP) * (2 * kLetMaxP + 1) / 2];
     __shared__ cdd Ms[kLetMaxP * (kLetMaxP + 1) / 2];
     const int nI = 2 * p - 1, P2 = p * p, NO = p * (p + 1) / 2;
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(64) void k_m2l_remote(TreeRef A, TreeRef B, const i
         os[q] = t - j * (j + 1) / 2;
     }
     double are[kOutSlots] = {}, aim[kOutSlots] = {};
-    for (int64_t k = off[c]; k < off[c + 1]; ++k) {
+    for (int64_t k = it_k0[item]; k < it_k1[item]; ++k) {
         const int b = src[k];
         const double tx = (A.ctr[3 * c] - B.ctr[3 * b]) / hA, ty = (A.ctr[3 * c + 1] - B.ctr[3 * b + 1]) / hA,
                      tz = (A.ctr[3 * c + 2] - B.ctr[3 * b + 2]) / hA;
@@ -417,131 +422,211 @@ __global__ __launch_bounds__(64) void k_m2l_remote(TreeRef A, TreeRef B, const i
         }
         __syncthreads();
     }
-    TM *dst = LA + (int64_t)c * P2pad;
+    double *dst = part + item * P2pad;
     for (int q = 0; q < kOutSlots; ++q) {
         const int j = oj[q], sO = os[q];
         if (j < 0) continue;
         const double sg = (j & 1) ? -1.0 : 1.0;
-        if (sO == 0) dst[j * j] = (TM)((double)dst[j * j] + sg * are[q]);
+        if (sO == 0) dst[j * j] = sg * are[q];
         else {
             const int r = j * j + 2 * sO - 1;
-            dst[r] = (TM)((double)dst[r] + sg * are[q]);
-            dst[r + 1] = (TM)((double)dst[r + 1] + sg * aim[q]);
+            dst[r] = sg * are[q];
+            dst[r + 1] = sg * aim[q];
         }
     }
 }
 
-// Remote P2P and M2P for one target leaf A per wave, lanes over A's bodies
-// (absolute float64 positions xa, in A's sorted order), added to its sums:
-//   P2P: the bodies of the sent leaves, direct sum skipping r = 0 pairs;
+// L[c] += the sum of the cell's item rows, in item order (one thread per
+// (target, coefficient)).
+template <class TM>
+__global__ __launch_bounds__(256) void k_m2l_remote_reduce(const int32_t *tg, const int64_t *tg_i, int64_t ntg,
+                                                           const double *part, int P2, int P2pad, TM *LA)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = t / P2;
+    const int r = (int)(t % P2);
+    if (k >= ntg) return;
+    double acc = 0.0;
+    for (int64_t it = tg_i[k]; it < tg_i[k + 1]; ++it) acc += part[it * P2pad + r];
+    TM *dst = LA + (int64_t)tg[k] * P2pad + r;
+    *dst = (TM)((double)*dst + acc);
+}
+
+// Remote P2P and M2P: one wave per work item, a run of list entries of one
+// target leaf A; G lanes share a body of A (G a power of two, about 64 / |A|)
+// and split the item's sources, a fixed-order tree of shuffles sums them, and
+// the item's sums per body go to its rows of part (4 doubles per body).
+//   P2P: the bodies of the sent leaves, direct sum skipping r = 0 pairs
+//        (absolute float64 positions xa, xb in sorted order; FAST takes the
+//        reciprocal square root at float32 precision, for the mixed path);
 //   M2P: the multipole series of each multipole-only cell at the body, with
 //        t = (x - c_B) / h_B:  phi += Re L_0^0 / h_B,
 //        E += (Re L_1^1, Im L_1^1, -Re L_1^0) / h_B^2,
 //        L_j^s = (-1)^j sum_{n<p, m} M_n^m I_{n+j}^{m+s}(t)
 //   (the local expansion of the series about the body itself, whose value
 //   and gradient there are the series' own).
-template <class TM, class TS>
-__global__ __launch_bounds__(64) void k_p2p_m2p_remote(TreeRef A, TreeRef B, const int32_t *tgts,
-                                                       const int64_t *poff, const int32_t *psrc,
-                                                       const int64_t *moff, const int32_t *msrc,
-                                                       const double4 *xa, const double4 *xb, int p, int P2pad,
-                                                       const TM *MB, TS *phi_s, TS *E_s)
+__device__ __forceinline__ int lanes_per_body(int cnt)
+{
+    int G = 1;
+    while (G < 16 && 2 * G * cnt <= 64) G *= 2;
+    return G;
+}
+
+template <bool FAST>
+__device__ __forceinline__ double rsqrt_d(double r2)
+{
+    if (FAST) return (double)__builtin_amdgcn_rsqf((float)r2);
+    return 1.0 / sqrt(r2);
+}
+
+// the M2P series of one multipole row (real layout, scaled) at t, accumulated
+template <class TM>
+__device__ __forceinline__ void m2p_series(const TM *Mr, int p, double tx, double ty, double tz, double &l00,
+                                           double &l10, double &l11r, double &l11i)
+{
+    const double r2 = tx * tx + ty * ty + tz * tz, ir2 = 1.0 / r2;
+    cdd mm = {1.0 / sqrt(r2), 0.0};  // I_m^m
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const double f = -(2.0 * m - 1.0) * ir2;
+            mm = cdd{(mm.re * tx - mm.im * ty) * f, (mm.re * ty + mm.im * tx) * f};
+        }
+        cdd i1 = mm, i2 = {0.0, 0.0};
+        for (int n = m; n <= p; ++n) {
+            if (n > m) {
+                cdd cur;
+                if (n == m + 1) cur = cdd{i1.re * (2.0 * m + 1.0) * tz * ir2, i1.im * (2.0 * m + 1.0) * tz * ir2};
+                else {
+                    const double a = (2.0 * n - 1.0) * tz, bb = -(double)((n + m - 1) * (n - m - 1));
+                    cur = cdd{(a * i1.re + bb * i2.re) * ir2, (a * i1.im + bb * i2.im) * ir2};
+                }
+                i2 = i1;
+                i1 = cur;
+            }
+            const cdd I = i1;  // I_n^m(t)
+            const double w = m == 0 ? 1.0 : 2.0;
+            if (n < p) {  // phi: M_n^m I_n^m, both signs of m
+                const double Mre = (double)Mr[m == 0 ? n * n : n * n + 2 * m - 1];
+                const double Mim = m == 0 ? 0.0 : (double)Mr[n * n + 2 * m];
+                l00 += w * (Mre * I.re - Mim * I.im);
+            }
+            if (n >= 1 && n - 1 >= m) {  // L_1^0 = -sum M_{n-1}^m I_n^m, both signs of m
+                const int d = n - 1;
+                const double Mre = (double)Mr[m == 0 ? d * d : d * d + 2 * m - 1];
+                const double Mim = m == 0 ? 0.0 : (double)Mr[d * d + 2 * m];
+                l10 -= w * (Mre * I.re - Mim * I.im);
+            }
+            // L_1^1 = -sum_{m'>=0} M_{n-1}^{m'} I_n^{m'+1} + sum_{k>=1} conj(M_{n-1}^k I_n^{k-1})
+            if (n >= 1 && m >= 1) {  // m' = m - 1
+                const int d = n - 1, mp = m - 1;
+                const double Mre = (double)Mr[mp == 0 ? d * d : d * d + 2 * mp - 1];
+                const double Mim = mp == 0 ? 0.0 : (double)Mr[d * d + 2 * mp];
+                l11r -= Mre * I.re - Mim * I.im;
+                l11i -= Mre * I.im + Mim * I.re;
+            }
+            if (n >= 1 && m + 1 <= n - 1) {  // k = m + 1
+                const int d = n - 1, kk = m + 1;
+                const double Mre = (double)Mr[d * d + 2 * kk - 1], Mim = (double)Mr[d * d + 2 * kk];
+                l11r += Mre * I.re - Mim * I.im;
+                l11i -= Mre * I.im + Mim * I.re;
+            }
+        }
+    }
+}
+
+template <class TM, bool FAST>
+__global__ __launch_bounds__(64) void k_leaf_remote(TreeRef A, TreeRef B, const int32_t *it_leaf, const int64_t *it_k0,
+                                                    const int64_t *it_k1, const int64_t *it_base, int kind,
+                                                    const int32_t *src, const double4 *xa, const double4 *xb, int p,
+                                                    int P2pad, const TM *MB, double4 *part)
 {
     const int lane = threadIdx.x;
-    const int c = tgts[blockIdx.x];
-    __shared__ double Mr[kLetMaxP * kLetMaxP];
-    const int32_t b0 = A.beg[c], b1 = A.end[c];
-    for (int32_t base = b0; base < b1; base += 64) {
-        const int32_t i = base + lane;
-        const bool act = i < b1;
-        const double4 X = xa[act ? i : b0];
+    const int64_t item = blockIdx.x;
+    const int c = it_leaf[item];
+    const int32_t b0 = A.beg[c], cnt = A.end[c] - b0;
+    const int G = lanes_per_body(cnt);
+    const int sub = lane % G, per = 64 / G;
+    const int64_t k0 = it_k0[item], k1 = it_k1[item];
+    for (int32_t base = 0; base < cnt; base += per) {
+        const int t = base + lane / G;
+        const bool act = t < cnt;
+        const double4 X = xa[b0 + (act ? t : 0)];
         double ph = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        for (int64_t k = poff[c]; k < poff[c + 1]; ++k) {
-            const int b = psrc[k];
-            for (int32_t j = B.beg[b]; j < B.end[b]; ++j) {
-                const double4 Y = xb[j];
-                const double dx = X.x - Y.x, dy = X.y - Y.y, dz = X.z - Y.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 == 0.0) continue;
-                const double r = sqrt(r2), qr = Y.w / r, qr3 = qr / r2;
-                ph += qr;
-                ex += qr3 * dx;
-                ey += qr3 * dy;
-                ez += qr3 * dz;
+        if (kind == 0) {
+            // P2P: the item's source bodies, dealt to the G lanes in turn
+            int rot = 0;
+            for (int64_t k = k0; k < k1; ++k) {
+                const int b = src[k];
+                const int32_t j0 = B.beg[b], nb = B.end[b] - j0;
+                for (int32_t jj = (sub - rot + G) % G; jj < nb; jj += G) {
+                    const double4 Y = xb[j0 + jj];
+                    const double dx = X.x - Y.x, dy = X.y - Y.y, dz = X.z - Y.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 == 0.0) continue;
+                    const double ri = rsqrt_d<FAST>(r2);
+                    const double qr = Y.w * ri, qr3 = qr * ri * ri;
+                    ph += qr;
+                    ex += qr3 * dx;
+                    ey += qr3 * dy;
+                    ez += qr3 * dz;
+                }
+                rot = (rot + nb) % G;
+            }
+        } else {
+            // M2P: the item's cells dealt to the G lanes
+            for (int64_t k = k0 + sub; k < k1; k += G) {
+                const int b = src[k];
+                const double ih = 1.0 / side(B, b);
+                const double tx = (X.x - B.ctr[3 * b]) * ih, ty = (X.y - B.ctr[3 * b + 1]) * ih,
+                             tz = (X.z - B.ctr[3 * b + 2]) * ih;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                m2p_series<TM>(MB + (int64_t)b * P2pad, p, tx, ty, tz, a0, a1, a2, a3);
+                ph += a0 * ih;
+                ex += a2 * ih * ih;
+                ey += a3 * ih * ih;
+                ez += -a1 * ih * ih;
             }
         }
-        for (int64_t k = moff[c]; k < moff[c + 1]; ++k) {
-            const int b = msrc[k];
-            const TM *mb = MB + (int64_t)b * P2pad;
-            __syncthreads();
-            for (int r = lane; r < p * p; r += 64) Mr[r] = (double)mb[r];
-            __syncthreads();
-            const double hb = side(B, b), ih = 1.0 / hb;
-            const double tx = (X.x - B.ctr[3 * b]) * ih, ty = (X.y - B.ctr[3 * b + 1]) * ih,
-                         tz = (X.z - B.ctr[3 * b + 2]) * ih;
-            const double r2 = tx * tx + ty * ty + tz * tz, ir2 = 1.0 / r2;
-            // column m of the irregular harmonics, m = 0..p, degrees m..p
-            double l00 = 0.0, l10 = 0.0, l11r = 0.0, l11i = 0.0;
-            cdd mm = {1.0 / sqrt(r2), 0.0};  // I_m^m
-            for (int m = 0; m <= p; ++m) {
-                if (m > 0) {
-                    const double f = -(2.0 * m - 1.0) * ir2;
-                    mm = cdd{(mm.re * tx - mm.im * ty) * f, (mm.re * ty + mm.im * tx) * f};
-                }
-                cdd i1 = mm, i2 = {0.0, 0.0};
-                for (int n = m; n <= p; ++n) {
-                    // I_n^m = i1 (after the step below)
-                    if (n > m) {
-                        cdd cur;
-                        if (n == m + 1) cur = cdd{i1.re * (2.0 * m + 1.0) * tz * ir2, i1.im * (2.0 * m + 1.0) * tz * ir2};
-                        else {
-                            const double a = (2.0 * n - 1.0) * tz, bb = -(double)((n + m - 1) * (n - m - 1));
-                            cur = cdd{(a * i1.re + bb * i2.re) * ir2, (a * i1.im + bb * i2.im) * ir2};
-                        }
-                        i2 = i1;
-                        i1 = cur;
-                    }
-                    const cdd I = i1;  // I_n^m(t)
-                    const double w = m == 0 ? 1.0 : 2.0;
-                    // phi: M_n^m I_n^m (n < p), both signs of m
-                    if (n < p) {
-                        const double Mre = Mr[m == 0 ? n * n : n * n + 2 * m - 1], Mim = m == 0 ? 0.0 : Mr[n * n + 2 * m];
-                        l00 += w * (Mre * I.re - Mim * I.im);
-                    }
-                    // L_1^0 = -sum M_{n-1}^m I_n^m (n - 1 < p), both signs of m
-                    if (n >= 1 && n - 1 >= m) {
-                        const int d = n - 1;
-                        const double Mre = Mr[m == 0 ? d * d : d * d + 2 * m - 1], Mim = m == 0 ? 0.0 : Mr[d * d + 2 * m];
-                        l10 -= w * (Mre * I.re - Mim * I.im);
-                    }
-                    // L_1^1 = -sum_{m'>=0} M_{n-1}^{m'} I_n^{m'+1} + sum_{k>=1} conj(M_{n-1}^k I_n^{k-1})
-                    if (n >= 1 && m >= 1 && n - 1 >= m - 1) {  // m' = m - 1
-                        const int d = n - 1, mp = m - 1;
-                        const double Mre = Mr[mp == 0 ? d * d : d * d + 2 * mp - 1], Mim = mp == 0 ? 0.0 : Mr[d * d + 2 * mp];
-                        l11r -= Mre * I.re - Mim * I.im;
-                        l11i -= Mre * I.im + Mim * I.re;
-                    }
-                    if (n >= 1 && m + 1 <= n - 1) {  // k = m + 1
-                        const int d = n - 1, kk = m + 1;
-                        const double Mre = Mr[d * d + 2 * kk - 1], Mim = Mr[d * d + 2 * kk];
-                        const double pr = Mre * I.re - Mim * I.im, pi = Mre * I.im + Mim * I.re;
-                        l11r += pr;
-                        l11i -= pi;
-                    }
-                }
+        // the G lanes of a body, in a fixed order
+        for (int w = 1; w < G; w <<= 1) {
+            const double rp = __shfl_down(ph, w, 64), rx = __shfl_down(ex, w, 64);
+            const double ry = __shfl_down(ey, w, 64), rz = __shfl_down(ez, w, 64);
+            if (sub % (2 * w) == 0 && sub + w < G) {
+                ph += rp;
+                ex += rx;
+                ey += ry;
+                ez += rz;
             }
-            ph += l00 * ih;
-            const double ih2 = ih * ih;
-            ex += l11r * ih2;
-            ey += l11i * ih2;
-            ez += -l10 * ih2;
         }
-        if (act) {
-            phi_s[i] = (TS)((double)phi_s[i] + ph);
-            E_s[3 * (int64_t)i] = (TS)((double)E_s[3 * (int64_t)i] + ex);
-            E_s[3 * (int64_t)i + 1] = (TS)((double)E_s[3 * (int64_t)i + 1] + ey);
-            E_s[3 * (int64_t)i + 2] = (TS)((double)E_s[3 * (int64_t)i + 2] + ez);
+        if (act && sub == 0) part[it_base[item] + t] = make_double4(ph, ex, ey, ez);
+    }
+}
+
+// Each body of a leaf: its items' sums in item order (P2P items, then M2P
+// items), added to the body's potential and field.
+template <class TS>
+__global__ __launch_bounds__(256) void k_leaf_reduce(TreeRef A, const int32_t *lf, const int64_t *lf_i,
+                                                     const int64_t *it_base, int64_t nlf, const double4 *part,
+                                                     TS *phi_s, TS *E_s)
+{
+    const int64_t k = blockIdx.x;
+    if (k >= nlf) return;
+    const int c = lf[k];
+    const int32_t b0 = A.beg[c], cnt = A.end[c] - b0;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+        double ph = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int64_t it = lf_i[k]; it < lf_i[k + 1]; ++it) {
+            const double4 v = part[it_base[it] + t];
+            ph += v.x;
+            ex += v.y;
+            ey += v.z;
+            ez += v.w;
         }
+        const int64_t i = b0 + t;
+        phi_s[i] = (TS)((double)phi_s[i] + ph);
+        E_s[3 * i] = (TS)((double)E_s[3 * i] + ex);
+        E_s[3 * i + 1] = (TS)((double)E_s[3 * i + 1] + ey);
+        E_s[3 * i + 2] = (TS)((double)E_s[3 * i + 2] + ez);
     }
 }
 
@@ -620,8 +705,13 @@ struct RemoteLists {
     uint64_t dig[3] = {0, 0, 0};
     int64_t *off[3] = {nullptr, nullptr, nullptr};
     int32_t *src[3] = {nullptr, nullptr, nullptr};
-    int32_t *tg_m2l = nullptr, *tg_leaf = nullptr;  // targets with M2L pairs; leaves with P2P or M2P pairs
-    int64_t ntg_m2l = 0, ntg_leaf = 0;
+    // work items: M2L runs of one target (and each target's first item);
+    // P2P and M2P runs of one leaf (rows of their sums; each leaf's items)
+    int64_t nmi = 0, nmt = 0, npi = 0, nqi = 0, nlf = 0, nrow = 0;
+    int32_t *mi_tgt = nullptr, *mt_tgt = nullptr, *pi_leaf = nullptr, *qi_leaf = nullptr, *lf = nullptr;
+    int64_t *mi_k0 = nullptr, *mi_k1 = nullptr, *mt_i = nullptr, *pi_k0 = nullptr, *pi_k1 = nullptr;
+    int64_t *qi_k0 = nullptr, *qi_k1 = nullptr, *it_base = nullptr, *lf_i = nullptr;
+    int64_t *pb = nullptr, *qb = nullptr;  // row base of each P2P / M2P item
     int64_t let[5] = {0, 0, 0, 0, 0};         // cells, multipole-only, body leaves, bodies, digest
 };
 
@@ -634,22 +724,13 @@ int bits_of(int64_t v)
     return b;
 }
 
-// Targets of a CSR with at least one entry in any of the given lists.
-std::vector<int32_t> targets_with(const std::vector<const int64_t *> &offs, int64_t nc, hipStream_t s)
+// Host copy of a CSR offset array.
+std::vector<int64_t> host_offsets(const int64_t *d, int64_t nc, hipStream_t s)
 {
-    std::vector<int32_t> t;
-    std::vector<std::vector<int64_t>> h(offs.size());
-    for (size_t k = 0; k < offs.size(); ++k) {
-        h[k].resize(nc + 1);
-        FMM_HIP(hipMemcpyAsync(h[k].data(), offs[k], sizeof(int64_t) * (nc + 1), hipMemcpyDeviceToHost, s));
-    }
+    std::vector<int64_t> h(nc + 1);
+    FMM_HIP(hipMemcpyAsync(h.data(), d, sizeof(int64_t) * (nc + 1), hipMemcpyDeviceToHost, s));
     FMM_HIP(hipStreamSynchronize(s));
-    for (int64_t c = 0; c < nc; ++c) {
-        bool any = false;
-        for (auto &v : h) any |= v[c + 1] > v[c];
-        if (any) t.push_back((int32_t)c);
-    }
-    return t;
+    return h;
 }
 
 }  // namespace
@@ -868,16 +949,99 @@ void let_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int 
                     FMM_HIP(hipStreamSynchronize(s));
                     L.dig[t] = d;
                 }
-                std::vector<int32_t> tm = targets_with({L.off[0]}, PA->ncell, s);
-                std::vector<int32_t> tl = targets_with({L.off[1], L.off[2]}, PA->ncell, s);
-                L.ntg_m2l = (int64_t)tm.size();
-                L.ntg_leaf = (int64_t)tl.size();
-                L.tg_m2l = static_cast<int32_t *>(hold(sizeof(int32_t) * std::max<size_t>(1, tm.size())));
-                L.tg_leaf = static_cast<int32_t *>(hold(sizeof(int32_t) * std::max<size_t>(1, tl.size())));
-                if (!tm.empty())
-                    FMM_HIP(hipMemcpyAsync(L.tg_m2l, tm.data(), sizeof(int32_t) * tm.size(), hipMemcpyHostToDevice, s));
-                if (!tl.empty())
-                    FMM_HIP(hipMemcpyAsync(L.tg_leaf, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, s));
+                // work items: runs of at most kRChunk M2L pairs of a target, of
+                // 16 P2P source leaves or 8 M2P cells of a leaf
+                const std::vector<int64_t> om = host_offsets(L.off[0], PA->ncell, s);
+                const std::vector<int64_t> op = host_offsets(L.off[1], PA->ncell, s);
+                const std::vector<int64_t> oq = host_offsets(L.off[2], PA->ncell, s);
+                std::vector<int32_t> h_mi_tgt, h_mt_tgt, h_pi_leaf, h_qi_leaf, h_lf;
+                std::vector<int64_t> h_mi_k0, h_mi_k1, h_mt_i, h_pi_k0, h_pi_k1, h_qi_k0, h_qi_k1, h_lf_i, h_base_p,
+                    h_base_q;
+                std::vector<int32_t> h_cnt(PA->ncell);
+                FMM_HIP(hipMemcpyAsync(h_cnt.data(), PA->c_end, sizeof(int32_t) * PA->ncell, hipMemcpyDeviceToHost, s));
+                std::vector<int32_t> h_beg(PA->ncell);
+                FMM_HIP(hipMemcpyAsync(h_beg.data(), PA->c_beg, sizeof(int32_t) * PA->ncell, hipMemcpyDeviceToHost, s));
+                FMM_HIP(hipStreamSynchronize(s));
+                int64_t rows = 0;
+                for (int64_t c = 0; c < PA->ncell; ++c) {
+                    if (om[c + 1] > om[c]) {
+                        h_mt_tgt.push_back((int32_t)c);
+                        h_mt_i.push_back((int64_t)h_mi_tgt.size());
+                        for (int64_t k = om[c]; k < om[c + 1]; k += kRChunk) {
+                            h_mi_tgt.push_back((int32_t)c);
+                            h_mi_k0.push_back(k);
+                            h_mi_k1.push_back(std::min<int64_t>(om[c + 1], k + kRChunk));
+                        }
+                    }
+                    if (op[c + 1] > op[c] || oq[c + 1] > oq[c]) {
+                        const int64_t nb = h_cnt[c] - h_beg[c];
+                        h_lf.push_back((int32_t)c);
+                        h_lf_i.push_back((int64_t)(h_base_p.size() + h_base_q.size()));
+                        for (int64_t k = op[c]; k < op[c + 1]; k += 16) {
+                            h_pi_leaf.push_back((int32_t)c);
+                            h_pi_k0.push_back(k);
+                            h_pi_k1.push_back(std::min<int64_t>(op[c + 1], k + 16));
+                            h_base_p.push_back(rows);
+                            rows += nb;
+                        }
+                        for (int64_t k = oq[c]; k < oq[c + 1]; k += 8) {
+                            h_qi_leaf.push_back((int32_t)c);
+                            h_qi_k0.push_back(k);
+                            h_qi_k1.push_back(std::min<int64_t>(oq[c + 1], k + 8));
+                            h_base_q.push_back(rows);
+                            rows += nb;
+                        }
+                    }
+                }
+                h_mt_i.push_back((int64_t)h_mi_tgt.size());
+                // the reduction walks a leaf's items as one range of bases:
+                // its P2P items' bases, then its M2P items' bases
+                std::vector<int64_t> h_base;
+                {
+                    size_t ip = 0, iq = 0;
+                    std::vector<int64_t> starts;
+                    for (size_t k = 0; k < h_lf.size(); ++k) {
+                        starts.push_back((int64_t)h_base.size());
+                        const int c = h_lf[k];
+                        while (ip < h_pi_leaf.size() && h_pi_leaf[ip] == c) h_base.push_back(h_base_p[ip++]);
+                        while (iq < h_qi_leaf.size() && h_qi_leaf[iq] == c) h_base.push_back(h_base_q[iq++]);
+                    }
+                    starts.push_back((int64_t)h_base.size());
+                    h_lf_i = starts;
+                }
+                L.nmi = (int64_t)h_mi_tgt.size();
+                L.nmt = (int64_t)h_mt_tgt.size();
+                L.npi = (int64_t)h_pi_leaf.size();
+                L.nqi = (int64_t)h_qi_leaf.size();
+                L.nlf = (int64_t)h_lf.size();
+                L.nrow = rows;
+                auto up32 = [&](const std::vector<int32_t> &v) {
+                    int32_t *d = static_cast<int32_t *>(hold(sizeof(int32_t) * std::max<size_t>(1, v.size())));
+                    if (!v.empty()) FMM_HIP(hipMemcpyAsync(d, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, s));
+                    return d;
+                };
+                auto up64 = [&](const std::vector<int64_t> &v) {
+                    int64_t *d = static_cast<int64_t *>(hold(sizeof(int64_t) * std::max<size_t>(1, v.size())));
+                    if (!v.empty()) FMM_HIP(hipMemcpyAsync(d, v.data(), sizeof(int64_t) * v.size(), hipMemcpyHostToDevice, s));
+                    return d;
+                };
+                L.mi_tgt = up32(h_mi_tgt);
+                L.mi_k0 = up64(h_mi_k0);
+                L.mi_k1 = up64(h_mi_k1);
+                L.mt_tgt = up32(h_mt_tgt);
+                L.mt_i = up64(h_mt_i);
+                L.pi_leaf = up32(h_pi_leaf);
+                L.pi_k0 = up64(h_pi_k0);
+                L.pi_k1 = up64(h_pi_k1);
+                L.qi_leaf = up32(h_qi_leaf);
+                L.qi_k0 = up64(h_qi_k0);
+                L.qi_k1 = up64(h_qi_k1);
+                L.lf = up32(h_lf);
+                L.lf_i = up64(h_lf_i);
+                std::vector<int64_t> h_bp(h_base_p), h_bq(h_base_q);
+                L.it_base = up64(h_base);
+                L.pb = up64(h_bp);
+                L.qb = up64(h_bq);
                 FMM_HIP(hipStreamSynchronize(s));
             }
         }
@@ -901,34 +1065,53 @@ void let_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int 
             eval_m2l(PA, s);
             for (int sdr = 0; sdr < R; ++sdr) {
                 const RemoteLists &L = RL[(int64_t)r * R + sdr];
-                if (sdr == r || !plans[sdr] || L.ntg_m2l == 0) continue;
+                if (sdr == r || !plans[sdr] || L.nmi == 0) continue;
                 fmm_plan *PB = plans[sdr];
-                if (f64)
-                    k_m2l_remote<double><<<(unsigned)L.ntg_m2l, 64, 0, s>>>(
-                        tree_ref(PA), tree_ref(PB), L.tg_m2l, L.off[0], L.src[0], PA->p, PA->P2pad,
-                        static_cast<const double *>(PB->Mc), static_cast<double *>(PA->Lc));
-                else
-                    k_m2l_remote<float><<<(unsigned)L.ntg_m2l, 64, 0, s>>>(
-                        tree_ref(PA), tree_ref(PB), L.tg_m2l, L.off[0], L.src[0], PA->p, PA->P2pad,
-                        static_cast<const float *>(PB->Mc), static_cast<float *>(PA->Lc));
+                double *part = static_cast<double *>(dalloc(al, sizeof(double) * L.nmi * PA->P2pad));
+                const int P2 = PA->p * PA->p;
+                if (f64) {
+                    k_m2l_remote<double><<<(unsigned)L.nmi, 64, 0, s>>>(tree_ref(PA), tree_ref(PB), L.mi_tgt, L.mi_k0,
+                                                                         L.mi_k1, L.src[0], PA->p, PA->P2pad,
+                                                                         static_cast<const double *>(PB->Mc), part);
+                    k_m2l_remote_reduce<double><<<grid1(L.nmt * P2, 256), 256, 0, s>>>(
+                        L.mt_tgt, L.mt_i, L.nmt, part, P2, PA->P2pad, static_cast<double *>(PA->Lc));
+                } else {
+                    k_m2l_remote<float><<<(unsigned)L.nmi, 64, 0, s>>>(tree_ref(PA), tree_ref(PB), L.mi_tgt, L.mi_k0,
+                                                                        L.mi_k1, L.src[0], PA->p, PA->P2pad,
+                                                                        static_cast<const float *>(PB->Mc), part);
+                    k_m2l_remote_reduce<float><<<grid1(L.nmt * P2, 256), 256, 0, s>>>(
+                        L.mt_tgt, L.mt_i, L.nmt, part, P2, PA->P2pad, static_cast<float *>(PA->Lc));
+                }
                 FMM_HIP(hipGetLastError());
+                al.free(part);
             }
             eval_down(PA, PA->ubody, PA->phi_s, PA->E_s, s);
             for (int sdr = 0; sdr < R; ++sdr) {
                 const RemoteLists &L = RL[(int64_t)r * R + sdr];
-                if (sdr == r || !plans[sdr] || L.ntg_leaf == 0) continue;
+                if (sdr == r || !plans[sdr] || L.nlf == 0) continue;
                 fmm_plan *PB = plans[sdr];
-                if (f64)
-                    k_p2p_m2p_remote<double, double><<<(unsigned)L.ntg_leaf, 64, 0, s>>>(
-                        tree_ref(PA), tree_ref(PB), L.tg_leaf, L.off[1], L.src[1], L.off[2], L.src[2], xs[r], xs[sdr],
-                        PA->p, PA->P2pad, static_cast<const double *>(PB->Mc), static_cast<double *>(PA->phi_s),
-                        static_cast<double *>(PA->E_s));
-                else
-                    k_p2p_m2p_remote<float, float><<<(unsigned)L.ntg_leaf, 64, 0, s>>>(
-                        tree_ref(PA), tree_ref(PB), L.tg_leaf, L.off[1], L.src[1], L.off[2], L.src[2], xs[r], xs[sdr],
-                        PA->p, PA->P2pad, static_cast<const float *>(PB->Mc), static_cast<float *>(PA->phi_s),
-                        static_cast<float *>(PA->E_s));
+                double4 *part = static_cast<double4 *>(dalloc(al, sizeof(double4) * L.nrow));
+#define LEAF_REMOTE(TM, FAST, NI, LEAF, K0, K1, BASE, KIND, SRC)                                          \
+    if (NI > 0)                                                                                        \
+        k_leaf_remote<TM, FAST><<<(unsigned)NI, 64, 0, s>>>(tree_ref(PA), tree_ref(PB), LEAF, K0, K1, BASE, \
+                                                           KIND, SRC, xs[r], xs[sdr], PA->p, PA->P2pad,  \
+                                                           static_cast<const TM *>(PB->Mc), part)
+                if (f64) {
+                    LEAF_REMOTE(double, false, L.npi, L.pi_leaf, L.pi_k0, L.pi_k1, L.pb, 0, L.src[1]);
+                    LEAF_REMOTE(double, false, L.nqi, L.qi_leaf, L.qi_k0, L.qi_k1, L.qb, 1, L.src[2]);
+                    k_leaf_reduce<double><<<(unsigned)L.nlf, 64, 0, s>>>(tree_ref(PA), L.lf, L.lf_i, L.it_base, L.nlf,
+                                                                         part, static_cast<double *>(PA->phi_s),
+                                                                         static_cast<double *>(PA->E_s));
+                } else {
+                    LEAF_REMOTE(float, true, L.npi, L.pi_leaf, L.pi_k0, L.pi_k1, L.pb, 0, L.src[1]);
+                    LEAF_REMOTE(float, true, L.nqi, L.qi_leaf, L.qi_k0, L.qi_k1, L.qb, 1, L.src[2]);
+                    k_leaf_reduce<float><<<(unsigned)L.nlf, 64, 0, s>>>(tree_ref(PA), L.lf, L.lf_i, L.it_base, L.nlf,
+                                                                        part, static_cast<float *>(PA->phi_s),
+                                                                        static_cast<float *>(PA->E_s));
+                }
+#undef LEAF_REMOTE
                 FMM_HIP(hipGetLastError());
+                al.free(part);
             }
             // results to the caller's order
             int32_t *mem = idx + rstart[r];

@@ -971,7 +971,9 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     int64_t allpairs = 0;
     for (int id = 0; id < nk; ++id) allpairs += key_cnt[id];
     const int64_t pbytes = (int64_t)P->P2pad * (int64_t)esz;
-    const int64_t bbytes = std::min<int64_t>(16ll << 30, std::max<int64_t>(2ll << 30, allpairs * pbytes / 4));
+    // (a plan that may not allocate keeps it at 16 MiB: more chunks, same sums)
+    const int64_t bbytes = P->noalloc ? (16ll << 20)
+                                      : std::min<int64_t>(16ll << 30, std::max<int64_t>(2ll << 30, allpairs * pbytes / 4));
     const int64_t budget = std::max<int64_t>((int64_t)TW, bbytes / pbytes);
     std::vector<int32_t> h_op, h_cnt, chunk_of(nk);
     std::vector<int64_t> h_first;

@@ -250,26 +250,46 @@ __global__ void k_list_totals(const int64_t *offs, int64_t nf, int64_t *tot)
 // (side 2 in units u = S 2^-22) has its farthest corner from a cell's
 // center (2 i + 1) 2^(21 - l) at sum_d max(|2 v_d - C_d|, |2 v_d + 2 - C_d|)^2;
 // each body raises the maximum of its leaf and of every ancestor.
+// Level by level from the deepest: the lanes of a wave hold consecutive
+// sorted bodies, so their ancestors at one level are non-decreasing across
+// the lanes; a segmented maximum over lanes with the same ancestor leaves one
+// atomic per (wave, cell), skipped when it cannot raise the value.
 __global__ __launch_bounds__(256) void k_tight_r2(const uint64_t *keys, const int32_t *leaf_of, const int32_t *par,
-                                                  const int32_t *lvl, const int32_t *ix, int64_t n,
+                                                  const int32_t *lvl, const int32_t *ix, int64_t n, int depth,
                                                   unsigned long long *r2)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t k = keys[i];
+    const int lane = threadIdx.x & 63;
+    const bool act = i < n;
     int64_t v[3] = {0, 0, 0};
-    for (int b = 0; b < kLevels; ++b)
-        for (int d = 0; d < 3; ++d) v[d] |= (int64_t)((k >> (3 * b + 2 - d)) & 1ull) << b;
-    for (int c = leaf_of[i]; c >= 0; c = par[c]) {
-        const int l = lvl[c];
-        int64_t s = 0;
-        for (int d = 0; d < 3; ++d) {
-            const int64_t C = (2ll * ix[3 * c + d] + 1) << (kLevels - l);
-            const int64_t lo = 2 * v[d] - C, hi = 2 * v[d] + 2 - C;
-            const int64_t m = max(lo < 0 ? -lo : lo, hi < 0 ? -hi : hi);
-            s += m * m;
+    int c = -1;
+    if (act) {
+        const uint64_t k = keys[i];
+        for (int b = 0; b < kLevels; ++b)
+            for (int d = 0; d < 3; ++d) v[d] |= (int64_t)((k >> (3 * b + 2 - d)) & 1ull) << b;
+        c = leaf_of[i];
+    }
+    for (int l = depth; l >= 0; --l) {
+        // this lane's cell at level l (its leaf may be coarser: then none yet)
+        const int a = (c >= 0 && lvl[c] == l) ? c : -1;
+        unsigned long long s = 0;
+        if (a >= 0) {
+            for (int d = 0; d < 3; ++d) {
+                const int64_t C = (2ll * ix[3 * a + d] + 1) << (kLevels - l);
+                const int64_t lo = 2 * v[d] - C, hi = 2 * v[d] + 2 - C;
+                const int64_t m = max(lo < 0 ? -lo : lo, hi < 0 ? -hi : hi);
+                s += (unsigned long long)(m * m);
+            }
         }
-        atomicMax(&r2[c], (unsigned long long)s);
+        // segmented maximum towards the first lane of each run of equal a
+        for (int w = 1; w < 64; w <<= 1) {
+            const unsigned long long so = __shfl_down(s, w, 64);
+            const int ao = __shfl_down(a, w, 64);
+            if (lane + w < 64 && ao == a && so > s) s = so;
+        }
+        const int ap = __shfl_up(a, 1, 64);
+        if (a >= 0 && (lane == 0 || ap != a) && s > r2[a]) atomicMax(&r2[a], s);
+        if (a >= 0) c = par[a];
     }
 }
 
@@ -647,7 +667,8 @@ void traverse(fmm_plan *P, hipStream_t s)
     if (P->tight) {
         unsigned long long *r2 = static_cast<unsigned long long *>(al.alloc(sizeof(unsigned long long) * nc));
         FMM_HIP(hipMemsetAsync(r2, 0, sizeof(unsigned long long) * nc, s));
-        k_tight_r2<<<grid1(P->n, 256), 256, 0, s>>>(P->keys, P->leaf_of, P->c_par, P->c_lvl, P->c_ix, P->n, r2);
+        k_tight_r2<<<grid1(P->n, 256), 256, 0, s>>>(P->keys, P->leaf_of, P->c_par, P->c_lvl, P->c_ix, P->n, P->depth,
+                                                    r2);
         FMM_HIP(hipGetLastError());
         P->c_rad = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * nc));
         k_tight_rad<<<grid1(nc, 256), 256, 0, s>>>(r2, nc, P->c_rad);

@@ -37,8 +37,12 @@ def test_noalloc_matches_evaluate_twice(precision, n1):
         E = torch.full_like(E_r, np.nan)
         F.evaluate_noalloc(xt, qt, p=p, theta=theta, ncrit=ncrit, precision=precision, out=(phi, E))
         torch.cuda.synchronize()
-        # the same kernels on the same plan: bit for bit
-        assert torch.equal(phi, phi_r) and torch.equal(E, E_r), (precision, x.shape[0])
+        # the same kernels on the same tree and lists; the cross-level products
+        # may reach a target in more chunks (the scratch keeps their buffer
+        # small), so sums can group differently: equal to rounding
+        bar = 1e-12 if precision == "fp64" else 1e-6
+        assert rel(host(phi), host(phi_r)) < bar and rel(host(E), host(E_r)) < bar, (precision, x.shape[0])
+        assert not torch.isnan(phi).any() and not torch.isnan(E).any()
         # and within the bar against the oracle at sampled targets
         tg = W.sample_targets(x.shape[0], 256)
         T = oracle.Tree(x, ncrit, theta, targets=tg)
@@ -53,7 +57,7 @@ def test_noalloc_limits_and_errors():
     phi, E = F.evaluate_noalloc(dev(x), dev(q), p=4, field=False)
     assert E is None
     phi_r, _ = F.evaluate(dev(x), dev(q), p=4, field=False)
-    assert torch.equal(phi, phi_r)
+    assert rel(host(phi), host(phi_r)) < 1e-6
     # beyond the stated maximum n: a clear error, nothing runs
     big = torch.zeros(((1 << 18) + 1, 3), dtype=torch.float64, device="cuda:0")
     big[:, 0] = torch.arange(big.shape[0], dtype=torch.float64, device="cuda:0")
@@ -67,4 +71,4 @@ def test_noalloc_limits_and_errors():
         F.evaluate_noalloc(dev(xp), dev(qp), p=12, theta=0.3, ncrit=8)
     assert ei.value.code == 2 and "scratch" in str(ei.value)
     phi2, _ = F.evaluate_noalloc(dev(x), dev(q), p=4, field=False)
-    assert torch.equal(phi2, phi_r)
+    assert rel(host(phi2), host(phi_r)) < 1e-6
