@@ -196,12 +196,11 @@ FMM_API fmm_status fmm_evaluate(const void *x, const void *q, fmm_dtype dtype, i
  * but each waits for the previous one to finish.
  * Limits: n <= FMM_NOALLOC_MAX_N, else FMM_ERR_UNSUPPORTED; a tree whose plan
  * does not fit the array (deep adaptive trees, large p with small theta)
- * fails with FMM_ERR_NOMEM and a message giving the bytes needed.  Uniform
- * bodies at p <= 8, theta >= 0.4, ncrit >= 64 fit up to the maximum n in
- * the mixed precision, and up to about 100,000 bodies in float64 (whose
- * coefficients and operators take twice the bytes).
+ * fails with FMM_ERR_NOMEM and a message giving the bytes in use and asked
+ * for.  Uniform bodies at p <= 8, theta >= 0.4, ncrit >= 64 fit up to the
+ * maximum n in either precision.
  * Other errors: those of fmm_evaluate (without the allocator's). */
-#define FMM_NOALLOC_MAX_N (1 << 18)
+#define FMM_NOALLOC_MAX_N (1 << 17)
 #define FMM_NOALLOC_SCRATCH_BYTES (512ull << 20)
 FMM_API fmm_status fmm_evaluate_noalloc(const void *x, const void *q, fmm_dtype dtype, int64_t n, int32_t p,
                                         double theta, int32_t ncrit, int32_t precision, void *phi, void *field,

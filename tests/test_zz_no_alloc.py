@@ -23,10 +23,11 @@ def _case(n, seed, dist):
     return x, q
 
 
-@pytest.mark.parametrize("precision,n1", [("mixed", 1 << 18), ("fp64", 100_000)])
-def test_noalloc_matches_evaluate_twice(precision, n1):
-    # the largest input the scratch takes for uniform bodies at p = 8 (float64
-    # plans are about twice as large), then a smaller adaptive one
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_noalloc_matches_evaluate_twice(precision):
+    # the largest input the entry point takes (uniform bodies at p = 8), then a
+    # smaller adaptive one
+    n1 = 1 << 17
     cases = [(_case(n1, 51, "cube"), 8, 0.4, 64), (_case(30_000, 52, "plummer"), 6, 0.4, 32)]
     for (x, q), p, theta, ncrit in cases:
         xt, qt = dev(x), dev(q)
@@ -59,14 +60,14 @@ def test_noalloc_limits_and_errors():
     phi_r, _ = F.evaluate(dev(x), dev(q), p=4, field=False)
     assert rel(host(phi), host(phi_r)) < 1e-6
     # beyond the stated maximum n: a clear error, nothing runs
-    big = torch.zeros(((1 << 18) + 1, 3), dtype=torch.float64, device="cuda:0")
+    big = torch.zeros(((1 << 17) + 1, 3), dtype=torch.float64, device="cuda:0")
     big[:, 0] = torch.arange(big.shape[0], dtype=torch.float64, device="cuda:0")
     with pytest.raises(F.FMMError) as ei:
         F.evaluate_noalloc(big, torch.ones(big.shape[0], dtype=torch.float64, device="cuda:0"), p=4)
     assert ei.value.code == 4 and "exceeds" in str(ei.value)
     # a plan larger than the scratch (a deep adaptive tree at high order and a
     # tight acceptance criterion): out of scratch, reported, and the next call works
-    xp, qp = _case(1 << 18, 54, "plummer")
+    xp, qp = _case(1 << 17, 54, "plummer")
     with pytest.raises(F.FMMError) as ei:
         F.evaluate_noalloc(dev(xp), dev(qp), p=12, theta=0.3, ncrit=8)
     assert ei.value.code == 2 and "scratch" in str(ei.value)
