@@ -81,8 +81,9 @@ def roofline_phases(cfg, stats, ph, n, precision):
         # tree build: x, q read (32 B), key (8 B), one sort read + write of
         # (key, index) (24 B), sorted body write (16 B)
         "build": (0.0, 1.0, 80.0 * n),
-        "m2l_same": (2.0 * p2 * p2 * stats["n_m2l_same"], mm, 8.0 * p2 * ncell),
-        "m2l_cross": (2.0 * p2 * p2 * stats["n_m2l_cross"], mm, 0.0),
+        # same-level pairs of sparse tile rows run with the cross-level pairs
+        "m2l_same": (2.0 * p2 * p2 * (stats["n_m2l_same"] - stats["n_m2l_sparse"]), mm, 8.0 * p2 * ncell),
+        "m2l_cross": (2.0 * p2 * p2 * (stats["n_m2l_cross"] + stats["n_m2l_sparse"]), mm, 0.0),
         "p2p": (20.0 * stats["p2p_body_pairs"], va, 32.0 * n),
         "p2m": (5.0 * p2 * n, va, 16.0 * n),
         "l2l": (2.0 * p2 * p2 * ncell, va, 0.0),
@@ -110,6 +111,8 @@ def main():
                     help="targets of the single-thread oracle run (-1: an eighth of the sample, 0: skip)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 GPU forward runs (0 = skip)")
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
+    ap.add_argument("--m2l-sparse", type=int, default=24,
+                    help="same-level tile rows with fewer sources per 64 targets run pair by pair (0: never)")
     ap.add_argument("--tight", action="store_true",
                     help="acceptance also by cell radii tight to the bodies (fewer M2L and P2P pairs)")
     ap.add_argument("--let-ranks", default="",
@@ -145,7 +148,8 @@ def main():
     x = torch.as_tensor(x_np, device=dev)
     q = torch.as_tensor(q_np, device=dev)
     w = torch.as_tensor(w_np, device=dev)
-    prm = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision=args.precision, tight=args.tight)
+    prm = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision=args.precision, tight=args.tight,
+                   m2l_sparse=args.m2l_sparse)
     log(f"bench: {args.config} n={n} p={cfg['p']} theta={cfg['theta']} ncrit={cfg['ncrit']} {args.precision}")
     stream = torch.cuda.current_stream()
     new_plan = lambda timing=False: F.Plan(x, prm, timing=timing, torch_allocator=not args.pool)
@@ -229,7 +233,7 @@ def main():
     # roofline of the dominant kernel: the same-level M2L (all chunk launches
     # of k_m2l_batched in one evaluation, timed by events on their stream) or P2P
     p2 = cfg["p"] ** 2
-    m2l_flops = 2.0 * p2 * p2 * stats["n_m2l_same"]
+    m2l_flops = 2.0 * p2 * p2 * (stats["n_m2l_same"] - stats["n_m2l_sparse"])
     p2p_flops = 20.0 * body_pairs
     if ph["m2l_same"] >= ph["p2p"]:
         peak = PEAK["mfma_f32"] if args.precision == "mixed" else PEAK["mfma_f64"]
@@ -244,6 +248,10 @@ def main():
         roof = {"kernel": "k_p2p", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": recorded_traffic("k_p2p", args.config, args.precision),
                 "launch_ms": ph["p2p"], "flops_per_launch": p2p_flops}
+    # all M2L work (both kernels' pairs) against both phases' time
+    m2l_all = 2.0 * p2 * p2 * stats["n_m2l"] / ((ph["m2l_same"] + ph["m2l_cross"]) * 1e-3) / 1e12
+    roof["m2l_all"] = {"achieved": m2l_all, "frac": m2l_all / (PEAK["mfma_f32"] if args.precision == "mixed"
+                                                              else PEAK["mfma_f64"])}
     roof["tstar_forward_ms"] = tstar_ms
     roof["overall_frac"] = tstar_ms / t_fwd
     roof["phases"] = per_phase
@@ -251,7 +259,8 @@ def main():
     # FP64 GPU baseline (same build + forward), one warm-up run
     fp64_ms, phi64_h, E64_h = None, None, None
     if args.fp64_steps > 0 and args.precision != "fp64":
-        prm64 = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision="fp64", tight=args.tight)
+        prm64 = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision="fp64", tight=args.tight,
+                         m2l_sparse=args.m2l_sparse)
         times = []
         for k in range(args.fp64_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -349,7 +358,7 @@ def main():
                                f"ncrit={cfg['ncrit']}{', tight radii' if args.tight else ''}; forward (build + "
                                f"evaluate) and backward (plan rebuilt, adjoint of L = sum w phi)", "n": n,
                    "p": cfg["p"], "theta": cfg["theta"], "ncrit": cfg["ncrit"], "precision": args.precision,
-                   "tight": args.tight},
+                   "tight": args.tight, "m2l_sparse": args.m2l_sparse},
         "forward_ms": t_fwd,
         "forward_ms_mean": float(np.mean(fwd)),
         "backward_ms": t_bwd,
@@ -362,7 +371,8 @@ def main():
         "err": err,
         "phases_ms": ph,
         "counts": {k: stats[k] for k in ("ncell", "nleaf", "depth", "n_m2l", "n_m2l_same", "n_m2l_cross", "n_p2p",
-                                         "p2p_body_pairs", "m2l_stencil", "m2l_offsets", "device_bytes")},
+                                         "p2p_body_pairs", "m2l_stencil", "m2l_offsets", "m2l_slots", "m2l_rows",
+                                         "n_m2l_sparse", "device_bytes")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -85,10 +85,15 @@ typedef struct {
                                    bodies, Section II.B, Fig. `orb2'), meet the criterion; the radius
                                    is the farthest corner of a member body's 2^-21 lattice cell,
                                    rounded up to units of S 2^-22 (default 0: cube radii only)     */
+    int32_t m2l_sparse;         /* same-level M2L runs as dense products over tiles of targets that
+                                   share one offset; a tile row (one offset) with fewer than
+                                   m2l_sparse sources per 64 targets is evaluated pair by pair with
+                                   the cross-level pairs instead (same sums up to rounding order;
+                                   default 24, 0: never)                                          */
 } fmm_params;
 
 /* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3,
- * kahan=1, tight=0.  P, theta and N_crit are the method parameters of Table I
+ * kahan=1, tight=0, m2l_sparse=24.  P, theta and N_crit are the method parameters of Table I
  * (Section III.A); the values are this library's defaults, not the paper's.
  * A NULL prm is ignored. */
 FMM_API void fmm_params_default(fmm_params *prm);
@@ -130,9 +135,13 @@ typedef struct {
     /* milliseconds of the last evaluation, per phase (HIP events on the stream) */
     double ms_p2m, ms_m2m, ms_m2l, ms_l2l, ms_l2p, ms_p2p, ms_evaluate, ms_adjoint;
     double ms_m2l_cross;     /* cross-level M2L (ms_m2l: same-level, batched) */
-    int64_t m2l_cross_keys;     /* cross-level (level difference, offset) keys with an operator */
-    int64_t m2l_cross_batched;  /* cross-level pairs run as shared-operator products */
+    int64_t m2l_cross_keys;     /* (level difference, offset) keys of the pair list (cross-level
+                                   pairs and the same-level pairs of sparse rows) with an operator */
+    int64_t m2l_cross_batched;  /* pairs of that list run as shared-operator products            */
     int64_t p2p_cut_leaves;     /* leaves whose P2P list is split over several work items */
+    int64_t n_m2l_sparse;       /* same-level pairs evaluated pair by pair (fmm_params.m2l_sparse) */
+    int64_t m2l_rows;           /* (tile, offset) rows the batched M2L multiplies: m2l_rows x the
+                                   tile width slots, of which n_m2l_same - n_m2l_sparse hold a pair */
 } fmm_stats;
 
 /* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are

@@ -37,7 +37,8 @@ class FMMError(RuntimeError):
 
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int32), ("theta", C.c_double), ("ncrit", C.c_int32), ("precision", C.c_int32),
-                ("coarse_fp64_levels", C.c_int32), ("kahan", C.c_int32), ("tight", C.c_int32)]
+                ("coarse_fp64_levels", C.c_int32), ("kahan", C.c_int32), ("tight", C.c_int32),
+                ("m2l_sparse", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -59,7 +60,7 @@ class _Stats(C.Structure):
                 ("ms_l2p", C.c_double), ("ms_p2p", C.c_double), ("ms_evaluate", C.c_double),
                 ("ms_adjoint", C.c_double), ("ms_m2l_cross", C.c_double),
                 ("m2l_cross_keys", C.c_int64), ("m2l_cross_batched", C.c_int64),
-                ("p2p_cut_leaves", C.c_int64)]
+                ("p2p_cut_leaves", C.c_int64), ("n_m2l_sparse", C.c_int64), ("m2l_rows", C.c_int64)]
 
 
 class _LetStats(C.Structure):
@@ -215,12 +216,15 @@ class Params:
     coarse_fp64_levels: int = 3
     kahan: bool = True
     tight: bool = False               # acceptance also by cell radii tight to the bodies
+    m2l_sparse: int = 24              # same-level tile rows below this many sources per 64
+                                      # targets run pair by pair (0: never)
 
     def to_c(self) -> _Params:
         if self.precision not in PREC:
             raise ValueError("precision must be 'mixed' or 'fp64'")
         return _Params(int(self.p), float(self.theta), int(self.ncrit), PREC[self.precision],
-                       int(self.coarse_fp64_levels), 1 if self.kahan else 0, 1 if self.tight else 0)
+                       int(self.coarse_fp64_levels), 1 if self.kahan else 0, 1 if self.tight else 0,
+                       int(self.m2l_sparse))
 
 
 class Plan:

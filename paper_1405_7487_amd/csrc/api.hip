@@ -355,6 +355,7 @@ void validate_params(const fmm_params &p)
     FMM_CHECK(p.precision == FMM_PREC_FP64 || p.precision == FMM_PREC_MIXED, FMM_ERR_INVALID, "bad precision");
     FMM_CHECK(p.coarse_fp64_levels >= 0 && p.coarse_fp64_levels <= kLevels + 1, FMM_ERR_INVALID,
               "coarse_fp64_levels must be in [0, 22]");
+    FMM_CHECK(p.m2l_sparse >= 0 && p.m2l_sparse <= 64, FMM_ERR_INVALID, "m2l_sparse must be in [0, 64]");
 }
 
 // ------------------------------------------------------------ no-alloc scratch
@@ -446,6 +447,7 @@ void fmm_params_default(fmm_params *prm)
     prm->coarse_fp64_levels = 3;
     prm->kahan = 1;
     prm->tight = 0;
+    prm->m2l_sparse = 24;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -481,6 +483,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         P->cfl = pr.coarse_fp64_levels;
         P->kahan = pr.kahan ? 1 : 0;
         P->tight = pr.tight ? 1 : 0;
+        P->m2l_sparse = pr.m2l_sparse;
         P->dtype = dtype;
         P->al.stream = s;
         if (fmm_plan_arena_.base) {
@@ -517,6 +520,12 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         p2p_prepare(P, s);
         FMM_HIP(hipStreamSynchronize(s));
         P->st.ms_ops = ms_since(t2a);
+        if (P->d_m2l_rows) {
+            unsigned long long rows = 0;
+            FMM_HIP(hipMemcpyAsync(&rows, P->d_m2l_rows, sizeof(rows), hipMemcpyDeviceToHost, s));
+            FMM_HIP(hipStreamSynchronize(s));
+            P->m2l_rows = (int64_t)rows;
+        }
         const bool f64 = P->precision == FMM_PREC_FP64;
         const size_t esz = f64 ? sizeof(double) : sizeof(float);
         const size_t ncoef = (size_t)(P->ncell + 1) * P->P2pad;  // + one all-zero row
@@ -766,6 +775,8 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
         st.m2l_cross_keys = P->nxk;
         st.m2l_cross_batched = P->nxb;
         st.p2p_cut_leaves = P->p2p_ncut;
+        st.n_m2l_sparse = P->n_m2l_sparse;
+        st.m2l_rows = P->m2l_rows;
         st.device_bytes = P->bytes_held;
         {
             std::lock_guard<std::mutex> lk(g_ev_mu);
@@ -853,7 +864,7 @@ fmm_status fmm_export_tree(const fmm_plan *Pc, const fmm_tree_export *o)
         }
         if (o->m2l) {
             std::vector<uint64_t> v;
-            csr_pairs(P->m2lx_off, P->m2lx_src, P->n_m2l_cross, v);
+            csr_pairs(P->m2lx_off, P->m2lx_src, P->n_m2lx, v);
             const int64_t ns = P->ntile * (int64_t)P->K * P->TW;
             if (ns > 0) {
                 std::vector<int32_t> sl(ns), tg(P->ntile * P->TW);

@@ -155,6 +155,7 @@ struct fmm_plan {
     double theta = 0.4, t4 = 0.64;
     int ncrit = 64, precision = FMM_PREC_MIXED, cfl = 3, kahan = 1;
     int tight = 0;                   // acceptance also by the cells' own radii (c_rad)
+    int m2l_sparse = 0;              // slot rows below this many sources per 64 targets run as pairs
     fmm_dtype dtype = FMM_F64;
     int timing = 0;
     fmm::Allocator al;
@@ -184,6 +185,10 @@ struct fmm_plan {
 
     // lists
     int64_t n_m2l_same = 0, n_m2l_cross = 0, n_p2p = 0, p2p_body_pairs = 0;
+    int64_t n_m2l_sparse = 0;  // same-level pairs moved from sparse slot rows to the pair list
+    int64_t n_m2lx = 0;        // entries of the m2lx CSR: cross-level plus moved same-level pairs
+    int64_t m2l_rows = 0;      // (tile, entry) rows left to the batched kernel
+    unsigned long long *d_m2l_rows = nullptr;  // its device copy (plan memory)
     int64_t *p2p_off = nullptr;  int32_t *p2p_src = nullptr;   // CSR over cells
     int64_t *p2p_near = nullptr;     // [ncell + 1] end of each list's leading run of touching leaves
     // P2P work items: (leaf, list range, output); long lists are cut into items

@@ -319,6 +319,22 @@ __global__ __launch_bounds__(256) void k_tile_klist(const uint8_t *kflag, int K,
     if (threadIdx.x == 0) nk[tile] = s_base;
 }
 
+// Sum of the tiles' entry counts (rows the batched kernel multiplies).
+__global__ __launch_bounds__(1024) void k_sum_rows(const int32_t *nk, int64_t ntile, unsigned long long *out)
+{
+    __shared__ unsigned long long part[16];
+    unsigned long long t = 0;
+    for (int64_t i = threadIdx.x; i < ntile; i += blockDim.x) t += (unsigned long long)nk[i];
+    for (int w = 32; w >= 1; w >>= 1) t += __shfl_xor(t, w, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += part[w];
+        *out = a;
+    }
+}
+
 // L += the G partial products of each target, in chunk order.
 template <class T>
 __global__ __launch_bounds__(256) void k_m2l_reduce(const T *part, int G, int64_t ncol, int P2pad,
@@ -550,7 +566,7 @@ __global__ __launch_bounds__(256) void k_x_codes(const int32_t *tgt, const int32
     const int la = lvl[a], lb = lvl[b], dl = lb - la;
     const int adl = dl < 0 ? -dl : dl;
     int cd = -1;
-    if (adl >= 1 && adl <= xc.maxdl) {
+    if (adl <= xc.maxdl && xc.R[adl] > 0) {
         const int f = la > lb ? la : lb, R = xc.R[adl], W = 2 * R + 1;
         int64_t D[3];
         bool ok = true;
@@ -578,6 +594,20 @@ __global__ __launch_bounds__(256) void k_x_sum_stripes(int32_t *cnt, int64_t nco
     int32_t t = cnt[c];
     for (int k = 1; k < kXStripes; ++k) t += cnt[k * ncode + c];
     cnt[c] = t;
+}
+
+// The shared-operator tiles of key id: tile tile0[id] + j covers pairs
+// pair0[id] + j TW onwards (at most TW of the key's count).
+__global__ __launch_bounds__(256) void k_x_tiles(const int64_t *tile0, const int64_t *pair0, const int64_t *cnt,
+                                                 int TW, int32_t *xt_op, int64_t *xt_first, int32_t *xt_cnt)
+{
+    const int id = blockIdx.x;
+    const int64_t t0 = tile0[id], nt = tile0[id + 1] - t0;
+    for (int64_t j = threadIdx.x; j < nt; j += blockDim.x) {
+        xt_op[t0 + j] = id;
+        xt_first[t0 + j] = pair0[id] + j * TW;
+        xt_cnt[t0 + j] = (int32_t)min((int64_t)TW, cnt[id] - j * TW);
+    }
 }
 
 // Sort key (key id, target) for batched pairs; generic pairs get id = nk and
@@ -854,6 +884,10 @@ void m2l_prepare(fmm_plan *P, hipStream_t s)
     P->tile_nk = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->ntile));
     k_tile_klist<<<(unsigned)P->ntile, 256, 0, s>>>(P->tile_kflag, P->K, P->tile_kl, P->tile_nk);
     FMM_HIP(hipGetLastError());
+    // (read by the host after the build's final synchronisation)
+    P->d_m2l_rows = static_cast<unsigned long long *>(plan_alloc(P, sizeof(unsigned long long)));
+    k_sum_rows<<<1, 1024, 0, s>>>(P->tile_nk, P->ntile, P->d_m2l_rows);
+    FMM_HIP(hipGetLastError());
 
     const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
     const double opbytes = (double)m2l_opsz(P->P2pad / 16, m2l_q(P->p), (int)esz) * esz;
@@ -903,20 +937,24 @@ namespace {
 // pairs left to the generic kernel.
 void x_batch_prepare(fmm_plan *P, hipStream_t s)
 {
-    const int64_t nx = P->n_m2l_cross, nc = P->ncell;
+    const int64_t nx = P->n_m2lx, nc = P->ncell;
     Allocator &al = P->al;
     const bool f64 = P->precision == FMM_PREC_FP64;
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
 
+    // Key (dl, D): level difference dl = l_B - l_A and center offset D in
+    // half sides of the finer cell.  Same-level pairs (dl = 0, from sparse
+    // slot rows) have D = 2 t with t in the stencil, |t_d| <= R.
     XCodes xc;
     for (int maxdl = kXMaxDl; maxdl >= 1; --maxdl) {
         xc = XCodes();
         xc.maxdl = maxdl;
         int64_t base = 0;
+        xc.R[0] = P->n_m2l_sparse > 0 ? 2 * P->R : 0;
         for (int adl = 1; adl <= maxdl; ++adl)
             xc.R[adl] = (int)std::ceil(std::sqrt(3.0) * ((std::ldexp(1.0, adl) + 2.0) / P->theta + 1.0));
         for (int dl = -maxdl; dl <= maxdl; ++dl) {
-            if (dl == 0) continue;
+            if (xc.R[dl < 0 ? -dl : dl] == 0) continue;
             const int64_t W = 2 * xc.R[dl < 0 ? -dl : dl] + 1;
             xc.base[dl + kXMaxDl] = (int)base;
             base += W * W * W;
@@ -943,7 +981,7 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     std::vector<int32_t> id_of(xc.ncode, -1), key_cnt;
     std::vector<double4> tr;
     for (int dl = -xc.maxdl; dl <= xc.maxdl; ++dl) {
-        if (dl == 0) continue;
+        if (xc.R[dl < 0 ? -dl : dl] == 0) continue;
         const int R = xc.R[dl < 0 ? -dl : dl], W = 2 * R + 1, b0 = xc.base[dl + kXMaxDl];
         const double sc = std::ldexp(0.5, -std::max(dl, 0));
         for (int64_t o = 0; o < (int64_t)W * W * W; ++o) {
@@ -975,31 +1013,33 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     const int64_t bbytes = P->noalloc ? (16ll << 20)
                                       : std::min<int64_t>(16ll << 30, std::max<int64_t>(2ll << 30, allpairs * pbytes / 4));
     const int64_t budget = std::max<int64_t>((int64_t)TW, bbytes / pbytes);
-    std::vector<int32_t> h_op, h_cnt, chunk_of(nk);
-    std::vector<int64_t> h_first;
+    // per key: first tile, first pair and pair count (the tiles themselves
+    // are filled on the device)
+    std::vector<int32_t> chunk_of(nk);
+    std::vector<int64_t> kinfo(3 * (size_t)nk + 1);  // [tile0 (nk + 1) | pair0 (nk) | count (nk)]
     P->xchunks.clear();
-    int64_t pos = 0, maxchunk = 0;
+    int64_t pos = 0, ntl = 0, maxchunk = 0;
     XChunk cur;
     for (int id = 0; id < nk; ++id) {
         if (pos > cur.p0 && pos - cur.p0 + key_cnt[id] > budget) {
             cur.p1 = pos;
-            cur.t1 = (int64_t)h_op.size();
+            cur.t1 = ntl;
             maxchunk = std::max(maxchunk, cur.p1 - cur.p0);
             P->xchunks.push_back(cur);
             cur = XChunk();
             cur.p0 = pos;
-            cur.t0 = (int64_t)h_op.size();
+            cur.t0 = ntl;
         }
         chunk_of[id] = (int32_t)P->xchunks.size();
-        for (int64_t k = 0; k < key_cnt[id]; k += TW) {
-            h_op.push_back(id);
-            h_first.push_back(pos + k);
-            h_cnt.push_back((int32_t)std::min<int64_t>(TW, key_cnt[id] - k));
-        }
+        kinfo[id] = ntl;
+        kinfo[nk + 1 + id] = pos;
+        kinfo[2 * (size_t)nk + 1 + id] = key_cnt[id];
+        ntl += (key_cnt[id] + TW - 1) / TW;
         pos += key_cnt[id];
     }
+    kinfo[nk] = ntl;
     cur.p1 = pos;
-    cur.t1 = (int64_t)h_op.size();
+    cur.t1 = ntl;
     maxchunk = std::max(maxchunk, cur.p1 - cur.p0);
     P->xchunks.push_back(cur);
     const int64_t nb = pos;
@@ -1007,14 +1047,16 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     FMM_CHECK(nchunk < (1 << 11), FMM_ERR_UNSUPPORTED, "m2l: too many cross-level chunks");
     P->nxk = nk;
     P->nxb = nb;
-    P->nxt = (int64_t)h_op.size();
+    P->nxt = ntl;
 
     P->xt_op = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->nxt));
     P->xt_first = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * P->nxt));
     P->xt_cnt = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * P->nxt));
-    FMM_HIP(hipMemcpyAsync(P->xt_op, h_op.data(), sizeof(int32_t) * P->nxt, hipMemcpyHostToDevice, s));
-    FMM_HIP(hipMemcpyAsync(P->xt_first, h_first.data(), sizeof(int64_t) * P->nxt, hipMemcpyHostToDevice, s));
-    FMM_HIP(hipMemcpyAsync(P->xt_cnt, h_cnt.data(), sizeof(int32_t) * P->nxt, hipMemcpyHostToDevice, s));
+    int64_t *d_kinfo = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * kinfo.size()));
+    FMM_HIP(hipMemcpyAsync(d_kinfo, kinfo.data(), sizeof(int64_t) * kinfo.size(), hipMemcpyHostToDevice, s));
+    k_x_tiles<<<(unsigned)nk, 256, 0, s>>>(d_kinfo, d_kinfo + nk + 1, d_kinfo + 2 * (size_t)nk + 1, TW, P->xt_op,
+                                           P->xt_first, P->xt_cnt);
+    FMM_HIP(hipGetLastError());
     double4 *d_tr = static_cast<double4 *>(al.alloc(sizeof(double4) * nk));
     FMM_HIP(hipMemcpyAsync(d_tr, tr.data(), sizeof(double4) * nk, hipMemcpyHostToDevice, s));
     const int RTx = P->P2pad / 16;
@@ -1086,6 +1128,7 @@ void x_batch_prepare(fmm_plan *P, hipStream_t s)
     P->xbuf = plan_alloc(P, esz * (size_t)maxchunk * P->P2pad);
 
     al.free(d_cs);
+    al.free(d_kinfo);
     al.free(d_nseg);
     al.free(sidx);
     al.free(flag);
@@ -1133,10 +1176,10 @@ void x_generic_prepare(fmm_plan *P, hipStream_t s)
 
 void m2l_cross_prepare(fmm_plan *P, hipStream_t s)
 {
-    P->n_gx = P->n_m2l_cross;
+    P->n_gx = P->n_m2lx;
     P->gx_off = P->m2lx_off;
     P->gx_src = P->m2lx_src;
-    if (P->n_m2l_cross == 0) return;
+    if (P->n_m2lx == 0) return;
     x_batch_prepare(P, s);
     x_generic_prepare(P, s);
 }

@@ -630,6 +630,77 @@ int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s)
     return h;
 }
 
+// Sparse rows of the slot table.  A row is one stencil entry of one tile: the
+// batched M2L multiplies it for all TW targets of the tile, so a row whose
+// sources are few costs nearly as much as a full one.
+// Pass 1 streams the table, 4 slots per lane (TW / 4 lanes per row): each
+// row's source count goes to its flag byte (0 for an empty row), and spc[r]
+// = the count if 0 < count * 64 < thr * TW (a sparse row), else 0.  An
+// exclusive scan of spc gives each sparse row its first output position.
+// Pass 2, 64 rows per wave, moves the pairs of each sparse row to out, in row
+// then lane order, as pair-list keys (target << cbits | source) and clears
+// the row (slots -1, flag 0).  No atomics: the output is the same on every
+// run.
+__global__ __launch_bounds__(256) void k_sparse_count(const int4 *slots4, uint8_t *kflag, int64_t nrow, int TW,
+                                                      int thr, int32_t *spc)
+{
+    const int lane = threadIdx.x & 63;
+    const int LPR = TW >> 2;  // lanes per row (16 or 32)
+    const int64_t n4 = nrow * LPR;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same trip count
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; i < n4; i += stride) {
+        const int64_t k = i + lane;
+        int o = 0;
+        if (k < n4) {
+            const int4 v = slots4[k];
+            o = (v.x >= 0) + (v.y >= 0) + (v.z >= 0) + (v.w >= 0);
+        }
+        for (int w = 1; w < LPR; w <<= 1) o += __shfl_xor(o, w, 64);
+        if (k < n4 && (lane & (LPR - 1)) == 0) {
+            const int64_t r = k / LPR;
+            kflag[r] = (uint8_t)o;
+            spc[r] = (o > 0 && o * 64 < thr * TW) ? o : 0;
+        }
+    }
+}
+
+template <int TWC>
+__global__ __launch_bounds__(256) void k_sparse_move(int32_t *slots, uint8_t *kflag, const int32_t *tile_tgt,
+                                                     const int32_t *spc, const int64_t *off, int64_t nrow, int K,
+                                                     int cbits, uint64_t *out)
+{
+    constexpr int TW = 64 * TWC;
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r0 = w0 * 64; r0 < nrow; r0 += nw * 64) {
+        const int64_t rl = r0 + lane;
+        const int c_l = rl < nrow ? spc[rl] : 0;
+        const int64_t o_l = c_l ? off[rl] : 0;
+        uint64_t todo = __ballot(c_l > 0);
+        while (todo) {
+            const int jl = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int64_t r = r0 + jl, tile = r / K;
+            unsigned long long base = (unsigned long long)__shfl(o_l, jl, 64);
+            int32_t *row = slots + r * TW;
+#pragma unroll
+            for (int c = 0; c < TWC; ++c) {
+                const int32_t sv = row[64 * c + lane];
+                const uint64_t m = __ballot(sv >= 0);
+                if (sv >= 0) {
+                    const int32_t tg = tile_tgt[tile * TW + 64 * c + lane];
+                    out[base + __popcll(m & ((1ull << lane) - 1))] = ((uint64_t)tg << cbits) | (uint64_t)sv;
+                    row[64 * c + lane] = -1;
+                }
+                base += __popcll(m);
+            }
+            if (lane == 0) kflag[r] = 0;
+        }
+    }
+}
+
 // Digests of the M2L list (same-level slots and cross-level CSR) and of the
 // P2P list; synchronises the stream.
 void list_digest(fmm_plan *P, uint64_t out[2], hipStream_t s)
@@ -826,6 +897,38 @@ void traverse(fmm_plan *P, hipStream_t s)
     al.free(d_tot);
     al.free(tile_pos);
 
+    // same-level pairs of sparse slot rows join the cross-level pairs
+    int64_t nsparse = 0;
+    const int64_t nrow = tiles * (int64_t)P->K;
+    if (P->m2l_sparse > 0 && nrow > 0) {
+        FMM_CHECK(P->TW == 64 || P->TW == 128, FMM_ERR_DEVICE, "traversal: tile width");
+        // (the flag array holds one byte per row: a count of at most 128 fits)
+        int32_t *spc = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nrow));
+        int64_t *off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * nrow));
+        int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+        k_sparse_count<<<grid_fill(nrow * (P->TW / 4)), 256, 0, s>>>(reinterpret_cast<const int4 *>(P->slots),
+                                                                      P->tile_kflag, nrow, P->TW, P->m2l_sparse, spc);
+        FMM_HIP(hipGetLastError());
+        scan_exclusive_i32to64(spc, off, nrow, d_tot, al, s);
+        FMM_HIP(hipMemcpyAsync(&nsparse, d_tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        FMM_HIP(hipStreamSynchronize(s));
+        if (nsparse > 0) {
+            uint64_t *sp = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * nsparse));
+            const dim3 gm = grid_fill((nrow + 63) / 64 * 64);
+            if (P->TW == 64)
+                k_sparse_move<1><<<gm, 256, 0, s>>>(P->slots, P->tile_kflag, P->tile_tgt, spc, off, nrow, P->K, cbits,
+                                                    sp);
+            else
+                k_sparse_move<2><<<gm, 256, 0, s>>>(P->slots, P->tile_kflag, P->tile_tgt, spc, off, nrow, P->K, cbits,
+                                                    sp);
+            FMM_HIP(hipGetLastError());
+            cross_parts.push_back({sp, nsparse});
+        }
+        al.free(d_tot);
+        al.free(off);
+        al.free(spc);
+    }
+
     int h_err = 0;
     unsigned long long h_cnt[2];
     FMM_HIP(hipMemcpyAsync(&h_err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -834,6 +937,8 @@ void traverse(fmm_plan *P, hipStream_t s)
     FMM_CHECK(h_err == 0, FMM_ERR_DEVICE, "traversal: same-level pair outside its stencil");
     P->n_m2l_same = (int64_t)h_cnt[0];
     P->n_m2l_cross = ncross;
+    P->n_m2l_sparse = nsparse;
+    P->n_m2lx = ncross + nsparse;
     P->n_p2p = np2p;
 
     // Concatenate (unless one generation produced the whole list), sort and
@@ -853,9 +958,9 @@ void traverse(fmm_plan *P, hipStream_t s)
         return all;
     };
     uint64_t *p2p_all = concat(p2p_parts, np2p);
-    uint64_t *cross_all = concat(cross_parts, ncross);
+    uint64_t *cross_all = concat(cross_parts, ncross + nsparse);
     sort_to_csr(P, p2p_all, np2p, cbits, 1, &P->p2p_off, &P->p2p_src, &P->p2p_near, nullptr, s);
-    sort_to_csr(P, cross_all, ncross, cbits, 0, &P->m2lx_off, &P->m2lx_src, nullptr, nullptr, s);
+    sort_to_csr(P, cross_all, ncross + nsparse, cbits, 0, &P->m2lx_off, &P->m2lx_src, nullptr, nullptr, s);
     P->p2p_body_pairs = -1;  // counted on demand by p2p_body_pairs()
     for (auto &pr : p2p_parts) al.free(pr.first);
     for (auto &pr : cross_parts) al.free(pr.first);

@@ -112,9 +112,9 @@ def test_fmm_matches_oracle(case):
     assert e64[0] < 1e-6 and e64[1] < 1e-6
     assert e64[0] < 1e-11 and e64[1] < 1e-11, e64  # roundoff only
     if case == "plummer":
-        # both cross-level paths run: shared-operator tiles and the generic kernel
+        # both pair-list paths run: shared-operator tiles and the generic kernel
         st = plan.stats()
-        assert 0 < st["m2l_cross_batched"] < st["n_m2l_cross"], st
+        assert 0 < st["m2l_cross_batched"] < st["n_m2l_cross"] + st["n_m2l_sparse"], st
     _, pm, Em = gpu_fmm(x, q, p, theta, ncrit, "mixed")
     em = (rel(pm, po), rel(Em, Eo))
     assert em[0] < 1e-4 and em[1] < 1e-4, em
@@ -150,6 +150,40 @@ def test_cross_level_pairs_plummer(p, n, ncrit, theta):
         st = plan.stats()
         assert st["m2l_cross_batched"] > 0.5 * st["n_m2l_cross"], st
         assert rel(ph, po) < tol and rel(Eh, Eo) < tol, (precision, rel(ph, po), rel(Eh, Eo))
+
+
+@pytest.mark.parametrize("p,n,ncrit,theta", [(6, 60000, 16, 0.35), (4, 40000, 24, 0.4)])
+def test_sparse_rows_run_as_pairs(p, n, ncrit, theta):
+    # same-level tile rows with few sources move to the pair list: the lists
+    # (as sets) and the values stay those of the oracle for every threshold,
+    # at a tile width of 64 (p = 6) and 128 (p = 4)
+    x, _, _ = W.plummer(n, 31)
+    q = np.random.default_rng(32).uniform(-1.0, 1.0, n)
+    T = oracle.Tree(x, ncrit, theta)
+    o = T.export()
+    po, Eo = T.fmm(q, p)
+    moved, rows, vals = [], [], []
+    for thr in (0, 24, 64):
+        plan = F.Plan(dev(x), F.Params(p=p, theta=theta, ncrit=ncrit, precision="fp64", m2l_sparse=thr))
+        st = plan.stats()
+        assert (st["n_m2l_same"], st["n_m2l_cross"]) == (T.n_m2l - st["n_m2l_cross"], st["n_m2l_cross"])
+        assert st["n_m2l"] == T.n_m2l and plan.list_digest() == (T.digest_m2l, T.digest_p2p)
+        assert np.array_equal(plan.export_tree()["m2l"], o["m2l"]), thr
+        assert st["m2l_cross_batched"] <= st["n_m2l_cross"] + st["n_m2l_sparse"]
+        moved.append(st["n_m2l_sparse"])
+        rows.append(st["m2l_rows"])
+        phi, E = plan.evaluate(dev(q))
+        vals.append((host(phi), host(E)))
+        assert rel(vals[-1][0], po) < 1e-11 and rel(vals[-1][1], Eo) < 1e-11, thr
+        plan.close()
+        plan = F.Plan(dev(x), F.Params(p=p, theta=theta, ncrit=ncrit, precision="mixed", m2l_sparse=thr))
+        phi, E = plan.evaluate(dev(q))
+        assert rel(host(phi), po) < 1e-4 and rel(host(E), Eo) < 1e-4, thr
+        plan.close()
+    assert moved[0] == 0 and 0 < moved[1] < moved[2] < T.n_m2l
+    assert rows[0] > rows[1] > rows[2]
+    # only the grouping of the sums differs
+    assert rel(vals[1][0], vals[0][0]) < 1e-13 and rel(vals[2][1], vals[0][1]) < 1e-13
 
 
 def test_nearly_coincident_bodies_keep_their_field():
