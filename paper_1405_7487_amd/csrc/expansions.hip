@@ -142,7 +142,8 @@ __host__ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
 // size ratio rho = h_B / h_A = 2^e (0 for same-level pairs), which scales
 // input degree n by rho^n.
 template <class T>
-__global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nops, int p, int P2pad, T *Tf)
+__global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nops, int p, int P2pad, int SCH, int GST,
+                                                      int64_t OPSZ, T *Tf)
 {
     const int op = blockIdx.x;
     if (op >= nops) return;
@@ -152,10 +153,9 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nop
     const int e2 = (int)t.w;
     if (threadIdx.x == 0) irregular_table(t.x, t.y, t.z, nI, H);
     __syncthreads();
+    // (SCH, GST, OPSZ: the table layout, computed by the host)
     const int P2 = p * p, Q = m2l_q(p), NCOL = 4 * Q;
-    const int RT = P2pad / 16, esz = (int)sizeof(T);
-    const int SCH = m2l_sch(RT, Q, esz), GST = m2l_gst(RT, Q, esz);
-    const int64_t OPSZ = m2l_opsz(RT, Q, esz);
+    const int RT = P2pad / 16;
     for (int e = threadIdx.x; e < P2pad * NCOL; e += blockDim.x) {
         const int row = e / NCOL, col = e % NCOL;
         double v = 0.0;
@@ -540,9 +540,13 @@ void make_operators(fmm_plan *P, hipStream_t s)
         FMM_HIP(hipMemsetAsync(C.ops, 0, (f64 ? sizeof(double) : sizeof(float)) * opn, s));
         if (P->nops > 0) {
             if (f64)
-                k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<double *>(C.ops));
+                k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, m2l_sch(P2pad / 16, Q, 8),
+                                                               m2l_gst(P2pad / 16, Q, 8), m2l_opsz(P2pad / 16, Q, 8),
+                                                               static_cast<double *>(C.ops));
             else
-                k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, static_cast<float *>(C.ops));
+                k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, m2l_sch(P2pad / 16, Q, 4),
+                                                              m2l_gst(P2pad / 16, Q, 4), m2l_opsz(P2pad / 16, Q, 4),
+                                                              static_cast<float *>(C.ops));
             FMM_HIP(hipGetLastError());
         }
         const size_t shn = (size_t)8 * P2pad * P2pad;
@@ -581,10 +585,13 @@ void make_operators(fmm_plan *P, hipStream_t s)
 void make_m2l_ops(fmm_plan *P, const double4 *tr_dev, int nops, void *out, hipStream_t s)
 {
     if (nops <= 0) return;
+    const int RT = P->P2pad / 16, Q = m2l_q(P->p);
     if (P->precision == FMM_PREC_FP64)
-        k_make_m2l_ops<double><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<double *>(out));
+        k_make_m2l_ops<double><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, m2l_sch(RT, Q, 8), m2l_gst(RT, Q, 8),
+                                                    m2l_opsz(RT, Q, 8), static_cast<double *>(out));
     else
-        k_make_m2l_ops<float><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, static_cast<float *>(out));
+        k_make_m2l_ops<float><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, m2l_sch(RT, Q, 4), m2l_gst(RT, Q, 4),
+                                                   m2l_opsz(RT, Q, 4), static_cast<float *>(out));
     FMM_HIP(hipGetLastError());
 }
 

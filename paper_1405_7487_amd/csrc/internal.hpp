@@ -56,8 +56,8 @@ inline int p2pad_of(int p) { return ((p * p + 15) / 16) * 16; }
 // each group SCH rows of P2pad values in MFMA fragment order:
 //     op[(c 4 + g) GST + ss P2pad + (row % 16) RT + row / 16] = T[row][g Q + c SCH + ss].
 // A stage is contiguous so that four waves copy it straight into LDS, 1 KiB
-// per wave and instruction; with RT odd the groups sit 64 bytes apart so the
-// fragment reads of lanes 0-31 fall in different LDS banks.  SCH is the
+// per wave and instruction; the groups are padded apart (m2l_gst) so that the
+// fragment reads of a step fall in different LDS banks.  SCH is the
 // largest divisor of Q (a multiple of 4, else of 2, when one exists) whose
 // stage fits 16 KiB (32 KiB for float64, whose fragments are half as long),
 // i.e. SCH RT <= 64.
@@ -86,9 +86,30 @@ __host__ __device__ constexpr int m2l_q(int p)
     return (best >= 4 || best == q0) ? q0 : 4 * RT;
 }
 __host__ __device__ constexpr int m2l_rt(int p) { return (p * p + 15) / 16; }
+// Whether the fragment reads of a step, lane (g, j) at word g G + j RT, fall
+// in 64 different LDS banks.
+__host__ __device__ constexpr bool m2l_banks_distinct(int G, int RT)
+{
+    bool seen[64] = {};
+    for (int g = 0; g < 4; ++g)
+        for (int j = 0; j < 16; ++j) {
+            const int b = (g * G + j * RT) % 64;
+            if (seen[b]) return false;
+            seen[b] = true;
+        }
+    return true;
+}
+// Elements from one k-group of a stage to the next: SCH rows of P2pad values
+// plus padding.  float32: the smallest pad that spreads the 64 lanes' reads
+// over 64 banks, where one exists (for RT = 6, 8, 16 none does); float64
+// (and those): 64 bytes when RT is odd.
 __host__ __device__ constexpr int m2l_gst(int RT, int Q, int esz)
 {
-    return m2l_sch(RT, Q, esz) * 16 * RT + ((RT & 1) ? 64 / esz : 0);
+    const int base = m2l_sch(RT, Q, esz) * 16 * RT;
+    if (esz == 4)
+        for (int pad = 0; pad < 64; ++pad)
+            if (m2l_banks_distinct(base + pad, RT)) return base + pad;
+    return base + ((RT & 1) ? 64 / esz : 0);
 }
 // elements per operator, and the zero tail a table needs after its last operator
 // (the last stage copy is rounded up to whole 4 KiB block rounds)

@@ -691,7 +691,8 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, j = lane & 15, g = lane >> 4;
     const int cnt = t_cnt[tile];
     const int64_t first = t_first[tile];
-    const T *opb = Tf + (int64_t)t_op[tile] * m2l_opsz(RT, Q, ESZ);
+    constexpr int64_t OPSZ = m2l_opsz(RT, Q, ESZ);
+    const T *opb = Tf + (int64_t)t_op[tile] * OPSZ;
 
     stage_copy<T, RT, Q, WV>(opb, lds, wave, lane);
     T bq[CG][Q];

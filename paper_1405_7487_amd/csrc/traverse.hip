@@ -53,7 +53,7 @@ struct TreeView {
     const int32_t *tile_pos;  // cell -> tile*64 + lane (or -1)
     const int32_t *kidx;      // [8][(2R+1)^3]
     int32_t *slots;
-    uint8_t *kflag;  // [ntile][K]: entry has a source in the tile
+    uint8_t *kflag;  // [ntile][K]: sources of the entry in the tile (set after the traversal)
     int K, R, TW;
     double t4;
 };
@@ -215,12 +215,8 @@ __global__ __launch_bounds__(256) void k_expand_write(TreeView T, const int2 *F,
                     int kk = -1;
                     if (abs(tx) <= T.R && abs(ty) <= T.R && abs(tz) <= T.R)
                         kk = kx[((tx + T.R) * W + (ty + T.R)) * W + (tz + T.R)];
-                    if (kk < 0 || pos < 0) {
-                        atomicOr(err, 1);
-                    } else {
-                        T.slots[(tile * T.K + kk) * T.TW + lane] = y;
-                        T.kflag[tile * T.K + kk] = 1;
-                    }
+                    if (kk < 0 || pos < 0) atomicOr(err, 1);
+                    else T.slots[(tile * T.K + kk) * T.TW + lane] = y;
                 } else if (k == 1) {
                     cross[ox++] = ((uint64_t)x << cbits) | (uint64_t)y;
                 } else if (k == 2) {
@@ -634,8 +630,9 @@ int64_t p2p_body_pairs(fmm_plan *P, hipStream_t s)
 // batched M2L multiplies it for all TW targets of the tile, so a row whose
 // sources are few costs nearly as much as a full one.
 // Pass 1 streams the table, 4 slots per lane (TW / 4 lanes per row): each
-// row's source count goes to its flag byte (0 for an empty row), and spc[r]
-// = the count if 0 < count * 64 < thr * TW (a sparse row), else 0.  An
+// row's source count goes to its flag byte (0 for an empty row), and, when
+// spc is given, spc[r] = the count if 0 < count * 64 < thr * TW (a sparse
+// row), else 0.  An
 // exclusive scan of spc gives each sparse row its first output position.
 // Pass 2, 64 rows per wave, moves the pairs of each sparse row to out, in row
 // then lane order, as pair-list keys (target << cbits | source) and clears
@@ -660,7 +657,7 @@ __global__ __launch_bounds__(256) void k_sparse_count(const int4 *slots4, uint8_
         if (k < n4 && (lane & (LPR - 1)) == 0) {
             const int64_t r = k / LPR;
             kflag[r] = (uint8_t)o;
-            spc[r] = (o > 0 && o * 64 < thr * TW) ? o : 0;
+            if (spc) spc[r] = (o > 0 && o * 64 < thr * TW) ? o : 0;
         }
     }
 }
@@ -816,8 +813,8 @@ void traverse(fmm_plan *P, hipStream_t s)
     al.free(idx);
     al.free(ck);
 
+    // (every byte is written by the row count after the traversal)
     P->tile_kflag = static_cast<uint8_t *>(plan_alloc(P, std::max<int64_t>(1, tiles * (int64_t)P->K)));
-    if (tiles > 0) FMM_HIP(hipMemsetAsync(P->tile_kflag, 0, tiles * (int64_t)P->K, s));
     const int64_t nslots = tiles * (int64_t)P->K * P->TW;
     P->slots = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nslots)));
     if (nslots > 0) {
@@ -897,18 +894,23 @@ void traverse(fmm_plan *P, hipStream_t s)
     al.free(d_tot);
     al.free(tile_pos);
 
-    // same-level pairs of sparse slot rows join the cross-level pairs
+    // Row counts (the flags the batched M2L lists its entries by); with
+    // m2l_sparse > 0 the same-level pairs of sparse rows join the cross-level
+    // pairs.
     int64_t nsparse = 0;
     const int64_t nrow = tiles * (int64_t)P->K;
-    if (P->m2l_sparse > 0 && nrow > 0) {
+    int32_t *spc = nullptr;
+    if (nrow > 0) {
         FMM_CHECK(P->TW == 64 || P->TW == 128, FMM_ERR_DEVICE, "traversal: tile width");
         // (the flag array holds one byte per row: a count of at most 128 fits)
-        int32_t *spc = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nrow));
-        int64_t *off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * nrow));
-        int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+        if (P->m2l_sparse > 0) spc = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nrow));
         k_sparse_count<<<grid_fill(nrow * (P->TW / 4)), 256, 0, s>>>(reinterpret_cast<const int4 *>(P->slots),
                                                                       P->tile_kflag, nrow, P->TW, P->m2l_sparse, spc);
         FMM_HIP(hipGetLastError());
+    }
+    if (spc) {
+        int64_t *off = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * nrow));
+        int64_t *d_tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
         scan_exclusive_i32to64(spc, off, nrow, d_tot, al, s);
         FMM_HIP(hipMemcpyAsync(&nsparse, d_tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         FMM_HIP(hipStreamSynchronize(s));
