@@ -36,6 +36,8 @@ def lib():
         L.oracle_op_m2p.restype = C.c_double
         L.oracle_op_m2m.argtypes = [_dp, _dp, _dp, C.c_int, _dp]
         L.oracle_op_m2l.argtypes = [_dp, _dp, _dp, C.c_int, _dp]
+        L.oracle_op_m2l_rot.argtypes = [_dp, _dp, _dp, C.c_int, _dp]
+        L.oracle_wigner_d.argtypes = [C.c_int, C.c_double, _dp]
         L.oracle_op_l2l.argtypes = [_dp, _dp, _dp, C.c_int, _dp]
         L.oracle_op_l2p.argtypes = [_dp, _dp, C.c_int, C.c_int64, _dp, _dp, _dp]
         L.oracle_tree_new.argtypes = [C.c_int64, _dp, C.c_int32, C.c_double, C.c_int64, _i64p]
@@ -148,6 +150,21 @@ def op_m2l(M, cB, cA, p):
     out = np.zeros(2 * p * p)
     lib().oracle_op_m2l(_d(_c(M)), _d(_f64(cB)), _d(_f64(cA)), p, _d(out))
     return out.view(np.complex128)
+
+
+def op_m2l_rot(M, cB, cA, p):
+    """M2L by rotating D onto +z, translating along z and rotating back:
+    O(p^3) per pair, the same operator as op_m2l up to rounding."""
+    out = np.zeros(2 * p * p)
+    lib().oracle_op_m2l_rot(_d(_c(M)), _d(_f64(cB)), _d(_f64(cA)), p, _d(out))
+    return out.view(np.complex128)
+
+
+def wigner_d(n, b):
+    """Wigner small-d matrix d^n_{m' m}(b), rows m' and columns m from -n to n."""
+    out = np.zeros((2 * n + 1) * (2 * n + 1))
+    lib().oracle_wigner_d(int(n), float(b), _d(out))
+    return out.reshape(2 * n + 1, 2 * n + 1)
 
 
 def op_l2l(L, cpar, cch, p):

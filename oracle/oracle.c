@@ -24,6 +24,9 @@
  *                  textbook definition (associated Legendre functions and
  *                  e^{i m phi}); translations from the addition theorem of
  *                  the regular solid harmonics
+ *   M2L by rotation the O(P^3) form of the same operator (Section III.A):
+ *                  rotate D onto +z with Wigner's explicit d-matrices,
+ *                  translate along z, rotate back
  *
  * Every target output is accumulated by one thread in a fixed order, so the
  * result is bit-identical for any OpenMP thread count.
@@ -36,7 +39,9 @@
  * against an independent recursive octree and published cell counts; list
  * invariants and lattice counts; the a priori error bound of the whole FMM;
  * energy symmetry; scaling and axis-permutation invariance; frozen-tree
- * finite differences.  No function here is "parity unpinned".
+ * finite differences; Wigner matrices against closed forms, orthogonality
+ * and the rotation of the harmonics; rotation M2L against the dense M2L.
+ * No function here is "parity unpinned".
  */
 #include <complex.h>
 #include <math.h>
@@ -224,6 +229,73 @@ static void m2l_add(const cplx *M, const double cB[3], const double cA[3], int p
     }
 }
 
+/* M2L by rotation, O(p^3) per pair.  The operators' cost ranges from O(P^3)
+ * to O(P^6) with the basis (Section III.A); with spherical harmonics the
+ * O(P^3) form rotates the frame so that D = c_A - c_B lies on +z, translates
+ * along z and rotates back (White & Head-Gordon 1996).
+ *
+ * Both R_n^m and I_n^m are multiples of C_n^m = sqrt((n-m)!/(n+m)!) P_n^m
+ * e^{i m f}:  R_n^m = r^n C_n^m / s_m,  I_n^m = s_m C_n^m / r^{n+1},  with
+ * s_m = sqrt((n+m)! (n-m)!).  Let Q = Ry(-t) Rz(-f) (t, f: polar and azimuth
+ * angles of D), so Q D = (0, 0, d).  The angular functions rotate as
+ * C_n^m(Q u) = sum_k U_{m k} C_n^k(u) with U_{m k} = d^n_{k m}(t) e^{-i k f},
+ * d^n the Wigner small-d matrix (for an active rotation R, Y(R^-1 u) =
+ * sum_k D_{k m}(R) Y_k(u)).  Writing the source's series in the rotated
+ * frame, sum_m M_m I^m(u) = sum_m Mt_m I^m(Q u), gives
+ *     Mt_m = sum_k conj(U_{m k}) (s_k / s_m) M_k;
+ * along z only I_k^0((0, 0, d)) = k! / d^{k+1} survives, so
+ *     Lt_j^s = (-1)^j sum_{n >= |s|} Mt_n^{-s} (n + j)! / d^{n+j+1};
+ * and sum_s Lt_s conj(R^s(Q t)) = sum_s L_s conj(R^s(t)) gives
+ *     L_k += sum_s Lt_s conj(U_{s k}) (s_k / s_s).
+ * The result equals m2l_add's up to rounding. */
+
+/* Wigner small-d matrix element d^n_{mp m}(b), Wigner's explicit sum. */
+static double wigner_d(int n, int mp, int m, double b)
+{
+    double c = cos(0.5 * b), sn = sin(0.5 * b), acc = 0.0;
+    double pre = sqrt(fact(n + m) * fact(n - m) * fact(n + mp) * fact(n - mp));
+    for (int k = 0; k <= 2 * n; ++k) {
+        int a1 = n + m - k, a3 = n - k - mp, a4 = k - m + mp;
+        if (a1 < 0 || a3 < 0 || a4 < 0) continue;
+        double term = pre / (fact(a1) * fact(k) * fact(a3) * fact(a4)) * pow(c, 2 * n - 2 * k + m - mp) *
+                      pow(sn, 2 * k - m + mp);
+        acc += (a4 & 1) ? -term : term;
+    }
+    return acc;
+}
+
+static double sfac(int n, int m) { return sqrt(fact(n + m) * fact(n - m)); }
+
+static void m2l_rot_add(const cplx *M, const double cB[3], const double cA[3], int p, cplx *L)
+{
+    double D[3] = {cA[0] - cB[0], cA[1] - cB[1], cA[2] - cB[2]};
+    double d = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    double ct = fmax(-1.0, fmin(1.0, D[2] / d));
+    double t = acos(ct), f = (D[0] == 0.0 && D[1] == 0.0) ? 0.0 : atan2(D[1], D[0]);
+    cplx Mt[ORC_MAXP * ORC_MAXP], Lt[ORC_MAXP * ORC_MAXP];
+    for (int n = 0; n < p; ++n)
+        for (int m = -n; m <= n; ++m) {
+            cplx acc = 0.0;
+            for (int k = -n; k <= n; ++k)  /* conj(U_{m k}) = d^n_{k m}(t) e^{+i k f} */
+                acc += wigner_d(n, k, m, t) * cexp(I * (double)k * f) * (sfac(n, k) / sfac(n, m)) * M[HIDX(n, k)];
+            Mt[HIDX(n, m)] = acc;
+        }
+    for (int j = 0; j < p; ++j)
+        for (int s = -j; s <= j; ++s) {
+            cplx acc = 0.0;
+            int as = s < 0 ? -s : s;
+            for (int n = as; n < p; ++n) acc += Mt[HIDX(n, -s)] * (fact(n + j) / pow(d, (double)(n + j + 1)));
+            Lt[HIDX(j, s)] = (j & 1) ? -acc : acc;
+        }
+    for (int j = 0; j < p; ++j)
+        for (int k = -j; k <= j; ++k) {
+            cplx acc = 0.0;
+            for (int s = -j; s <= j; ++s)  /* conj(U_{s k}) = d^j_{k s}(t) e^{+i k f} */
+                acc += Lt[HIDX(j, s)] * wigner_d(j, k, s, t) * (sfac(j, k) / sfac(j, s));
+            L[HIDX(j, k)] += acc * cexp(I * (double)k * f);
+        }
+}
+
 /* L2L (Section II.A): with t = t' + d (d = c_child - c_parent),
  * conj(R_j^s(t)) = sum_{k,l} conj(R_k^l(t')) conj(R_{j-k}^{s-l}(d)), so
  *   L'_k^l += sum_{j>=k,s} L_j^s conj(R_{j-k}^{s-l}(d)).                    */
@@ -318,6 +390,21 @@ void oracle_op_m2l(const double *Min, const double *cB, const double *cA, int p,
     m2l_add(M, cB, cA, p, L);
     from_c(L, p * p, Lout);
 }
+void oracle_op_m2l_rot(const double *Min, const double *cB, const double *cA, int p, double *Lout)
+{
+    cplx M[ORC_MAXP * ORC_MAXP], L[ORC_MAXP * ORC_MAXP] = {0};
+    to_c(Min, p * p, M);
+    m2l_rot_add(M, cB, cA, p, L);
+    from_c(L, p * p, Lout);
+}
+
+/* d^n_{mp m}(b) for all mp, m (row-major, (2n+1)^2 values). */
+void oracle_wigner_d(int n, double b, double *out)
+{
+    for (int mp = -n; mp <= n; ++mp)
+        for (int m = -n; m <= n; ++m) out[(mp + n) * (2 * n + 1) + (m + n)] = wigner_d(n, mp, m, b);
+}
+
 void oracle_op_l2l(const double *Lin, const double *cpar, const double *cch, int p, double *Lout)
 {
     cplx Lp[ORC_MAXP * ORC_MAXP], Lc[ORC_MAXP * ORC_MAXP] = {0};
@@ -1390,6 +1477,7 @@ int oracle_let_fmm(const void *h, const double *q, int p, double *phi, double *f
     const olet *L = (const olet *)h;
     if (!L || !q || p < 1 || p > ORC_MAXP) return 1;
     const int R = L->R, P2 = p * p;
+    if (R < 1) return 1;
     for (int r = 0; r < R; ++r)
         if (L->T[r] && L->T[r]->n_m2l_stored != L->T[r]->n_m2l) return 2;  /* built count_only */
     cplx **M = (cplx **)calloc((size_t)R, sizeof(cplx *));
