@@ -67,7 +67,17 @@ def recorded_traffic(kernel, config, precision):
     return None
 
 
-def roofline_phases(cfg, stats, ph, n, precision):
+def rotation_flops(p):
+    """Flops of one M2L pair by rotation as the kernel computes it: per
+    rotation two products of the degree-n coefficient vectors (complex) with
+    the real (2n+1)^2 table (4 flops per entry), two rotations, and the axial
+    translation (4 flops per (j, s, n) term)."""
+    rot = sum(2 * 4 * (2 * n + 1) ** 2 for n in range(p))
+    axial = sum(4 * (p - abs(s)) for j in range(p) for s in range(-j, j + 1))
+    return 2 * rot + axial
+
+
+def roofline_phases(cfg, stats, ph, n, precision, rotation=False):
     """T* = sum over phases of max(flops / peak, bytes / bandwidth), per phase
     and overall, with the algorithmic work of each phase (not what the
     implementation executes)."""
@@ -84,6 +94,11 @@ def roofline_phases(cfg, stats, ph, n, precision):
         # same-level pairs of sparse tile rows run with the cross-level pairs
         "m2l_same": (2.0 * p2 * p2 * (stats["n_m2l_same"] - stats["n_m2l_sparse"]), mm, 8.0 * p2 * ncell),
         "m2l_cross": (2.0 * p2 * p2 * (stats["n_m2l_cross"] + stats["n_m2l_sparse"]), mm, 0.0),
+    }
+    if rotation:  # every pair in the rotation kernel
+        work["m2l_same"] = (0.0, mm, 0.0)
+        work["m2l_cross"] = (rotation_flops(cfg["p"]) * stats["n_m2l"], PEAK["valu_f64"], 0.0)
+    work |= {
         "p2p": (20.0 * stats["p2p_body_pairs"], va, 32.0 * n),
         "p2m": (5.0 * p2 * n, va, 16.0 * n),
         "l2l": (2.0 * p2 * p2 * ncell, va, 0.0),
@@ -113,6 +128,8 @@ def main():
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
     ap.add_argument("--m2l-sparse", type=int, default=24,
                     help="same-level tile rows with fewer sources per 64 targets run pair by pair (0: never)")
+    ap.add_argument("--m2l-rotation", action="store_true",
+                    help="every M2L pair by rotation (O(p^3) per pair, float64 on the vector units)")
     ap.add_argument("--tight", action="store_true",
                     help="acceptance also by cell radii tight to the bodies (fewer M2L and P2P pairs)")
     ap.add_argument("--let-ranks", default="",
@@ -149,7 +166,7 @@ def main():
     q = torch.as_tensor(q_np, device=dev)
     w = torch.as_tensor(w_np, device=dev)
     prm = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision=args.precision, tight=args.tight,
-                   m2l_sparse=args.m2l_sparse)
+                   m2l_sparse=args.m2l_sparse, m2l_rotation=args.m2l_rotation)
     log(f"bench: {args.config} n={n} p={cfg['p']} theta={cfg['theta']} ncrit={cfg['ncrit']} {args.precision}")
     stream = torch.cuda.current_stream()
     new_plan = lambda timing=False: F.Plan(x, prm, timing=timing, torch_allocator=not args.pool)
@@ -228,14 +245,21 @@ def main():
           "p2p": mean("ms_p2p"), "l2p": mean("ms_l2p"), "evaluate": mean("ms_evaluate"),
           "adjoint": mean("ms_adjoint", stb)}
     stats["p2p_body_pairs"] = body_pairs
-    per_phase, tstar_ms = roofline_phases(cfg, stats, ph, n, args.precision)
+    per_phase, tstar_ms = roofline_phases(cfg, stats, ph, n, args.precision, args.m2l_rotation)
 
     # roofline of the dominant kernel: the same-level M2L (all chunk launches
     # of k_m2l_batched in one evaluation, timed by events on their stream) or P2P
     p2 = cfg["p"] ** 2
     m2l_flops = 2.0 * p2 * p2 * (stats["n_m2l_same"] - stats["n_m2l_sparse"])
     p2p_flops = 20.0 * body_pairs
-    if ph["m2l_same"] >= ph["p2p"]:
+    if args.m2l_rotation:
+        # every M2L pair in the rotation kernel (float64 vector arithmetic)
+        rot_flops = rotation_flops(cfg["p"]) * stats["n_m2l"]
+        achieved = rot_flops / (ph["m2l_cross"] * 1e-3) / 1e12
+        roof = {"kernel": "k_m2l_rot (M2L by rotation, all pairs, one evaluation)", "bound": "alu",
+                "achieved": achieved, "peak": PEAK["valu_f64"], "unit": "TFLOP/s", "frac": achieved / PEAK["valu_f64"],
+                "traffic": None, "launch_ms": ph["m2l_cross"], "flops_per_launch": rot_flops}
+    elif ph["m2l_same"] >= ph["p2p"]:
         peak = PEAK["mfma_f32"] if args.precision == "mixed" else PEAK["mfma_f64"]
         achieved = m2l_flops / (ph["m2l_same"] * 1e-3) / 1e12
         roof = {"kernel": "k_m2l_batched (same-level M2L, all chunk launches of one evaluation)", "bound": "mfma",
@@ -260,7 +284,7 @@ def main():
     fp64_ms, phi64_h, E64_h = None, None, None
     if args.fp64_steps > 0 and args.precision != "fp64":
         prm64 = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision="fp64", tight=args.tight,
-                         m2l_sparse=args.m2l_sparse)
+                         m2l_sparse=args.m2l_sparse, m2l_rotation=args.m2l_rotation)
         times = []
         for k in range(args.fp64_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -358,7 +382,7 @@ def main():
                                f"ncrit={cfg['ncrit']}{', tight radii' if args.tight else ''}; forward (build + "
                                f"evaluate) and backward (plan rebuilt, adjoint of L = sum w phi)", "n": n,
                    "p": cfg["p"], "theta": cfg["theta"], "ncrit": cfg["ncrit"], "precision": args.precision,
-                   "tight": args.tight, "m2l_sparse": args.m2l_sparse},
+                   "tight": args.tight, "m2l_sparse": args.m2l_sparse, "m2l_rotation": args.m2l_rotation},
         "forward_ms": t_fwd,
         "forward_ms_mean": float(np.mean(fwd)),
         "backward_ms": t_bwd,

@@ -38,7 +38,7 @@ class FMMError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int32), ("theta", C.c_double), ("ncrit", C.c_int32), ("precision", C.c_int32),
                 ("coarse_fp64_levels", C.c_int32), ("kahan", C.c_int32), ("tight", C.c_int32),
-                ("m2l_sparse", C.c_int32)]
+                ("m2l_sparse", C.c_int32), ("m2l_rotation", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -218,13 +218,14 @@ class Params:
     tight: bool = False               # acceptance also by cell radii tight to the bodies
     m2l_sparse: int = 24              # same-level tile rows below this many sources per 64
                                       # targets run pair by pair (0: never)
+    m2l_rotation: bool = False        # every M2L pair by rotation, O(p^3), float64 vector units
 
     def to_c(self) -> _Params:
         if self.precision not in PREC:
             raise ValueError("precision must be 'mixed' or 'fp64'")
         return _Params(int(self.p), float(self.theta), int(self.ncrit), PREC[self.precision],
                        int(self.coarse_fp64_levels), 1 if self.kahan else 0, 1 if self.tight else 0,
-                       int(self.m2l_sparse))
+                       int(self.m2l_sparse), 1 if self.m2l_rotation else 0)
 
 
 class Plan:

@@ -356,6 +356,7 @@ void validate_params(const fmm_params &p)
     FMM_CHECK(p.coarse_fp64_levels >= 0 && p.coarse_fp64_levels <= kLevels + 1, FMM_ERR_INVALID,
               "coarse_fp64_levels must be in [0, 22]");
     FMM_CHECK(p.m2l_sparse >= 0 && p.m2l_sparse <= 64, FMM_ERR_INVALID, "m2l_sparse must be in [0, 64]");
+    FMM_CHECK(p.m2l_rotation == 0 || p.m2l_rotation == 1, FMM_ERR_INVALID, "m2l_rotation must be 0 or 1");
 }
 
 // ------------------------------------------------------------ no-alloc scratch
@@ -448,6 +449,7 @@ void fmm_params_default(fmm_params *prm)
     prm->kahan = 1;
     prm->tight = 0;
     prm->m2l_sparse = 24;
+    prm->m2l_rotation = 0;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -484,6 +486,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         P->kahan = pr.kahan ? 1 : 0;
         P->tight = pr.tight ? 1 : 0;
         P->m2l_sparse = pr.m2l_sparse;
+        P->m2l_rotation = pr.m2l_rotation;
         P->dtype = dtype;
         P->al.stream = s;
         if (fmm_plan_arena_.base) {

@@ -177,6 +177,8 @@ struct fmm_plan {
     int ncrit = 64, precision = FMM_PREC_MIXED, cfl = 3, kahan = 1;
     int tight = 0;                   // acceptance also by the cells' own radii (c_rad)
     int m2l_sparse = 0;              // slot rows below this many sources per 64 targets run as pairs
+    int m2l_rotation = 0;            // every M2L pair by the O(p^3) rotation kernel
+    double *rot_x = nullptr;         // its table d^n(pi/2), n < p
     fmm_dtype dtype = FMM_F64;
     int timing = 0;
     fmm::Allocator al;

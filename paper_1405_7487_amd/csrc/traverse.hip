@@ -903,9 +903,11 @@ void traverse(fmm_plan *P, hipStream_t s)
     if (nrow > 0) {
         FMM_CHECK(P->TW == 64 || P->TW == 128, FMM_ERR_DEVICE, "traversal: tile width");
         // (the flag array holds one byte per row: a count of at most 128 fits)
-        if (P->m2l_sparse > 0) spc = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nrow));
+        // (with the rotation kernel every row moves: a threshold above the tile width)
+        const int thr = P->m2l_rotation ? 65 : P->m2l_sparse;
+        if (thr > 0) spc = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nrow));
         k_sparse_count<<<grid_fill(nrow * (P->TW / 4)), 256, 0, s>>>(reinterpret_cast<const int4 *>(P->slots),
-                                                                      P->tile_kflag, nrow, P->TW, P->m2l_sparse, spc);
+                                                                      P->tile_kflag, nrow, P->TW, thr, spc);
         FMM_HIP(hipGetLastError());
     }
     if (spc) {
