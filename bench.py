@@ -126,8 +126,9 @@ def main():
                     help="targets of the single-thread oracle run (-1: an eighth of the sample, 0: skip)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 GPU forward runs (0 = skip)")
     ap.add_argument("--pool", action="store_true", help="library caching pool instead of torch's allocator")
-    ap.add_argument("--m2l-sparse", type=int, default=24,
-                    help="same-level tile rows with fewer sources per 64 targets run pair by pair (0: never)")
+    ap.add_argument("--m2l-sparse", type=int, default=-1,
+                    help="same-level tile rows with fewer sources per 64 targets run pair by pair "
+                         "(0: never; -1: the library's automatic choice)")
     ap.add_argument("--m2l-rotation", action="store_true",
                     help="every M2L pair by rotation (O(p^3) per pair, float64 on the vector units)")
     ap.add_argument("--tight", action="store_true",

@@ -88,8 +88,10 @@ typedef struct {
     int32_t m2l_sparse;         /* same-level M2L runs as dense products over tiles of targets that
                                    share one offset; a tile row (one offset) with fewer than
                                    m2l_sparse sources per 64 targets is evaluated pair by pair with
-                                   the cross-level pairs instead (same sums up to rounding order;
-                                   default 24, 0: never)                                          */
+                                   the cross-level pairs instead (same sums up to rounding order).
+                                   0: never; -1 (default): 24 in plans with at least 1024 tiles,
+                                   else never (small plans pay more to set up the pairs than the
+                                   rows cost)                                                      */
     int32_t m2l_rotation;       /* 1: every M2L pair by rotation, O(p^3) per pair (the O(P^3) end of
                                    the operator cost range, Section III.A): the offset is turned onto
                                    +z, the expansion translated along z and turned back, in float64
@@ -98,7 +100,7 @@ typedef struct {
 } fmm_params;
 
 /* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3,
- * kahan=1, tight=0, m2l_sparse=24, m2l_rotation=0.  P, theta and N_crit are the method parameters of Table I
+ * kahan=1, tight=0, m2l_sparse=-1, m2l_rotation=0.  P, theta and N_crit are the method parameters of Table I
  * (Section III.A); the values are this library's defaults, not the paper's.
  * A NULL prm is ignored. */
 FMM_API void fmm_params_default(fmm_params *prm);

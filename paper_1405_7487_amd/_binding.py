@@ -216,8 +216,9 @@ class Params:
     coarse_fp64_levels: int = 3
     kahan: bool = True
     tight: bool = False               # acceptance also by cell radii tight to the bodies
-    m2l_sparse: int = 24              # same-level tile rows below this many sources per 64
-                                      # targets run pair by pair (0: never)
+    m2l_sparse: int = -1              # same-level tile rows below this many sources per 64
+                                      # targets run pair by pair (0: never; -1: 24 in plans
+                                      # with at least 1024 tiles)
     m2l_rotation: bool = False        # every M2L pair by rotation, O(p^3), float64 vector units
 
     def to_c(self) -> _Params:

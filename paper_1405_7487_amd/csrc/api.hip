@@ -355,7 +355,7 @@ void validate_params(const fmm_params &p)
     FMM_CHECK(p.precision == FMM_PREC_FP64 || p.precision == FMM_PREC_MIXED, FMM_ERR_INVALID, "bad precision");
     FMM_CHECK(p.coarse_fp64_levels >= 0 && p.coarse_fp64_levels <= kLevels + 1, FMM_ERR_INVALID,
               "coarse_fp64_levels must be in [0, 22]");
-    FMM_CHECK(p.m2l_sparse >= 0 && p.m2l_sparse <= 64, FMM_ERR_INVALID, "m2l_sparse must be in [0, 64]");
+    FMM_CHECK(p.m2l_sparse >= -1 && p.m2l_sparse <= 64, FMM_ERR_INVALID, "m2l_sparse must be in [-1, 64]");
     FMM_CHECK(p.m2l_rotation == 0 || p.m2l_rotation == 1, FMM_ERR_INVALID, "m2l_rotation must be 0 or 1");
 }
 
@@ -448,7 +448,7 @@ void fmm_params_default(fmm_params *prm)
     prm->coarse_fp64_levels = 3;
     prm->kahan = 1;
     prm->tight = 0;
-    prm->m2l_sparse = 24;
+    prm->m2l_sparse = -1;
     prm->m2l_rotation = 0;
 }
 

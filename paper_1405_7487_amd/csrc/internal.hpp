@@ -100,13 +100,14 @@ __host__ __device__ constexpr bool m2l_banks_distinct(int G, int RT)
     return true;
 }
 // Elements from one k-group of a stage to the next: SCH rows of P2pad values
-// plus padding.  float32: the smallest pad that spreads the 64 lanes' reads
-// over 64 banks, where one exists (for RT = 6, 8, 16 none does); float64
-// (and those): 64 bytes when RT is odd.
+// plus padding.  float32 with RT odd (fragment reads of single words): the
+// smallest pad that spreads the 64 lanes' reads over 64 banks.  RT even
+// keeps the groups 16-byte aligned (wide fragment reads); float64: 64 bytes
+// when RT is odd.
 __host__ __device__ constexpr int m2l_gst(int RT, int Q, int esz)
 {
     const int base = m2l_sch(RT, Q, esz) * 16 * RT;
-    if (esz == 4)
+    if (esz == 4 && (RT & 1))
         for (int pad = 0; pad < 64; ++pad)
             if (m2l_banks_distinct(base + pad, RT)) return base + pad;
     return base + ((RT & 1) ? 64 / esz : 0);

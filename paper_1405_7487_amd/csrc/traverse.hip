@@ -903,8 +903,10 @@ void traverse(fmm_plan *P, hipStream_t s)
     if (nrow > 0) {
         FMM_CHECK(P->TW == 64 || P->TW == 128, FMM_ERR_DEVICE, "traversal: tile width");
         // (the flag array holds one byte per row: a count of at most 128 fits)
-        // (with the rotation kernel every row moves: a threshold above the tile width)
-        const int thr = P->m2l_rotation ? 65 : P->m2l_sparse;
+        // (with the rotation kernel every row moves: a threshold above the tile
+        // width; the automatic threshold moves rows only in plans with at least
+        // 1024 tiles)
+        const int thr = P->m2l_rotation ? 65 : (P->m2l_sparse >= 0 ? P->m2l_sparse : (tiles >= 1024 ? 24 : 0));
         if (thr > 0) spc = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * nrow));
         k_sparse_count<<<grid_fill(nrow * (P->TW / 4)), 256, 0, s>>>(reinterpret_cast<const int4 *>(P->slots),
                                                                       P->tile_kflag, nrow, P->TW, thr, spc);
