@@ -510,6 +510,14 @@ __global__ __launch_bounds__(64) void k_m2l_cross(const int32_t *ch_tgt, const i
 constexpr int kRotWaves = 4;
 
 __device__ __forceinline__ cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// The lanes of one wave exchange data through LDS: wavefront-scope release
+// and acquire around the wave barrier order the writes before the reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 // i^{-m}
 __device__ __forceinline__ cd ipow_neg(int m)
 {
@@ -546,135 +554,137 @@ __global__ __launch_bounds__(64 * kRotWaves) void k_m2l_rot(const int64_t *off, 
         const int n = (int)sqrtf((float)r + 0.5f), m = r - n * n - n;
         sfc[r] = sqrt(fct[n + m] * fct[n - m]);
     }
+    __syncthreads();
     auto xo = [](int n) { return n * (2 * n - 1) * (2 * n + 1) / 3; };  // X^n's first element
     const double hA = ldexp(S, -lvl[c]);
     cd *v1 = V1[wv], *v2 = V2[wv], *et = ET[wv], *ef = EF[wv];
     double *g = G[wv];
     double are[kOutSlots] = {}, aim[kOutSlots] = {};
-    const int64_t q0 = off[c], nq = off[c + 1] - q0;
-    for (int64_t rd = 0; rd < nq; rd += kRotWaves) {
-        const int64_t q = q0 + rd + wv;
-        const bool has = rd + wv < nq;
-        int b = 0, dl = 0;
-        if (has) {
-            b = src[q];
-            dl = lvl[c] - lvl[b];
-            if (lane == 0) {
-                // e^{i t} = (tz + i rho) / d and e^{i f} = (tx + i ty) / rho come from
-                // the offset itself; their powers and k! / d^{k+1} by recurrence
-                const double tx = (ctr[3 * c] - ctr[3 * b]) / hA, ty = (ctr[3 * c + 1] - ctr[3 * b + 1]) / hA,
-                             tz = (ctr[3 * c + 2] - ctr[3 * b + 2]) / hA;
-                const double rho = sqrt(tx * tx + ty * ty), d = sqrt(rho * rho + tz * tz), id = 1.0 / d;
-                const cd emt = {tz * id, -rho * id};                                   // e^{-i t}
-                const cd eif = rho > 0.0 ? cd{-ty / rho, tx / rho} : cd{0.0, 1.0};   // i e^{i f}
-                cd a = {1.0, 0.0}, e = {1.0, 0.0};
-                double gk = id;
-                for (int k = 0; k < p; ++k) {
-                    et[p - 1 + k] = a;
-                    et[p - 1 - k] = cd{a.re, -a.im};
-                    ef[p - 1 + k] = e;
-                    ef[p - 1 - k] = cd{e.re, -e.im};
-                    a = cmul(a, emt);
-                    e = cmul(e, eif);
+    // Each wave walks its own pairs and its own LDS vectors: between the steps
+    // of a pair only the wave's lanes exchange data, whose LDS accesses run in
+    // order, so a wave barrier (no block barrier) separates them.
+    for (int64_t q = off[c] + wv; q < off[c + 1]; q += kRotWaves) {
+        const int b = src[q];
+        const int dl = lvl[c] - lvl[b];
+        {
+            // e^{i t} = (tz + i rho) / d and e^{i f} = (tx + i ty) / rho come from
+            // the offset itself; lane k raises them to the k-th power by squaring
+            const double tx = (ctr[3 * c] - ctr[3 * b]) / hA, ty = (ctr[3 * c + 1] - ctr[3 * b + 1]) / hA,
+                         tz = (ctr[3 * c + 2] - ctr[3 * b + 2]) / hA;
+            const double rho = sqrt(tx * tx + ty * ty), d = sqrt(rho * rho + tz * tz), id = 1.0 / d;
+            if (lane < p) {
+                cd a = {1.0, 0.0}, e = {1.0, 0.0}, ba = {tz * id, -rho * id};  // e^{-i t}
+                cd be = rho > 0.0 ? cd{-ty / rho, tx / rho} : cd{0.0, 1.0};    // i e^{i f}
+                for (int k = lane; k; k >>= 1) {
+                    if (k & 1) {
+                        a = cmul(a, ba);
+                        e = cmul(e, be);
+                    }
+                    ba = cmul(ba, ba);
+                    be = cmul(be, be);
                 }
-                for (int k = 0; k < 2 * p - 1; ++k) {
-                    g[k] = gk;
-                    gk *= (double)(k + 1) * id;
+                et[p - 1 + lane] = a;
+                et[p - 1 - lane] = cd{a.re, -a.im};
+                ef[p - 1 + lane] = e;
+                ef[p - 1 - lane] = cd{e.re, -e.im};
+            }
+            if (lane < 2 * p - 1) {  // k! / d^{k+1}
+                double pw = id, bb = id;
+                for (int k = lane; k; k >>= 1) {
+                    if (k & 1) pw *= bb;
+                    bb *= bb;
                 }
+                g[lane] = fct[lane] * pw;
             }
         }
-        __syncthreads();
+        wave_sync();
         const TM *mb = M + (int64_t)b * P2pad;
-        if (has)  // v1 = i^k e^{i k f} s_k M_k (source scaled to the target's level)
-            for (int r = lane; r < P2; r += 64) {
-                const int n = (int)sqrtf((float)r + 0.5f), m = r - n * n - n, am = m < 0 ? -m : m;
-                const double sc = ldexp(1.0, n * dl);
-                double re = sc * (double)mb[n * n + (am ? 2 * am - 1 : 0)], im = am ? sc * (double)mb[n * n + 2 * am] : 0.0;
-                if (m < 0) {  // M_n^{-m} = (-1)^m conj(M_n^m)
-                    im = -im;
-                    if (am & 1) { re = -re; im = -im; }
-                }
-                const cd z = cmul(cd{re, im}, ef[m + p - 1]);
-                v1[r] = cd{sfc[r] * z.re, sfc[r] * z.im};
+        for (int r = lane; r < P2; r += 64) {  // v1 = i^k e^{i k f} s_k M_k (source scaled to the target's level)
+            const int n = (int)sqrtf((float)r + 0.5f), m = r - n * n - n, am = m < 0 ? -m : m;
+            const double sc = ldexp(1.0, n * dl);
+            double re = sc * (double)mb[n * n + (am ? 2 * am - 1 : 0)], im = am ? sc * (double)mb[n * n + 2 * am] : 0.0;
+            if (m < 0) {  // M_n^{-m} = (-1)^m conj(M_n^m)
+                im = -im;
+                if (am & 1) { re = -re; im = -im; }
             }
-        __syncthreads();
-        if (has)  // v2_k = e^{-i k t} sum_m X_{k m} v1_m
-            for (int r = lane; r < P2; r += 64) {
-                const int n = (int)sqrtf((float)r + 0.5f), k = r - n * n - n, w = 2 * n + 1;
-                const double *xr = X + xo(n) + (k + n) * w;
-                const cd *vv = v1 + n * n;
-                double sr = 0.0, si = 0.0;
-                for (int m = 0; m < w; ++m) {
-                    sr += xr[m] * vv[m].re;
-                    si += xr[m] * vv[m].im;
-                }
-                v2[r] = cmul(cd{sr, si}, et[k + p - 1]);
+            const cd z = cmul(cd{re, im}, ef[m + p - 1]);
+            v1[r] = cd{sfc[r] * z.re, sfc[r] * z.im};
+        }
+        wave_sync();
+        for (int r = lane; r < P2; r += 64) {  // v2_k = e^{-i k t} sum_m X_{k m} v1_m
+            const int n = (int)sqrtf((float)r + 0.5f), k = r - n * n - n, w = 2 * n + 1;
+            const double *xr = X + xo(n) + (k + n) * w;
+            const cd *vv = v1 + n * n;
+            double sr = 0.0, si = 0.0;
+            for (int m = 0; m < w; ++m) {
+                sr += xr[m] * vv[m].re;
+                si += xr[m] * vv[m].im;
             }
-        __syncthreads();
-        if (has)  // v1_m = Mt_m = i^{-m} / s_m sum_k X_{k m} v2_k
-            for (int r = lane; r < P2; r += 64) {
-                const int n = (int)sqrtf((float)r + 0.5f), m = r - n * n - n, w = 2 * n + 1;
-                const double *xc = X + xo(n) + (m + n);
-                const cd *vv = v2 + n * n;
-                double sr = 0.0, si = 0.0;
-                for (int k = 0; k < w; ++k) {
-                    sr += xc[k * w] * vv[k].re;
-                    si += xc[k * w] * vv[k].im;
-                }
-                const cd z = cmul(cd{sr, si}, ipow_neg(m));
-                const double is = 1.0 / sfc[r];
-                v1[r] = cd{is * z.re, is * z.im};
+            v2[r] = cmul(cd{sr, si}, et[k + p - 1]);
+        }
+        wave_sync();
+        for (int r = lane; r < P2; r += 64) {  // v1_m = Mt_m = i^{-m} / s_m sum_k X_{k m} v2_k
+            const int n = (int)sqrtf((float)r + 0.5f), m = r - n * n - n, w = 2 * n + 1;
+            const double *xc = X + xo(n) + (m + n);
+            const cd *vv = v2 + n * n;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < w; ++k) {
+                sr += xc[k * w] * vv[k].re;
+                si += xc[k * w] * vv[k].im;
             }
-        __syncthreads();
-        if (has)  // v2_s = i^{-s} / s_s Lt_j^s, Lt_j^s = (-1)^j sum_{n >= |s|} Mt_n^{-s} (n + j)! / d^{n+j+1}
-            for (int r = lane; r < P2; r += 64) {
-                const int j = (int)sqrtf((float)r + 0.5f), sO = r - j * j - j, as = sO < 0 ? -sO : sO;
-                double sr = 0.0, si = 0.0;
-                for (int n = as; n < p; ++n) {
-                    const cd mv = v1[n * n + n - sO];
-                    sr += mv.re * g[n + j];
-                    si += mv.im * g[n + j];
-                }
-                const double sg = ((j & 1) ? -1.0 : 1.0) / sfc[r];
-                const cd z = cmul(cd{sr, si}, ipow_neg(sO));
-                v2[r] = cd{sg * z.re, sg * z.im};
+            const cd z = cmul(cd{sr, si}, ipow_neg(m));
+            const double is = 1.0 / sfc[r];
+            v1[r] = cd{is * z.re, is * z.im};
+        }
+        wave_sync();
+        // v2_s = i^{-s} / s_s Lt_j^s, Lt_j^s = (-1)^j sum_{n >= |s|} Mt_n^{-s} (n + j)! / d^{n+j+1}
+        for (int r = lane; r < P2; r += 64) {
+            const int j = (int)sqrtf((float)r + 0.5f), sO = r - j * j - j, as = sO < 0 ? -sO : sO;
+            double sr = 0.0, si = 0.0;
+            for (int n = as; n < p; ++n) {
+                const cd mv = v1[n * n + n - sO];
+                sr += mv.re * g[n + j];
+                si += mv.im * g[n + j];
             }
-        __syncthreads();
-        if (has)  // v1_k = e^{-i k t} sum_s X_{k s} v2_s
-            for (int r = lane; r < P2; r += 64) {
-                const int n = (int)sqrtf((float)r + 0.5f), k = r - n * n - n, w = 2 * n + 1;
-                const double *xr = X + xo(n) + (k + n) * w;
-                const cd *vv = v2 + n * n;
-                double sr = 0.0, si = 0.0;
-                for (int m = 0; m < w; ++m) {
-                    sr += xr[m] * vv[m].re;
-                    si += xr[m] * vv[m].im;
-                }
-                v1[r] = cmul(cd{sr, si}, et[k + p - 1]);
+            const double sg = ((j & 1) ? -1.0 : 1.0) / sfc[r];
+            const cd z = cmul(cd{sr, si}, ipow_neg(sO));
+            v2[r] = cd{sg * z.re, sg * z.im};
+        }
+        wave_sync();
+        for (int r = lane; r < P2; r += 64) {  // v1_k = e^{-i k t} sum_s X_{k s} v2_s
+            const int n = (int)sqrtf((float)r + 0.5f), k = r - n * n - n, w = 2 * n + 1;
+            const double *xr = X + xo(n) + (k + n) * w;
+            const cd *vv = v2 + n * n;
+            double sr = 0.0, si = 0.0;
+            for (int m = 0; m < w; ++m) {
+                sr += xr[m] * vv[m].re;
+                si += xr[m] * vv[m].im;
             }
-        __syncthreads();
-        if (has)  // L_k += e^{i k (f + pi/2)} s_k sum_u X_{u k} v1_u, for k >= 0
-            for (int qq = 0; qq < kOutSlots; ++qq) {
-                const int e = lane + 64 * qq;
-                if (e >= NO) continue;
-                int j = 0;
-                while ((j + 1) * (j + 2) / 2 <= e) ++j;
-                const int k = e - j * (j + 1) / 2, w = 2 * j + 1;
-                const double *xc = X + xo(j) + (k + j);
-                const cd *vv = v1 + j * j;
-                double sr = 0.0, si = 0.0;
-                for (int u = 0; u < w; ++u) {
-                    sr += xc[u * w] * vv[u].re;
-                    si += xc[u * w] * vv[u].im;
-                }
-                const cd z = cmul(cd{sr, si}, ef[k + p - 1]);
-                const double sc = sfc[j * j + j + k];
-                are[qq] += sc * z.re;
-                aim[qq] += sc * z.im;
+            v1[r] = cmul(cd{sr, si}, et[k + p - 1]);
+        }
+        wave_sync();
+        for (int qq = 0; qq < kOutSlots; ++qq) {  // L_k += e^{i k (f + pi/2)} s_k sum_u X_{u k} v1_u, k >= 0
+            const int e = lane + 64 * qq;
+            if (e >= NO) continue;
+            int j = 0;
+            while ((j + 1) * (j + 2) / 2 <= e) ++j;
+            const int k = e - j * (j + 1) / 2, w = 2 * j + 1;
+            const double *xc = X + xo(j) + (k + j);
+            const cd *vv = v1 + j * j;
+            double sr = 0.0, si = 0.0;
+            for (int u = 0; u < w; ++u) {
+                sr += xc[u * w] * vv[u].re;
+                si += xc[u * w] * vv[u].im;
             }
-        __syncthreads();
+            const cd z = cmul(cd{sr, si}, ef[k + p - 1]);
+            const double sc = sfc[j * j + j + k];
+            are[qq] += sc * z.re;
+            aim[qq] += sc * z.im;
+        }
+        wave_sync();
     }
-    // the waves' sums, in wave order (v1 of every wave is free now)
+    __syncthreads();
+    // the waves' sums, in wave order
     for (int qq = 0; qq < kOutSlots; ++qq) {
         const int e = lane + 64 * qq;
         if (e < NO) V1[wv][e] = cd{are[qq], aim[qq]};
