@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmm_hip.so")
-SOURCES = ["sort.hip", "tree.hip", "traverse.hip", "expansions.hip", "m2l.hip", "p2p.hip", "let.hip", "api.hip"]
+SOURCES = ["sort.hip", "tree.hip", "traverse.hip", "expansions.hip", "m2l.hip", "rotation.hip", "p2p.hip", "let.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

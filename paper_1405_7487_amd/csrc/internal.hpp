@@ -326,6 +326,10 @@ void eval_up(fmm_plan *P, const void *q, void *ub, hipStream_t s);
 void eval_m2l(fmm_plan *P, hipStream_t s);
 void eval_down(fmm_plan *P, void *ub, void *phi_s, void *E_s, hipStream_t s);
 // hands back every block an allocator still holds
+// M2L by rotation (rotation.hip): the table d^n(pi/2) and the kernel over
+// the plan's pair list, adding into the local expansions.
+void rotation_prepare(fmm_plan *P, hipStream_t s);
+void rotation_m2l(fmm_plan *P, hipStream_t s);
 void allocator_done(Allocator &a);
 // let.hip: the virtual-rank evaluation behind fmm_let_evaluate
 void let_evaluate(const void *x, const void *q, fmm_dtype dtype, int64_t n, int R, const int64_t *w,
