@@ -5,7 +5,7 @@
   flat inputs;
 * cell / leaf / depth counts of the workloads (seed 0) against an
   independent level-by-level count in numpy (the 2^24-body one runs with
-  the GPU tests, on the GPU box's host cores);
+  the GPU tests, whose host has 16 cores);
 * list counts of the complete uniform trees against lattice enumeration;
 * list invariants: symmetry, exact once-coverage of every ordered body pair,
   the acceptance criterion decided in exact rational arithmetic, no
