@@ -130,6 +130,25 @@ __host__ __device__ constexpr int64_t m2l_tail(int RT, int Q, int esz) { return 
 __host__ __device__ constexpr int m2l_cg(int RT, bool f64) { return f64 ? 1 : (RT <= 4 ? 2 : 1); }
 __host__ __device__ constexpr int m2l_wv(int RT, bool f64) { return 4; }
 
+// Sum of n values p[0], p[stride], ..., in float64, in index order; eight
+// loads are issued before they are added, so a thread keeps eight in flight
+// (the order of the additions, hence the result, is that of a plain loop).
+template <class T>
+__device__ __forceinline__ double strided_sum(const T *p, int64_t n, int64_t stride)
+{
+    double acc = 0.0;
+    int64_t k = 0;
+    for (; k + 8 <= n; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; k < n; ++k) acc += (double)p[k * stride];
+    return acc;
+}
+
 // ---------------------------------------------------------------- memory
 // Device memory of a plan: the caller's callbacks, the library's caching pool,
 // or (for the entry point that allocates nothing) blocks carved from a fixed

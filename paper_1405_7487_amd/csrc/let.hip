@@ -446,8 +446,7 @@ __global__ __launch_bounds__(256) void k_m2l_remote_reduce(const int32_t *tg, co
     const int64_t k = t / P2;
     const int r = (int)(t % P2);
     if (k >= ntg) return;
-    double acc = 0.0;
-    for (int64_t it = tg_i[k]; it < tg_i[k + 1]; ++it) acc += part[it * P2pad + r];
+    const double acc = strided_sum(part + tg_i[k] * P2pad + r, tg_i[k + 1] - tg_i[k], (int64_t)P2pad);
     TM *dst = LA + (int64_t)tg[k] * P2pad + r;
     *dst = (TM)((double)*dst + acc);
 }

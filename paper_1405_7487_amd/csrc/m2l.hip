@@ -503,8 +503,7 @@ __global__ __launch_bounds__(256) void k_gx_reduce(int64_t nc, const int64_t *co
     if (c >= nc) return;
     const int64_t a = cofs[c], b = cofs[c + 1];
     if (a == b) return;
-    double acc = 0.0;
-    for (int64_t k = a; k < b; ++k) acc += part[k * P2pad + r];
+    const double acc = strided_sum(part + a * P2pad + r, b - a, (int64_t)P2pad);
     TM *dst = L + c * P2pad + r;
     *dst = (TM)((double)*dst + acc);
 }
@@ -755,8 +754,8 @@ __global__ __launch_bounds__(256) void k_x_reduce(const int64_t *s_off, const in
     const int64_t seg = t / P2pad;
     const int row = (int)(t % P2pad);
     if (seg >= nseg) return;
-    double acc = 0.0;
-    for (int64_t k = s_off[seg]; k < s_off[seg + 1]; ++k) acc += (double)buf[(k - pos0) * P2pad + row];
+    const int64_t k0 = s_off[seg];
+    const double acc = strided_sum(buf + (k0 - pos0) * P2pad + row, s_off[seg + 1] - k0, (int64_t)P2pad);
     T *dst = L + (int64_t)s_tgt[seg] * P2pad + row;
     *dst = (T)((double)*dst + acc);
 }
