@@ -54,6 +54,8 @@ def lib():
                                          _i32p, _i32p, _i32p, _dp, _i32p, _i32p]
         L.oracle_fmm_at.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_int64, _i64p, _dp, _dp]
         L.oracle_fmm_at.restype = C.c_int
+        L.oracle_near_mutual.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.oracle_near_mutual.restype = C.c_int
         L.oracle_let_new.argtypes = [C.c_int64, _dp, _i64p, C.c_int32, C.c_int32, C.c_double, C.c_int]
         L.oracle_let_new.restype = C.c_void_p
         L.oracle_let_free.argtypes = [C.c_void_p]
@@ -289,6 +291,18 @@ class Tree:
         rc = lib().oracle_fmm_at(self._h, _d(xp), _d(q), int(p), nt, tp, _d(phi), _d(E))
         if rc:
             raise ValueError(f"oracle_fmm failed ({rc})")
+        return phi, E
+
+    def near_mutual(self, q):
+        """Near field (the P2P part alone) of every body, each unordered body
+        pair of the P2P lists evaluated once with both bodies updated
+        (mutual interactions, Section II.C).  Input order."""
+        q = _f64(q)
+        phi = np.zeros(self.n)
+        E = np.zeros((self.n, 3))
+        rc = lib().oracle_near_mutual(self._h, _d(self.x), _d(q), _d(phi), _d(E))
+        if rc:
+            raise ValueError(f"oracle_near_mutual failed ({rc})")
         return phi, E
 
 

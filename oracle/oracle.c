@@ -27,6 +27,9 @@
  *   M2L by rotation the O(P^3) form of the same operator (Section III.A):
  *                  rotate D onto +z with Wigner's explicit d-matrices,
  *                  translate along z, rotate back
+ *   mutual P2P     the near field with every unordered body pair of the
+ *                  P2P lists evaluated once and both bodies updated (mutual
+ *                  interactions, listed among the features in Section II.C)
  *
  * Every target output is accumulated by one thread in a fixed order, so the
  * result is bit-identical for any OpenMP thread count.
@@ -40,7 +43,9 @@
  * invariants and lattice counts; the a priori error bound of the whole FMM;
  * energy symmetry; scaling and axis-permutation invariance; frozen-tree
  * finite differences; Wigner matrices against closed forms, orthogonality
- * and the rotation of the harmonics; rotation M2L against the dense M2L.
+ * and the rotation of the harmonics; rotation M2L against the dense M2L;
+ * the mutual near field against a numpy sum over the exported P2P list, the
+ * direct sum and Newton's third law.
  * No function here is "parity unpinned".
  */
 #include <complex.h>
@@ -1050,6 +1055,71 @@ int oracle_fmm_at(const void *h, const double *xpos, const double *q, int p,
     free(M);
     free(L);
     return bad ? 3 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mutual interactions (Section II.C lists them among the features of the    */
+/* code the paper builds on): every unordered pair of bodies in the near     */
+/* field is evaluated once and both bodies are updated.                      */
+/* ------------------------------------------------------------------------ */
+
+/* Near field (P2P only, no expansions) of every body, input order.  The
+ * leaves are taken in ascending order; for leaf A each source B >= A of its
+ * P2P list (sources ascending) is visited once: B == A gives the pairs
+ * i < j of A's bodies, B > A every pair (i in A, j in B).  One distance, one
+ * reciprocal and one cube serve both updates: body i gains q_j / r and
+ * q_j (x_i - x_j) / r^3, body j gains q_i / r and q_i (x_j - x_i) / r^3.
+ * Coincident bodies are skipped, as in the one-sided sums.  Serial: the
+ * updates of B's bodies would race across leaves.  Needs a tree built for
+ * every target, at the coordinates x (input order) it was built from.     */
+int oracle_near_mutual(const void *h, const double *x, const double *q, double *phi, double *field)
+{
+    const otree *t = (const otree *)h;
+    if (!t || !x || !q || !phi || !field) return 1;
+    const int64_t n = t->n;
+    for (int64_t c = 0; c < t->ncell; ++c)
+        if (t->nch[c] == 0 && !t->need[c]) return 3;
+    double *xs = (double *)malloc((size_t)n * 3 * sizeof(double) + 1);
+    double *acc = (double *)calloc((size_t)n * 4 + 1, sizeof(double)); /* phi, Ex, Ey, Ez per sorted body */
+    if (!xs || !acc) return (free(xs), free(acc), 2);
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) xs[3 * i + d] = x[3 * (int64_t)t->perm[i] + d];
+    for (int64_t a = 0; a < t->ncell; ++a) {
+        if (t->nch[a] != 0) continue;
+        for (int64_t k = t->p2p_off[a]; k < t->p2p_off[a + 1]; ++k) {
+            const int64_t b = t->p2p_src[k];
+            if (b < a) continue;
+            for (int32_t i = t->beg[a]; i < t->end[a]; ++i) {
+                const int32_t j0 = b == a ? i + 1 : t->beg[b];
+                for (int32_t j = j0; j < t->end[b]; ++j) {
+                    const double dx = xs[3 * (int64_t)i] - xs[3 * (int64_t)j];
+                    const double dy = xs[3 * (int64_t)i + 1] - xs[3 * (int64_t)j + 1];
+                    const double dz = xs[3 * (int64_t)i + 2] - xs[3 * (int64_t)j + 2];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 == 0.0) continue;
+                    const double r = sqrt(r2);
+                    const double qi = q[t->perm[i]], qj = q[t->perm[j]];
+                    const double ri = 1.0 / r, ri3 = ri / r2;
+                    acc[4 * (int64_t)i] += qj * ri;
+                    acc[4 * (int64_t)i + 1] += qj * ri3 * dx;
+                    acc[4 * (int64_t)i + 2] += qj * ri3 * dy;
+                    acc[4 * (int64_t)i + 3] += qj * ri3 * dz;
+                    acc[4 * (int64_t)j] += qi * ri;
+                    acc[4 * (int64_t)j + 1] -= qi * ri3 * dx;
+                    acc[4 * (int64_t)j + 2] -= qi * ri3 * dy;
+                    acc[4 * (int64_t)j + 3] -= qi * ri3 * dz;
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t o = t->perm[i];
+        phi[o] = acc[4 * i];
+        for (int d = 0; d < 3; ++d) field[3 * o + d] = acc[4 * i + 1 + d];
+    }
+    free(xs);
+    free(acc);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
