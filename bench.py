@@ -131,6 +131,8 @@ def main():
                          "(0: never; -1: the library's automatic choice)")
     ap.add_argument("--m2l-rotation", action="store_true",
                     help="every M2L pair by rotation (O(p^3) per pair, float64 on the vector units)")
+    ap.add_argument("--mutual", action="store_true",
+                    help="mutual P2P: each unordered pair of different leaves once, both leaves updated")
     ap.add_argument("--tight", action="store_true",
                     help="acceptance also by cell radii tight to the bodies (fewer M2L and P2P pairs)")
     ap.add_argument("--let-ranks", default="",
@@ -167,7 +169,7 @@ def main():
     q = torch.as_tensor(q_np, device=dev)
     w = torch.as_tensor(w_np, device=dev)
     prm = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision=args.precision, tight=args.tight,
-                   m2l_sparse=args.m2l_sparse, m2l_rotation=args.m2l_rotation)
+                   m2l_sparse=args.m2l_sparse, m2l_rotation=args.m2l_rotation, mutual=args.mutual)
     log(f"bench: {args.config} n={n} p={cfg['p']} theta={cfg['theta']} ncrit={cfg['ncrit']} {args.precision}")
     stream = torch.cuda.current_stream()
     new_plan = lambda timing=False: F.Plan(x, prm, timing=timing, torch_allocator=not args.pool)
@@ -285,7 +287,7 @@ def main():
     fp64_ms, phi64_h, E64_h = None, None, None
     if args.fp64_steps > 0 and args.precision != "fp64":
         prm64 = F.Params(p=cfg["p"], theta=cfg["theta"], ncrit=cfg["ncrit"], precision="fp64", tight=args.tight,
-                         m2l_sparse=args.m2l_sparse, m2l_rotation=args.m2l_rotation)
+                         m2l_sparse=args.m2l_sparse, m2l_rotation=args.m2l_rotation, mutual=args.mutual)
         times = []
         for k in range(args.fp64_steps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -383,7 +385,8 @@ def main():
                                f"ncrit={cfg['ncrit']}{', tight radii' if args.tight else ''}; forward (build + "
                                f"evaluate) and backward (plan rebuilt, adjoint of L = sum w phi)", "n": n,
                    "p": cfg["p"], "theta": cfg["theta"], "ncrit": cfg["ncrit"], "precision": args.precision,
-                   "tight": args.tight, "m2l_sparse": args.m2l_sparse, "m2l_rotation": args.m2l_rotation},
+                   "tight": args.tight, "m2l_sparse": args.m2l_sparse, "m2l_rotation": args.m2l_rotation,
+                   "mutual": args.mutual},
         "forward_ms": t_fwd,
         "forward_ms_mean": float(np.mean(fwd)),
         "backward_ms": t_bwd,
@@ -397,7 +400,7 @@ def main():
         "phases_ms": ph,
         "counts": {k: stats[k] for k in ("ncell", "nleaf", "depth", "n_m2l", "n_m2l_same", "n_m2l_cross", "n_p2p",
                                          "p2p_body_pairs", "m2l_stencil", "m2l_offsets", "m2l_slots", "m2l_rows",
-                                         "n_m2l_sparse", "device_bytes")},
+                                         "n_m2l_sparse", "p2p_mutual_pairs", "device_bytes")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

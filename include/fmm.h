@@ -97,10 +97,18 @@ typedef struct {
                                    +z, the expansion translated along z and turned back, in float64
                                    on the vector units; 0 (default): dense operators, O(p^4) on the
                                    matrix cores                                                    */
+    int32_t mutual;             /* 1: mutual P2P (Section II.C lists mutual interactions among the
+                                   features of the underlying code): each unordered pair of
+                                   different leaves is evaluated once and both leaves gain their
+                                   sums, a leaf's own pairs one-sided; the sums of every (pair,
+                                   body) are kept and added per body in a fixed order, so results
+                                   stay bit-reproducible; needs 16 B (32 B in FP64) per source body
+                                   of every such pair in the plan.  0 (default): every list entry
+                                   one-sided                                                       */
 } fmm_params;
 
 /* Fills defaults: p=8, theta=0.4, ncrit=64, MIXED, coarse_fp64_levels=3,
- * kahan=1, tight=0, m2l_sparse=-1, m2l_rotation=0.  P, theta and N_crit are the method parameters of Table I
+ * kahan=1, tight=0, m2l_sparse=-1, m2l_rotation=0, mutual=0.  P, theta and N_crit are the method parameters of Table I
  * (Section III.A); the values are this library's defaults, not the paper's.
  * A NULL prm is ignored. */
 FMM_API void fmm_params_default(fmm_params *prm);
@@ -149,6 +157,7 @@ typedef struct {
     int64_t n_m2l_sparse;       /* same-level pairs evaluated pair by pair (fmm_params.m2l_sparse) */
     int64_t m2l_rows;           /* (tile, offset) rows the batched M2L multiplies: m2l_rows x the
                                    tile width slots, of which n_m2l_same - n_m2l_sparse hold a pair */
+    int64_t p2p_mutual_pairs;   /* unordered leaf pairs evaluated once for both leaves (mutual) */
 } fmm_stats;
 
 /* Host buffers for fmm_export_tree; any pointer may be NULL.  Lists are

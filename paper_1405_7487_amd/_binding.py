@@ -38,7 +38,7 @@ class FMMError(RuntimeError):
 class _Params(C.Structure):
     _fields_ = [("p", C.c_int32), ("theta", C.c_double), ("ncrit", C.c_int32), ("precision", C.c_int32),
                 ("coarse_fp64_levels", C.c_int32), ("kahan", C.c_int32), ("tight", C.c_int32),
-                ("m2l_sparse", C.c_int32), ("m2l_rotation", C.c_int32)]
+                ("m2l_sparse", C.c_int32), ("m2l_rotation", C.c_int32), ("mutual", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -60,7 +60,8 @@ class _Stats(C.Structure):
                 ("ms_l2p", C.c_double), ("ms_p2p", C.c_double), ("ms_evaluate", C.c_double),
                 ("ms_adjoint", C.c_double), ("ms_m2l_cross", C.c_double),
                 ("m2l_cross_keys", C.c_int64), ("m2l_cross_batched", C.c_int64),
-                ("p2p_cut_leaves", C.c_int64), ("n_m2l_sparse", C.c_int64), ("m2l_rows", C.c_int64)]
+                ("p2p_cut_leaves", C.c_int64), ("n_m2l_sparse", C.c_int64), ("m2l_rows", C.c_int64),
+                ("p2p_mutual_pairs", C.c_int64)]
 
 
 class _LetStats(C.Structure):
@@ -220,13 +221,14 @@ class Params:
                                       # targets run pair by pair (0: never; -1: 24 in plans
                                       # with at least 1024 tiles)
     m2l_rotation: bool = False        # every M2L pair by rotation, O(p^3), float64 vector units
+    mutual: bool = False              # P2P: each unordered leaf pair once, both leaves updated
 
     def to_c(self) -> _Params:
         if self.precision not in PREC:
             raise ValueError("precision must be 'mixed' or 'fp64'")
         return _Params(int(self.p), float(self.theta), int(self.ncrit), PREC[self.precision],
                        int(self.coarse_fp64_levels), 1 if self.kahan else 0, 1 if self.tight else 0,
-                       int(self.m2l_sparse), 1 if self.m2l_rotation else 0)
+                       int(self.m2l_sparse), 1 if self.m2l_rotation else 0, 1 if self.mutual else 0)
 
 
 class Plan:

@@ -357,6 +357,7 @@ void validate_params(const fmm_params &p)
               "coarse_fp64_levels must be in [0, 22]");
     FMM_CHECK(p.m2l_sparse >= -1 && p.m2l_sparse <= 64, FMM_ERR_INVALID, "m2l_sparse must be in [-1, 64]");
     FMM_CHECK(p.m2l_rotation == 0 || p.m2l_rotation == 1, FMM_ERR_INVALID, "m2l_rotation must be 0 or 1");
+    FMM_CHECK(p.mutual == 0 || p.mutual == 1, FMM_ERR_INVALID, "mutual must be 0 or 1");
 }
 
 // ------------------------------------------------------------ no-alloc scratch
@@ -450,6 +451,7 @@ void fmm_params_default(fmm_params *prm)
     prm->tight = 0;
     prm->m2l_sparse = -1;
     prm->m2l_rotation = 0;
+    prm->mutual = 0;
 }
 
 const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -487,6 +489,7 @@ fmm_status fmm_build(const void *x, fmm_dtype dtype, int64_t n, const fmm_params
         P->tight = pr.tight ? 1 : 0;
         P->m2l_sparse = pr.m2l_sparse;
         P->m2l_rotation = pr.m2l_rotation;
+        P->mutual = pr.mutual;
         P->dtype = dtype;
         P->al.stream = s;
         if (fmm_plan_arena_.base) {
@@ -779,6 +782,7 @@ fmm_status fmm_plan_stats(const fmm_plan *Pc, fmm_stats *out)
         st.m2l_cross_batched = P->nxb;
         st.p2p_cut_leaves = P->p2p_ncut;
         st.n_m2l_sparse = P->n_m2l_sparse;
+        st.p2p_mutual_pairs = P->mu_nup;
         st.m2l_rows = P->m2l_rows;
         st.device_bytes = P->bytes_held;
         {

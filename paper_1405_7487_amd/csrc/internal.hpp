@@ -198,6 +198,7 @@ struct fmm_plan {
     int tight = 0;                   // acceptance also by the cells' own radii (c_rad)
     int m2l_sparse = 0;              // slot rows below this many sources per 64 targets run as pairs
     int m2l_rotation = 0;            // every M2L pair by the O(p^3) rotation kernel
+    int mutual = 0;                  // P2P: each unordered leaf pair once, both leaves updated
     double *rot_x = nullptr;         // its table d^n(pi/2), n < p
     fmm_dtype dtype = FMM_F64;
     int timing = 0;
@@ -242,6 +243,19 @@ struct fmm_plan {
     int32_t *p2p_cl_leaf = nullptr, *p2p_cl_n = nullptr;   // cut leaves, their item counts
     int64_t *p2p_cl_part = nullptr;  // first partial slot of each cut leaf
     void *p2p_part = nullptr;        // [4 npart] partial phi, then partial E (3 per slot)
+    // mutual P2P: the upper entries (source > target) of every leaf's list in
+    // list order, the first slot of each entry's source-side sums, the entries
+    // ordered by source, and work items over the upper entries
+    int64_t mu_nup = 0, mu_nitem = 0, mu_nslot = 0, mu_nabody = 0;
+    int32_t *mu_src = nullptr;       // [nup] source leaf of each upper entry
+    int64_t *mu_pb = nullptr;        // [nup] first source-side slot of each upper entry
+    uint64_t *mu_tkey = nullptr;     // [nup] sources ascending (stable: entries ascending within one source)
+    int32_t *mu_tval = nullptr;      // [nup] the upper entry of each
+    int32_t *mu_it_leaf = nullptr;   // [nitem] target leaf
+    int64_t *mu_it_u = nullptr;      // [4 nitem] first entry, end of the touching run, end, first target-side slot
+    int64_t *mu_li = nullptr;        // [nleaf + 1] first item of each leaf (leaf order)
+    void *mu_bufA = nullptr;         // [nabody] target-side sums per item (phi, E) as 4-vectors
+    void *mu_bufB = nullptr;         // [nslot] source-side sums per (upper entry, source body)
     int64_t *m2lx_off = nullptr; int32_t *m2lx_src = nullptr;  // cross-level M2L
     // batched same-level M2L
     int K = 0, nops = 0, R = 0;      // stencil size per class, #operators, offset radius

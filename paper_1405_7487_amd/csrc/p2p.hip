@@ -487,6 +487,429 @@ __global__ void k_items_totals(const int64_t *sc, int64_t m, int64_t *tot)
     }
 }
 
+// ---------------------------------------------------------------- mutual P2P
+// Mutual interactions (listed among the features in Section II.C): each
+// unordered pair of different leaves (A, B), A < B, is evaluated once and both
+// leaves gain their sums; a leaf's own pairs stay one-sided (k_p2p with an
+// empty list).  One wave per work item (a leaf A and a run of its upper
+// entries, the list entries with source B > A).  The sources of the run are
+// staged 64 at a time as four chunks of 16; the wave's four rows of 16 lanes
+// each pair up to 16 of A's bodies (one per lane, kept in registers) with one
+// chunk.  In 16 steps lane i meets every source of its chunk once: the
+// source-side sums travel one lane along the row per step (a DPP rotation
+// within the row), so after the 16 steps every source's sum is back on the
+// lane it started from, complete over the row's targets, with no atomics and
+// no reduction across lanes.  Rows that hold different target chunks of A
+// against the same source chunk add their sums in a fixed order (a lane
+// exchange across rows).  The source-side sums of every (upper entry, source
+// body) go to their own slot, the target-side sums of every item to theirs,
+// and k_mu_reduce adds them per body in a fixed order: the leaf's own pairs,
+// its items in order, then its lower entries ordered by their upper twin.
+constexpr int kMuBatch = 64;  // sources staged per batch: four chunks of 16
+
+__device__ __forceinline__ int row_ror1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, false); }
+__device__ __forceinline__ float row_ror1(float v) { return __builtin_bit_cast(float, row_ror1_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double row_ror1(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)row_ror1_i((int)(unsigned)u), hi = (unsigned)row_ror1_i((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <class T, class V4>
+__device__ __forceinline__ V4 near_dummy()
+{
+    V4 v;
+    v.x = (T)-1e15;
+    v.y = (T)-1e15;
+    v.z = (T)-1e15;
+    v.w = (T)0;
+    return v;
+}
+
+// Stages the next (up to) kMuBatch sources of upper entries [k, k1) of leaf
+// A (entry k already consumed up to body o) into this lane's v (and w, the
+// residual, with COMP), shifted into A's frame exactly as list_pass does;
+// advances (k, o) and returns the number staged.  Slots past it hold
+// zero-charge dummies.
+template <class T, class V4, bool COMP>
+__device__ int mu_gather(GatherLds<T> *gs, int A, int64_t &k, int64_t k1, int32_t &o, const int32_t *usrc,
+                         const int32_t *beg, const int32_t *end, const double *ctr, const V4 *ub, const V4 *ul, V4 &v,
+                         V4 &w)
+{
+    const int lane = threadIdx.x;
+    const double cax = ctr[3 * A], cay = ctr[3 * A + 1], caz = ctr[3 * A + 2];
+    const int64_t kk = k + lane;
+    const bool in = kk < k1;
+    const int b = in ? usrc[kk] : A;
+    const int32_t skip = lane == 0 ? o : 0;
+    const int32_t sz = in ? end[b] - beg[b] - skip : 0;
+    int32_t pre = sz;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t t = __shfl_up(pre, d, 64);
+        if (lane >= d) pre += t;
+    }
+    const int staged = min(__shfl(pre, 63, 64), kMuBatch);
+    gs->incl[lane] = pre;
+    gs->excl[lane] = pre - sz;
+    gs->base[lane] = beg[b] + skip;
+    const double shx = ctr[3 * b] - cax, shy = ctr[3 * b + 1] - cay, shz = ctr[3 * b + 2] - caz;
+    gs->sh[lane][0] = (T)shx;
+    gs->sh[lane][1] = (T)shy;
+    gs->sh[lane][2] = (T)shz;
+    if (COMP) {
+        gs->sl[lane][0] = (T)(shx - (double)(T)shx);
+        gs->sl[lane][1] = (T)(shy - (double)(T)shy);
+        gs->sl[lane][2] = (T)(shz - (double)(T)shz);
+    }
+    __syncthreads();
+    int e = 0;  // the entry of slot `lane`: the first whose inclusive prefix exceeds it
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1)
+        if (gs->incl[e + step - 1] <= lane) e += step;
+    if (lane < staged) {
+        const int64_t j = gs->base[e] + (lane - gs->excl[e]);
+        v = ub[j];
+        if (COMP) {
+            const V4 r = ul[j];
+            const T hx = v.x + gs->sh[e][0], hy = v.y + gs->sh[e][1], hz = v.z + gs->sh[e][2];
+            const T bx = hx - v.x, by = hy - v.y, bz = hz - v.z;
+            w.x = ((v.x - (hx - bx)) + (gs->sh[e][0] - bx)) + (r.x + gs->sl[e][0]);
+            w.y = ((v.y - (hy - by)) + (gs->sh[e][1] - by)) + (r.y + gs->sl[e][1]);
+            w.z = ((v.z - (hz - bz)) + (gs->sh[e][2] - bz)) + (r.z + gs->sl[e][2]);
+            w.w = (T)0;
+            v.x = hx;
+            v.y = hy;
+            v.z = hz;
+        } else {
+            v.x += gs->sh[e][0];
+            v.y += gs->sh[e][1];
+            v.z += gs->sh[e][2];
+        }
+    } else {
+        v = far_dummy<T, V4>();
+        w = V4{};
+    }
+    const int nf = __popcll(__ballot(pre <= staged));
+    if (nf == 64) {
+        k += 64;
+        o = 0;
+    } else {
+        const int32_t consumed = staged - __shfl(pre - sz, nf, 64);
+        o = (nf == 0 ? o : 0) + consumed;
+        k += nf;
+    }
+    return staged;
+}
+
+// One staged batch against this lane's target u (residual ut with COMP).
+// nac target chunks of 16 (1, 2 or 4) share the four rows: row r holds target
+// chunk r % nac and, in round rd, source chunk rd (4 / nac) + r / nac.
+// dst: the source-side slots of the batch's first source; add: accumulate
+// into them (a later target chunk of a leaf with more than 64 bodies).
+template <class T, class V4, bool COMP>
+__device__ __forceinline__ void mu_batch(const V4 *cur, const V4 *curw, int staged, int nac, int row, int i,
+                                         int delta, const V4 &u, const V4 &ut, Acc<T> &pa, V4 *dst, bool add)
+{
+    const int spr = 4 / nac;
+    for (int rd = 0; rd < nac; ++rd) {
+        const int sc = rd * spr + row / nac;
+        const V4 *cs = cur + sc * 16;
+        const V4 *cw = curw + sc * 16;
+        Acc<T> b{0, 0, 0, 0};
+#pragma unroll 4
+        for (int t = 0; t < 16; ++t) {
+            const int j = (i + t * delta) & 15;  // the source whose sum this lane holds now
+            const V4 v = cs[j];
+            T dx = u.x - v.x, dy = u.y - v.y, dz = u.z - v.z;
+            if (COMP) {
+                const V4 w = cw[j];
+                dx += ut.x - w.x;
+                dy += ut.y - w.y;
+                dz += ut.z - w.z;
+            }
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            T ri = rsqrt_t<T>(r2);
+            if (COMP) ri = r2 > (T)0 ? ri : (T)0;
+            const T ri2 = ri * ri;
+            const T qs = v.w * ri, qt = u.w * ri;
+            const T fs = qs * ri2, ft = qt * ri2;
+            pa.p += qs;
+            pa.x += fs * dx;
+            pa.y += fs * dy;
+            pa.z += fs * dz;
+            b.p += qt;
+            b.x -= ft * dx;
+            b.y -= ft * dy;
+            b.z -= ft * dz;
+            b.p = row_ror1(b.p);
+            b.x = row_ror1(b.x);
+            b.y = row_ror1(b.y);
+            b.z = row_ror1(b.z);
+        }
+        if (nac >= 2) {
+            b.p += __shfl_xor(b.p, 16, 64);
+            b.x += __shfl_xor(b.x, 16, 64);
+            b.y += __shfl_xor(b.y, 16, 64);
+            b.z += __shfl_xor(b.z, 16, 64);
+        }
+        if (nac == 4) {
+            b.p += __shfl_xor(b.p, 32, 64);
+            b.x += __shfl_xor(b.x, 32, 64);
+            b.y += __shfl_xor(b.y, 32, 64);
+            b.z += __shfl_xor(b.z, 32, 64);
+        }
+        const int slot = sc * 16 + i;
+        if (row % nac == 0 && slot < staged) {
+            V4 o;
+            o.x = b.p;
+            o.y = b.x;
+            o.z = b.y;
+            o.w = b.z;
+            if (add) {
+                const V4 q = dst[slot];
+                o.x += q.x;
+                o.y += q.y;
+                o.z += q.z;
+                o.w += q.w;
+            }
+            dst[slot] = o;
+        }
+    }
+}
+
+// Upper entries [k, k1) of leaf A as one stream, batch by batch (the loads of
+// batch i + 1 in flight while batch i is multiplied).  Source-side slots of
+// the stream start at dst.
+template <class T, class V4, bool KAHAN, bool COMP>
+__device__ void mu_pass(V4 *sb, GatherLds<T> *gs, int A, int64_t k, int64_t k1, const int32_t *usrc,
+                        const int32_t *beg, const int32_t *end, const double *ctr, const V4 *ub, const V4 *ul, int nac,
+                        int row, int i, int delta, const V4 &u, const V4 &ut, Acc<T> &s, Acc<T> &c, V4 *dst, bool add)
+{
+    const int lane = threadIdx.x;
+    int32_t o = 0;
+    V4 v, w;
+    int st_next = k < k1 ? mu_gather<T, V4, COMP>(gs, A, k, k1, o, usrc, beg, end, ctr, ub, ul, v, w) : 0;
+    int64_t pos = 0;
+    int buf = 0;
+    while (st_next > 0) {
+        V4 *cur = sb + buf * 2 * kMuBatch;
+        cur[lane] = v;
+        if (COMP) cur[kMuBatch + lane] = w;
+        const int st_cur = st_next;
+        __syncthreads();
+        st_next = k < k1 ? mu_gather<T, V4, COMP>(gs, A, k, k1, o, usrc, beg, end, ctr, ub, ul, v, w) : 0;
+        Acc<T> pa{0, 0, 0, 0};
+        mu_batch<T, V4, COMP>(cur, cur + kMuBatch, st_cur, nac, row, i, delta, u, ut, pa, dst + pos, add);
+        fold_into<T, KAHAN>(s, c, pa);
+        pos += st_cur;
+        buf ^= 1;
+    }
+    __syncthreads();
+}
+
+// it_u: [4 nitem] = first upper entry, end of its touching run, end, first
+// target-side slot.
+template <class T, class V4, bool KAHAN>
+__global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *it_leaf, const int64_t *it_u, int64_t nitem,
+                                                   const int32_t *usrc, const int64_t *pb, const int32_t *beg,
+                                                   const int32_t *end, const double *ctr, const V4 *ub, const V4 *ul,
+                                                   V4 *bufA, V4 *bufB)
+{
+    __shared__ V4 sb[4 * kMuBatch];
+    __shared__ GatherLds<T> gs;
+    const int64_t item = blockIdx.x;
+    const int A = it_leaf[item];
+    const int64_t u0 = it_u[item], un = it_u[nitem + item], u1 = it_u[2 * nitem + item], a0 = it_u[3 * nitem + item];
+    const int lane = threadIdx.x, row = lane >> 4, i = lane & 15;
+    // direction of the row rotation: after one step lane i holds the sum that
+    // was on lane i + delta (mod 16)
+    const int delta = (row_ror1_i(i) - i) & 15;
+    const int32_t tb = beg[A], nt = end[A] - tb;
+    for (int base = 0; base < nt; base += 64) {
+        const int cnt = min(64, nt - base);
+        const int nac = cnt <= 16 ? 1 : (cnt <= 32 ? 2 : 4);
+        const int ti = (row % nac) * 16 + i;
+        const bool valid = ti < cnt;
+        const V4 u = valid ? ub[tb + base + ti] : near_dummy<T, V4>();
+        const V4 ut = (ul && valid) ? ul[tb + base + ti] : V4{};
+        Acc<T> s{0, 0, 0, 0}, c{0, 0, 0, 0};
+        int64_t k0 = u0;
+        if (ul && un > u0) {
+            mu_pass<T, V4, KAHAN, true>(sb, &gs, A, u0, un, usrc, beg, end, ctr, ub, ul, nac, row, i, delta, u, ut, s,
+                                        c, bufB + pb[u0], base > 0);
+            k0 = un;
+        }
+        if (u1 > k0)
+            mu_pass<T, V4, KAHAN, false>(sb, &gs, A, k0, u1, usrc, beg, end, ctr, ub, ul, nac, row, i, delta, u, ut, s,
+                                         c, bufB + pb[k0], base > 0);
+        if (KAHAN) {
+            s.p -= c.p; s.x -= c.x; s.y -= c.y; s.z -= c.z;
+        }
+        // rows that hold the same targets: a fixed-order sum
+        if (nac == 1) {
+            s.p += __shfl_xor(s.p, 16, 64);
+            s.x += __shfl_xor(s.x, 16, 64);
+            s.y += __shfl_xor(s.y, 16, 64);
+            s.z += __shfl_xor(s.z, 16, 64);
+        }
+        if (nac <= 2) {
+            s.p += __shfl_xor(s.p, 32, 64);
+            s.x += __shfl_xor(s.x, 32, 64);
+            s.y += __shfl_xor(s.y, 32, 64);
+            s.z += __shfl_xor(s.z, 32, 64);
+        }
+        if (row < nac && valid) {
+            V4 oa;
+            oa.x = s.p;
+            oa.y = s.x;
+            oa.z = s.y;
+            oa.w = s.z;
+            bufA[a0 + base + ti] = oa;
+        }
+    }
+}
+
+// Per leaf: its own pairs (already in phi_s / E_s from k_p2p), then the
+// target-side sums of its items in order, then the source-side sums of the
+// upper entries that name it, ordered by entry; added in float64.
+template <class T, class V4>
+__global__ __launch_bounds__(64) void k_mu_reduce(const int32_t *leaves, const int64_t *li, const int64_t *it_u,
+                                                  int64_t nitem, const uint64_t *tkey, const int32_t *tval,
+                                                  int64_t nup, const int64_t *pb, const int32_t *beg,
+                                                  const int32_t *end, const V4 *bufA, const V4 *bufB, T *phi_s, T *E_s)
+{
+    const int64_t l = blockIdx.x;
+    const int A = leaves[l];
+    const int32_t tb = beg[A], nt = end[A] - tb;
+    // [lo, hi): the entries whose source is A
+    int64_t lo = 0, hi = nup;
+    while (lo < hi) {
+        const int64_t m = (lo + hi) >> 1;
+        if (tkey[m] < (uint64_t)A) lo = m + 1;
+        else hi = m;
+    }
+    int64_t hi2 = nup, lo2 = lo;
+    while (lo2 < hi2) {
+        const int64_t m = (lo2 + hi2) >> 1;
+        if (tkey[m] <= (uint64_t)A) lo2 = m + 1;
+        else hi2 = m;
+    }
+    const int64_t i0 = li[l], i1 = li[l + 1];
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        const int64_t o = tb + t;
+        double p = phi_s[o], x = E_s[3 * o], y = E_s[3 * o + 1], z = E_s[3 * o + 2];
+        for (int64_t it = i0; it < i1; ++it) {
+            const V4 a = bufA[it_u[3 * nitem + it] + t];
+            p += (double)a.x;
+            x += (double)a.y;
+            y += (double)a.z;
+            z += (double)a.w;
+        }
+        for (int64_t q = lo; q < lo2; ++q) {
+            const V4 b = bufB[pb[tval[q]] + t];
+            p += (double)b.x;
+            x += (double)b.y;
+            y += (double)b.z;
+            z += (double)b.w;
+        }
+        phi_s[o] = (T)p;
+        E_s[3 * o] = (T)x;
+        E_s[3 * o + 1] = (T)y;
+        E_s[3 * o + 2] = (T)z;
+    }
+}
+
+// Per leaf (i < nl): upper entries, those in the touching run, items and
+// target-side slots; zeros at i = nl.
+__global__ __launch_bounds__(256) void k_mu_count(const int32_t *leaves, int64_t nl, const int64_t *off,
+                                                  const int64_t *near, const int32_t *src, const int32_t *beg,
+                                                  const int32_t *end, int32_t *cu, int32_t *ct, int32_t *ci,
+                                                  int32_t *ca)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nl) return;
+    if (i == nl) {
+        cu[i] = ct[i] = ci[i] = ca[i] = 0;
+        return;
+    }
+    const int A = leaves[i];
+    const int64_t k0 = off[A], kn = near[A], k1 = off[A + 1];
+    int32_t nu = 0, nn = 0;
+    for (int64_t k = k0; k < k1; ++k)
+        if (src[k] > A) {
+            ++nu;
+            if (k < kn) ++nn;
+        }
+    const int32_t nit = (int32_t)((nu + kItemEntries - 1) / kItemEntries);
+    cu[i] = nu;
+    ct[i] = nn;
+    ci[i] = nit;
+    ca[i] = nit * (end[A] - beg[A]);
+}
+
+// Per leaf: its upper entries in list order with their source sizes, its
+// items, and its first item.  su, si, sa: exclusive scans (first element at
+// index 0 of each) of the upper-entry, item and target-slot counts.
+__global__ __launch_bounds__(256) void k_mu_fill(const int32_t *leaves, int64_t nl, const int64_t *off,
+                                                 const int32_t *src, const int32_t *beg, const int32_t *end,
+                                                 const int32_t *ct, const int64_t *su, const int64_t *si,
+                                                 const int64_t *sa, int32_t *usrc, int32_t *usz, int32_t *it_leaf,
+                                                 int64_t *it_u, int64_t nitem, int64_t *li)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nl) return;
+    li[i] = si[i] - si[0];
+    if (i == nl) return;
+    const int A = leaves[i];
+    const int64_t k0 = off[A], k1 = off[A + 1];
+    const int64_t ub0 = su[i] - su[0];
+    int64_t u = ub0;
+    for (int64_t k = k0; k < k1; ++k) {
+        const int32_t b = src[k];
+        if (b > A) {
+            usrc[u] = b;
+            usz[u] = end[b] - beg[b];
+            ++u;
+        }
+    }
+    const int64_t ue = u, un = ub0 + ct[i];
+    const int64_t it0 = si[i] - si[0], a_0 = sa[i] - sa[0];
+    const int nt = end[A] - beg[A];
+    for (int64_t c = 0; ub0 + c * kItemEntries < ue; ++c) {
+        const int64_t it = it0 + c;
+        const int64_t a = ub0 + c * kItemEntries, e = min(ue, a + kItemEntries);
+        it_leaf[it] = A;
+        it_u[it] = a;
+        it_u[nitem + it] = min(e, max(a, un));
+        it_u[2 * nitem + it] = e;
+        it_u[3 * nitem + it] = a_0 + c * nt;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mu_keys(const int32_t *usrc, int64_t n, uint64_t *key, int32_t *val)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    key[u] = (uint64_t)usrc[u];
+    val[u] = (int32_t)u;
+}
+
+// The one-sided items of the mutual mode: every leaf with an empty list, so
+// k_p2p runs only its own bodies and writes them straight to the outputs.
+__global__ __launch_bounds__(256) void k_own_items(const int32_t *leaves, int64_t nl, const int64_t *off,
+                                                   const int32_t *beg, int32_t *it_leaf, int64_t *it_k0,
+                                                   int64_t *it_k1, int64_t *it_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl) return;
+    const int A = leaves[i];
+    it_leaf[i] = A;
+    it_k0[i] = it_k1[i] = off[A];
+    it_out[i] = beg[A];
+}
+
 template <class T, class V4, bool KAHAN>
 void launch_items(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
 {
@@ -496,6 +919,21 @@ void launch_items(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream
         static_cast<const V4 *>(ub), static_cast<const V4 *>(P->ulo), static_cast<T *>(phi_s), static_cast<T *>(E_s),
         static_cast<T *>(P->p2p_part), static_cast<T *>(P->p2p_part) + P->p2p_npart);
     FMM_HIP(hipGetLastError());
+    if (P->mutual && P->mu_nitem > 0) {
+        FMM_CHECK(P->mu_nitem < (1ll << 32), FMM_ERR_UNSUPPORTED, "p2p: too many mutual work items");
+        k_p2p_mutual<T, V4, KAHAN><<<(unsigned)P->mu_nitem, 64, 0, s>>>(
+            P->mu_it_leaf, P->mu_it_u, P->mu_nitem, P->mu_src, P->mu_pb, P->c_beg, P->c_end, P->c_ctr,
+            static_cast<const V4 *>(ub), static_cast<const V4 *>(P->ulo), static_cast<V4 *>(P->mu_bufA),
+            static_cast<V4 *>(P->mu_bufB));
+        FMM_HIP(hipGetLastError());
+    }
+    if (P->mutual) {
+        k_mu_reduce<T, V4><<<(unsigned)P->nleaf, 64, 0, s>>>(
+            P->leaves, P->mu_li, P->mu_it_u, P->mu_nitem, P->mu_tkey, P->mu_tval, P->mu_nup, P->mu_pb, P->c_beg,
+            P->c_end, static_cast<const V4 *>(P->mu_bufA), static_cast<const V4 *>(P->mu_bufB),
+            static_cast<T *>(phi_s), static_cast<T *>(E_s));
+        FMM_HIP(hipGetLastError());
+    }
     if (P->p2p_ncut > 0) {
         k_p2p_reduce<T><<<(unsigned)P->p2p_ncut, 64, 0, s>>>(
             P->p2p_cl_leaf, P->p2p_cl_part, P->p2p_cl_n, P->c_beg, P->c_end, static_cast<const T *>(P->p2p_part),
@@ -519,6 +957,78 @@ void p2p(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream_t s)
     launch_p2p(P, ub, phi_s, E_s, s);
 }
 
+// Mutual mode: one-sided items for the leaves' own bodies, the upper entries
+// of every list with their source-side slots (a scan of the source sizes),
+// the entries ordered by source (a stable radix sort) and the work items.
+static void p2p_mutual_prepare(fmm_plan *P, hipStream_t s)
+{
+    const int64_t nl = P->nleaf;
+    Allocator &al = P->al;
+    P->p2p_nitem = nl;
+    P->p2p_it_leaf = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * nl));
+    P->p2p_it_k0 = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * nl));
+    P->p2p_it_k1 = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * nl));
+    P->p2p_it_out = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * nl));
+    k_own_items<<<grid1(nl, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->c_beg, P->p2p_it_leaf, P->p2p_it_k0,
+                                              P->p2p_it_k1, P->p2p_it_out);
+    FMM_HIP(hipGetLastError());
+
+    const int64_t m = nl + 1;
+    int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 4 * m));
+    int64_t *sc = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 4 * m));
+    int64_t *tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+    k_mu_count<<<grid1(m, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->p2p_near, P->p2p_src, P->c_beg, P->c_end,
+                                             cnt, cnt + m, cnt + 2 * m, cnt + 3 * m);
+    FMM_HIP(hipGetLastError());
+    // one scan over [upper entries | touching (unused) | items | target slots]
+    scan_exclusive_i32to64(cnt, sc, 4 * m, tot, al, s);
+    int64_t h[4];
+    FMM_HIP(hipMemcpyAsync(&h[0], sc + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipMemcpyAsync(&h[1], sc + 2 * m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipMemcpyAsync(&h[2], sc + 3 * m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipMemcpyAsync(&h[3], tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP(hipStreamSynchronize(s));
+    // sc[0 .. m) scans the upper-entry counts (total h[0]); sc[2m .. 3m) the
+    // item counts, from h[1]; sc[3m .. 4m) the target slots, from h[2]
+    const int64_t nup = h[0];
+    P->mu_nup = nup;
+    P->mu_nitem = h[2] - h[1];
+    P->mu_nabody = h[3] - h[2];
+    FMM_CHECK(nup < (1ll << 31), FMM_ERR_UNSUPPORTED, "mutual P2P: more than 2^31 upper entries");
+    P->mu_li = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * m));
+    P->mu_src = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nup)));
+    P->mu_it_leaf = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, P->mu_nitem)));
+    P->mu_it_u = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * 4 * std::max<int64_t>(1, P->mu_nitem)));
+    int32_t *usz = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<int64_t>(1, nup)));
+    k_mu_fill<<<grid1(m, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->p2p_src, P->c_beg, P->c_end, cnt + m, sc,
+                                            sc + 2 * m, sc + 3 * m, P->mu_src, usz, P->mu_it_leaf, P->mu_it_u,
+                                            P->mu_nitem, P->mu_li);
+    FMM_HIP(hipGetLastError());
+    al.free(tot);
+    al.free(sc);
+    al.free(cnt);
+    const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
+    P->mu_pb = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * std::max<int64_t>(1, nup)));
+    P->mu_tkey = static_cast<uint64_t *>(plan_alloc(P, sizeof(uint64_t) * std::max<int64_t>(1, nup)));
+    P->mu_tval = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nup)));
+    P->mu_nslot = 0;
+    if (nup > 0) {
+        int64_t *t2 = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
+        scan_exclusive_i32to64(usz, P->mu_pb, nup, t2, al, s);
+        FMM_HIP(hipMemcpyAsync(&P->mu_nslot, t2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        k_mu_keys<<<grid1(nup, 256), 256, 0, s>>>(P->mu_src, nup, P->mu_tkey, P->mu_tval);
+        FMM_HIP(hipGetLastError());
+        int bits = 1;
+        while ((1ll << bits) < P->ncell) ++bits;
+        radix_sort_u64(P->mu_tkey, P->mu_tval, nup, bits, al, s);
+        FMM_HIP(hipStreamSynchronize(s));
+        al.free(t2);
+    }
+    al.free(usz);
+    P->mu_bufA = plan_alloc(P, esz * 4 * std::max<int64_t>(1, P->mu_nabody));
+    P->mu_bufB = plan_alloc(P, esz * 4 * std::max<int64_t>(1, P->mu_nslot));
+}
+
 // Work items of the P2P kernel: one per leaf, or one per kItemEntries list
 // entries for leaves with longer lists, with their partial-sum slots; built
 // on the device by two scans in leaf order.
@@ -529,6 +1039,10 @@ void p2p_prepare(fmm_plan *P, hipStream_t s)
     P->p2p_ncut = 0;
     P->p2p_npart = 0;
     if (nl == 0) return;
+    if (P->mutual) {
+        p2p_mutual_prepare(P, s);
+        return;
+    }
     Allocator &al = P->al;
     int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 3 * (nl + 1)));
     int64_t *sc = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 3 * (nl + 1)));

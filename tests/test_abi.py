@@ -34,7 +34,7 @@ def test_params_default_and_last_error_without_gpu():
     p = F._binding._Params()
     lib.fmm_params_default(ctypes.byref(p))
     assert (p.p, p.theta, p.ncrit, p.precision, p.coarse_fp64_levels, p.kahan, p.tight, p.m2l_sparse,
-            p.m2l_rotation) == (8, 0.4, 64, 1, 3, 1, 0, -1, 0)
+            p.m2l_rotation, p.mutual) == (8, 0.4, 64, 1, 3, 1, 0, -1, 0, 0)
     assert lib.fmm_last_error() == b""
     # argument validation happens before any device call
     out = ctypes.c_void_p()
