@@ -501,19 +501,31 @@ __global__ void k_items_totals(const int64_t *sc, int64_t m, int64_t *tot)
 // lane it started from, complete over the row's targets, with no atomics and
 // no reduction across lanes.  Rows that hold different target chunks of A
 // against the same source chunk add their sums in a fixed order (a lane
-// exchange across rows).  The source-side sums of every (upper entry, source
-// body) go to their own slot, the target-side sums of every item to theirs,
-// and k_mu_reduce adds them per body in a fixed order: the leaf's own pairs,
-// its items in order, then its lower entries ordered by their upper twin.
+// exchange across rows).  The source-side sums of every (upper entry, target
+// chunk of 64, source body) go to their own slot, the target-side sums of
+// every item to theirs, and k_mu_reduce adds them per body in a fixed order:
+// the leaf's items in order, then its lower entries ordered by their upper
+// twin, then the leaf's own pairs.
 constexpr int kMuBatch = 64;  // sources staged per batch: four chunks of 16
 
-__device__ __forceinline__ int row_ror1_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, false); }
-__device__ __forceinline__ float row_ror1(float v) { return __builtin_bit_cast(float, row_ror1_i(__builtin_bit_cast(int, v))); }
-__device__ __forceinline__ double row_ror1(double v)
+// Rotation of a value by n lanes within each row of 16 (DPP row_ror).
+template <int N> __device__ __forceinline__ int row_ror_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x120 + N, 0xf, 0xf, false); }
+template <int N> __device__ __forceinline__ float row_ror(float v)
+{
+    return __builtin_bit_cast(float, row_ror_i<N>(__builtin_bit_cast(int, v)));
+}
+template <int N> __device__ __forceinline__ double row_ror(double v)
 {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)row_ror1_i((int)(unsigned)u), hi = (unsigned)row_ror1_i((int)(unsigned)(u >> 32));
+    const unsigned lo = (unsigned)row_ror_i<N>((int)(unsigned)u), hi = (unsigned)row_ror_i<N>((int)(unsigned)(u >> 32));
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int N, class T> __device__ __forceinline__ void row_ror_acc(Acc<T> &b)
+{
+    b.p = row_ror<N>(b.p);
+    b.x = row_ror<N>(b.x);
+    b.y = row_ror<N>(b.y);
+    b.z = row_ror<N>(b.z);
 }
 
 template <class T, class V4>
@@ -529,13 +541,15 @@ __device__ __forceinline__ V4 near_dummy()
 
 // Stages the next (up to) kMuBatch sources of upper entries [k, k1) of leaf
 // A (entry k already consumed up to body o) into this lane's v (and w, the
-// residual, with COMP), shifted into A's frame exactly as list_pass does;
-// advances (k, o) and returns the number staged.  Slots past it hold
-// zero-charge dummies.
+// residual, with COMP), shifted into A's frame exactly as list_pass does,
+// with the slot of its source-side sums for target chunk c in dst; advances
+// (k, o) and returns the number staged.  Slots past it hold zero-charge
+// dummies.  The slots of upper entry u for target chunk c are
+// pb[u] + c |B| + (body - beg[B]).
 template <class T, class V4, bool COMP>
-__device__ int mu_gather(GatherLds<T> *gs, int A, int64_t &k, int64_t k1, int32_t &o, const int32_t *usrc,
-                         const int32_t *beg, const int32_t *end, const double *ctr, const V4 *ub, const V4 *ul, V4 &v,
-                         V4 &w)
+__device__ int mu_gather(GatherLds<T> *gs, int64_t *sdst, int A, int c, int64_t &k, int64_t k1, int32_t &o,
+                         const int32_t *usrc, const int64_t *pb, const int32_t *beg, const int32_t *end,
+                         const double *ctr, const V4 *ub, const V4 *ul, V4 &v, V4 &w, int64_t &dst)
 {
     const int lane = threadIdx.x;
     const double cax = ctr[3 * A], cay = ctr[3 * A + 1], caz = ctr[3 * A + 2];
@@ -543,7 +557,8 @@ __device__ int mu_gather(GatherLds<T> *gs, int A, int64_t &k, int64_t k1, int32_
     const bool in = kk < k1;
     const int b = in ? usrc[kk] : A;
     const int32_t skip = lane == 0 ? o : 0;
-    const int32_t sz = in ? end[b] - beg[b] - skip : 0;
+    const int32_t full = end[b] - beg[b];
+    const int32_t sz = in ? full - skip : 0;
     int32_t pre = sz;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -554,6 +569,7 @@ __device__ int mu_gather(GatherLds<T> *gs, int A, int64_t &k, int64_t k1, int32_
     gs->incl[lane] = pre;
     gs->excl[lane] = pre - sz;
     gs->base[lane] = beg[b] + skip;
+    sdst[lane] = in ? pb[kk] + (int64_t)c * full + skip : 0;
     const double shx = ctr[3 * b] - cax, shy = ctr[3 * b + 1] - cay, shz = ctr[3 * b + 2] - caz;
     gs->sh[lane][0] = (T)shx;
     gs->sh[lane][1] = (T)shy;
@@ -568,16 +584,19 @@ __device__ int mu_gather(GatherLds<T> *gs, int A, int64_t &k, int64_t k1, int32_
 #pragma unroll
     for (int step = 32; step >= 1; step >>= 1)
         if (gs->incl[e + step - 1] <= lane) e += step;
+    dst = 0;
     if (lane < staged) {
-        const int64_t j = gs->base[e] + (lane - gs->excl[e]);
+        const int32_t r = lane - gs->excl[e];
+        const int64_t j = gs->base[e] + r;
+        dst = sdst[e] + r;
         v = ub[j];
         if (COMP) {
-            const V4 r = ul[j];
+            const V4 q = ul[j];
             const T hx = v.x + gs->sh[e][0], hy = v.y + gs->sh[e][1], hz = v.z + gs->sh[e][2];
             const T bx = hx - v.x, by = hy - v.y, bz = hz - v.z;
-            w.x = ((v.x - (hx - bx)) + (gs->sh[e][0] - bx)) + (r.x + gs->sl[e][0]);
-            w.y = ((v.y - (hy - by)) + (gs->sh[e][1] - by)) + (r.y + gs->sl[e][1]);
-            w.z = ((v.z - (hz - bz)) + (gs->sh[e][2] - bz)) + (r.z + gs->sl[e][2]);
+            w.x = ((v.x - (hx - bx)) + (gs->sh[e][0] - bx)) + (q.x + gs->sl[e][0]);
+            w.y = ((v.y - (hy - by)) + (gs->sh[e][1] - by)) + (q.y + gs->sl[e][1]);
+            w.z = ((v.z - (hz - bz)) + (gs->sh[e][2] - bz)) + (q.z + gs->sl[e][2]);
             w.w = (T)0;
             v.x = hx;
             v.y = hy;
@@ -605,12 +624,15 @@ __device__ int mu_gather(GatherLds<T> *gs, int A, int64_t &k, int64_t k1, int32_
 
 // One staged batch against this lane's target u (residual ut with COMP).
 // nac target chunks of 16 (1, 2 or 4) share the four rows: row r holds target
-// chunk r % nac and, in round rd, source chunk rd (4 / nac) + r / nac.
-// dst: the source-side slots of the batch's first source; add: accumulate
-// into them (a later target chunk of a leaf with more than 64 bodies).
+// chunk r % nac and, in round rd, source chunk rd (4 / nac) + r / nac.  With
+// a chunk of at most g = 8 or 4 targets (nac = 1) the row holds each target
+// on 16 / g lanes, which together meet the 16 sources in g steps; the sums
+// then turn the remaining 16 - g lanes in one rotation, back to their
+// sources' lanes.  dsl: the source-side slot of every staged source.
 template <class T, class V4, bool COMP>
-__device__ __forceinline__ void mu_batch(const V4 *cur, const V4 *curw, int staged, int nac, int row, int i,
-                                         int delta, const V4 &u, const V4 &ut, Acc<T> &pa, V4 *dst, bool add)
+__device__ __forceinline__ void mu_batch(const V4 *cur, const V4 *curw, const int64_t *dsl, int staged, int nac,
+                                         int g, int row, int i, int delta, const V4 &u, const V4 &ut, Acc<T> &pa,
+                                         V4 *bufB)
 {
     const int spr = 4 / nac;
     for (int rd = 0; rd < nac; ++rd) {
@@ -619,7 +641,7 @@ __device__ __forceinline__ void mu_batch(const V4 *cur, const V4 *curw, int stag
         const V4 *cw = curw + sc * 16;
         Acc<T> b{0, 0, 0, 0};
 #pragma unroll 4
-        for (int t = 0; t < 16; ++t) {
+        for (int t = 0; t < g; ++t) {
             const int j = (i + t * delta) & 15;  // the source whose sum this lane holds now
             const V4 v = cs[j];
             T dx = u.x - v.x, dy = u.y - v.y, dz = u.z - v.z;
@@ -643,11 +665,10 @@ __device__ __forceinline__ void mu_batch(const V4 *cur, const V4 *curw, int stag
             b.x -= ft * dx;
             b.y -= ft * dy;
             b.z -= ft * dz;
-            b.p = row_ror1(b.p);
-            b.x = row_ror1(b.x);
-            b.y = row_ror1(b.y);
-            b.z = row_ror1(b.z);
+            row_ror_acc<1>(b);
         }
+        if (g == 8) row_ror_acc<8>(b);
+        else if (g == 4) row_ror_acc<12>(b);
         if (nac >= 2) {
             b.p += __shfl_xor(b.p, 16, 64);
             b.x += __shfl_xor(b.x, 16, 64);
@@ -667,43 +688,39 @@ __device__ __forceinline__ void mu_batch(const V4 *cur, const V4 *curw, int stag
             o.y = b.x;
             o.z = b.y;
             o.w = b.z;
-            if (add) {
-                const V4 q = dst[slot];
-                o.x += q.x;
-                o.y += q.y;
-                o.z += q.z;
-                o.w += q.w;
-            }
-            dst[slot] = o;
+            bufB[dsl[slot]] = o;
         }
     }
 }
 
 // Upper entries [k, k1) of leaf A as one stream, batch by batch (the loads of
-// batch i + 1 in flight while batch i is multiplied).  Source-side slots of
-// the stream start at dst.
+// batch i + 1 in flight while batch i is multiplied), against target chunk c.
 template <class T, class V4, bool KAHAN, bool COMP>
-__device__ void mu_pass(V4 *sb, GatherLds<T> *gs, int A, int64_t k, int64_t k1, const int32_t *usrc,
-                        const int32_t *beg, const int32_t *end, const double *ctr, const V4 *ub, const V4 *ul, int nac,
-                        int row, int i, int delta, const V4 &u, const V4 &ut, Acc<T> &s, Acc<T> &c, V4 *dst, bool add)
+__device__ void mu_pass(V4 *sb, int64_t *sd, GatherLds<T> *gs, int64_t *sdst, int A, int c, int64_t k, int64_t k1,
+                        const int32_t *usrc, const int64_t *pb, const int32_t *beg, const int32_t *end,
+                        const double *ctr, const V4 *ub, const V4 *ul, int nac, int g, int row, int i, int delta,
+                        const V4 &u, const V4 &ut, Acc<T> &s, Acc<T> &cc, V4 *bufB)
 {
     const int lane = threadIdx.x;
     int32_t o = 0;
     V4 v, w;
-    int st_next = k < k1 ? mu_gather<T, V4, COMP>(gs, A, k, k1, o, usrc, beg, end, ctr, ub, ul, v, w) : 0;
-    int64_t pos = 0;
+    int64_t dst = 0;
+    int st_next = k < k1 ? mu_gather<T, V4, COMP>(gs, sdst, A, c, k, k1, o, usrc, pb, beg, end, ctr, ub, ul, v, w, dst)
+                         : 0;
     int buf = 0;
     while (st_next > 0) {
         V4 *cur = sb + buf * 2 * kMuBatch;
+        int64_t *cd = sd + buf * kMuBatch;
         cur[lane] = v;
         if (COMP) cur[kMuBatch + lane] = w;
+        cd[lane] = dst;
         const int st_cur = st_next;
         __syncthreads();
-        st_next = k < k1 ? mu_gather<T, V4, COMP>(gs, A, k, k1, o, usrc, beg, end, ctr, ub, ul, v, w) : 0;
+        st_next = k < k1 ? mu_gather<T, V4, COMP>(gs, sdst, A, c, k, k1, o, usrc, pb, beg, end, ctr, ub, ul, v, w, dst)
+                         : 0;
         Acc<T> pa{0, 0, 0, 0};
-        mu_batch<T, V4, COMP>(cur, cur + kMuBatch, st_cur, nac, row, i, delta, u, ut, pa, dst + pos, add);
-        fold_into<T, KAHAN>(s, c, pa);
-        pos += st_cur;
+        mu_batch<T, V4, COMP>(cur, cur + kMuBatch, cd, st_cur, nac, g, row, i, delta, u, ut, pa, bufB);
+        fold_into<T, KAHAN>(s, cc, pa);
         buf ^= 1;
     }
     __syncthreads();
@@ -718,6 +735,8 @@ __global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *it_leaf, const
                                                    V4 *bufA, V4 *bufB)
 {
     __shared__ V4 sb[4 * kMuBatch];
+    __shared__ int64_t sd[2 * kMuBatch];
+    __shared__ int64_t sdst[64];
     __shared__ GatherLds<T> gs;
     const int64_t item = blockIdx.x;
     const int A = it_leaf[item];
@@ -725,29 +744,37 @@ __global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *it_leaf, const
     const int lane = threadIdx.x, row = lane >> 4, i = lane & 15;
     // direction of the row rotation: after one step lane i holds the sum that
     // was on lane i + delta (mod 16)
-    const int delta = (row_ror1_i(i) - i) & 15;
+    const int delta = (row_ror_i<1>(i) - i) & 15;
     const int32_t tb = beg[A], nt = end[A] - tb;
     for (int base = 0; base < nt; base += 64) {
         const int cnt = min(64, nt - base);
         const int nac = cnt <= 16 ? 1 : (cnt <= 32 ? 2 : 4);
-        const int ti = (row % nac) * 16 + i;
+        const int g = cnt <= 4 ? 4 : (cnt <= 8 ? 8 : 16);
+        const int ti = (row % nac) * 16 + (i & (g - 1));
         const bool valid = ti < cnt;
         const V4 u = valid ? ub[tb + base + ti] : near_dummy<T, V4>();
         const V4 ut = (ul && valid) ? ul[tb + base + ti] : V4{};
         Acc<T> s{0, 0, 0, 0}, c{0, 0, 0, 0};
         int64_t k0 = u0;
         if (ul && un > u0) {
-            mu_pass<T, V4, KAHAN, true>(sb, &gs, A, u0, un, usrc, beg, end, ctr, ub, ul, nac, row, i, delta, u, ut, s,
-                                        c, bufB + pb[u0], base > 0);
+            mu_pass<T, V4, KAHAN, true>(sb, sd, &gs, sdst, A, base / 64, u0, un, usrc, pb, beg, end, ctr, ub, ul, nac,
+                                        g, row, i, delta, u, ut, s, c, bufB);
             k0 = un;
         }
         if (u1 > k0)
-            mu_pass<T, V4, KAHAN, false>(sb, &gs, A, k0, u1, usrc, beg, end, ctr, ub, ul, nac, row, i, delta, u, ut, s,
-                                         c, bufB + pb[k0], base > 0);
+            mu_pass<T, V4, KAHAN, false>(sb, sd, &gs, sdst, A, base / 64, k0, u1, usrc, pb, beg, end, ctr, ub, ul, nac,
+                                         g, row, i, delta, u, ut, s, c, bufB);
         if (KAHAN) {
             s.p -= c.p; s.x -= c.x; s.y -= c.y; s.z -= c.z;
         }
-        // rows that hold the same targets: a fixed-order sum
+        // lanes that hold the same target: a fixed-order sum, within the row
+        // (copies of a short chunk), then across rows
+        for (int w = g; w < 16; w <<= 1) {
+            s.p += __shfl_xor(s.p, w, 64);
+            s.x += __shfl_xor(s.x, w, 64);
+            s.y += __shfl_xor(s.y, w, 64);
+            s.z += __shfl_xor(s.z, w, 64);
+        }
         if (nac == 1) {
             s.p += __shfl_xor(s.p, 16, 64);
             s.x += __shfl_xor(s.x, 16, 64);
@@ -760,7 +787,7 @@ __global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *it_leaf, const
             s.y += __shfl_xor(s.y, 32, 64);
             s.z += __shfl_xor(s.z, 32, 64);
         }
-        if (row < nac && valid) {
+        if (row < nac && i < g && valid) {
             V4 oa;
             oa.x = s.p;
             oa.y = s.x;
@@ -773,13 +800,17 @@ __global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *it_leaf, const
 
 // Per leaf: its own pairs (already in phi_s / E_s from k_p2p), then the
 // target-side sums of its items in order, then the source-side sums of the
-// upper entries that name it, ordered by entry; added in float64.
+// upper entries that name it (ordered by entry, each over the target chunks
+// of the entry's leaf in order); added in float64.  G groups of lanes take
+// every G-th term, eight loads in flight, and their sums are added in group
+// order.
 template <class T, class V4>
 __global__ __launch_bounds__(64) void k_mu_reduce(const int32_t *leaves, const int64_t *li, const int64_t *it_u,
                                                   int64_t nitem, const uint64_t *tkey, const int32_t *tval,
                                                   int64_t nup, const int64_t *pb, const int32_t *beg,
                                                   const int32_t *end, const V4 *bufA, const V4 *bufB, T *phi_s, T *E_s)
 {
+    __shared__ double red[64][4];
     const int64_t l = blockIdx.x;
     const int A = leaves[l];
     const int32_t tb = beg[A], nt = end[A] - tb;
@@ -797,83 +828,147 @@ __global__ __launch_bounds__(64) void k_mu_reduce(const int32_t *leaves, const i
         else hi2 = m;
     }
     const int64_t i0 = li[l], i1 = li[l + 1];
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-        const int64_t o = tb + t;
-        double p = phi_s[o], x = E_s[3 * o], y = E_s[3 * o + 1], z = E_s[3 * o + 2];
-        for (int64_t it = i0; it < i1; ++it) {
-            const V4 a = bufA[it_u[3 * nitem + it] + t];
-            p += (double)a.x;
-            x += (double)a.y;
-            y += (double)a.z;
-            z += (double)a.w;
+    // groups: G = the largest power of two with G nt <= 64 (1 above 64 bodies)
+    int G = 1;
+    while (2 * G * nt <= 64) G *= 2;
+    const int span = nt < 64 ? nt : 64;
+    const int grp = threadIdx.x / span, tl = threadIdx.x % span;
+    for (int t0 = 0; t0 < nt; t0 += span) {
+        const int t = t0 + tl;
+        const bool act = grp < G && t < nt;
+        double p = 0, x = 0, y = 0, z = 0;
+        if (act) {
+            for (int64_t it = i0 + grp; it < i1; it += G) {
+                const V4 a = bufA[it_u[3 * nitem + it] + t];
+                p += (double)a.x;
+                x += (double)a.y;
+                y += (double)a.z;
+                z += (double)a.w;
+            }
+            constexpr int D = 8;
+            for (int64_t q = lo + grp; q < lo2; q += (int64_t)G * D) {
+                V4 vals[D];
+                int nv = 0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    const int64_t qq = q + (int64_t)r * G;
+                    vals[r] = V4{};
+                    if (qq < lo2) {
+                        const int64_t e = tval[qq];
+                        vals[r] = bufB[pb[e] + t];
+                        nv = r + 1;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    if (r < nv) {
+                        const int64_t qq = q + (int64_t)r * G;
+                        const int64_t e = tval[qq];
+                        const int64_t nch = (pb[e + 1] - pb[e]) / nt;
+                        p += (double)vals[r].x;
+                        x += (double)vals[r].y;
+                        y += (double)vals[r].z;
+                        z += (double)vals[r].w;
+                        for (int64_t cc = 1; cc < nch; ++cc) {
+                            const V4 b = bufB[pb[e] + cc * nt + t];
+                            p += (double)b.x;
+                            x += (double)b.y;
+                            y += (double)b.z;
+                            z += (double)b.w;
+                        }
+                    }
+                }
+            }
         }
-        for (int64_t q = lo; q < lo2; ++q) {
-            const V4 b = bufB[pb[tval[q]] + t];
-            p += (double)b.x;
-            x += (double)b.y;
-            y += (double)b.z;
-            z += (double)b.w;
+        if (G > 1) {
+            red[threadIdx.x][0] = p;
+            red[threadIdx.x][1] = x;
+            red[threadIdx.x][2] = y;
+            red[threadIdx.x][3] = z;
+            __syncthreads();
+            if (grp == 0 && act) {
+                for (int gg = 1; gg < G; ++gg) {
+                    p += red[gg * span + tl][0];
+                    x += red[gg * span + tl][1];
+                    y += red[gg * span + tl][2];
+                    z += red[gg * span + tl][3];
+                }
+            }
+            __syncthreads();
         }
-        phi_s[o] = (T)p;
-        E_s[3 * o] = (T)x;
-        E_s[3 * o + 1] = (T)y;
-        E_s[3 * o + 2] = (T)z;
+        if (grp == 0 && act) {
+            const int64_t o = tb + t;
+            phi_s[o] = (T)((double)phi_s[o] + p);
+            E_s[3 * o] = (T)((double)E_s[3 * o] + x);
+            E_s[3 * o + 1] = (T)((double)E_s[3 * o + 1] + y);
+            E_s[3 * o + 2] = (T)((double)E_s[3 * o + 2] + z);
+        }
     }
 }
 
-// Per leaf (i < nl): upper entries, those in the touching run, items and
-// target-side slots; zeros at i = nl.
+// One wave per leaf (i < nl): upper entries, those in the touching run, items
+// and target-side slots; zeros at i = nl.
 __global__ __launch_bounds__(256) void k_mu_count(const int32_t *leaves, int64_t nl, const int64_t *off,
                                                   const int64_t *near, const int32_t *src, const int32_t *beg,
                                                   const int32_t *end, int32_t *cu, int32_t *ct, int32_t *ci,
                                                   int32_t *ca)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i > nl) return;
     if (i == nl) {
-        cu[i] = ct[i] = ci[i] = ca[i] = 0;
+        if (lane == 0) cu[i] = ct[i] = ci[i] = ca[i] = 0;
         return;
     }
     const int A = leaves[i];
     const int64_t k0 = off[A], kn = near[A], k1 = off[A + 1];
     int32_t nu = 0, nn = 0;
-    for (int64_t k = k0; k < k1; ++k)
-        if (src[k] > A) {
-            ++nu;
-            if (k < kn) ++nn;
-        }
-    const int32_t nit = (int32_t)((nu + kItemEntries - 1) / kItemEntries);
-    cu[i] = nu;
-    ct[i] = nn;
-    ci[i] = nit;
-    ca[i] = nit * (end[A] - beg[A]);
+    for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+        const bool up = k < k1 && src[k] > A;
+        nu += __popcll(__ballot(up));
+        nn += __popcll(__ballot(up && k < kn));
+    }
+    if (lane == 0) {
+        const int32_t nit = (int32_t)((nu + kItemEntries - 1) / kItemEntries);
+        cu[i] = nu;
+        ct[i] = nn;
+        ci[i] = nit;
+        ca[i] = nit * (end[A] - beg[A]);
+    }
 }
 
-// Per leaf: its upper entries in list order with their source sizes, its
-// items, and its first item.  su, si, sa: exclusive scans (first element at
-// index 0 of each) of the upper-entry, item and target-slot counts.
+// One wave per leaf: its upper entries in list order with their source-side
+// slot counts (source bodies times A's target chunks), its items, and its
+// first item.  su, si, sa: exclusive scans (first
+// element at index 0 of each) of the upper-entry, item and target-slot counts.
 __global__ __launch_bounds__(256) void k_mu_fill(const int32_t *leaves, int64_t nl, const int64_t *off,
                                                  const int32_t *src, const int32_t *beg, const int32_t *end,
                                                  const int32_t *ct, const int64_t *su, const int64_t *si,
                                                  const int64_t *sa, int32_t *usrc, int32_t *usz, int32_t *it_leaf,
                                                  int64_t *it_u, int64_t nitem, int64_t *li)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i > nl) return;
-    li[i] = si[i] - si[0];
+    if (lane == 0) li[i] = si[i] - si[0];
     if (i == nl) return;
     const int A = leaves[i];
     const int64_t k0 = off[A], k1 = off[A + 1];
     const int64_t ub0 = su[i] - su[0];
+    const int32_t nch = (end[A] - beg[A] + 63) / 64;  // target chunks of A
     int64_t u = ub0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int32_t b = src[k];
-        if (b > A) {
-            usrc[u] = b;
-            usz[u] = end[b] - beg[b];
-            ++u;
+    for (int64_t k = k0 + lane; k - lane < k1; k += 64) {
+        const int32_t b = k < k1 ? src[k] : A;
+        const bool up = b > A;
+        const uint64_t m = __ballot(up);
+        if (up) {
+            const int64_t o = u + __popcll(m & ((1ull << lane) - 1));
+            usrc[o] = b;
+            usz[o] = (end[b] - beg[b]) * nch;
         }
+        u += __popcll(m);
     }
+    if (lane != 0) return;
     const int64_t ue = u, un = ub0 + ct[i];
     const int64_t it0 = si[i] - si[0], a_0 = sa[i] - sa[0];
     const int nt = end[A] - beg[A];
@@ -977,7 +1072,7 @@ static void p2p_mutual_prepare(fmm_plan *P, hipStream_t s)
     int32_t *cnt = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * 4 * m));
     int64_t *sc = static_cast<int64_t *>(al.alloc(sizeof(int64_t) * 4 * m));
     int64_t *tot = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
-    k_mu_count<<<grid1(m, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->p2p_near, P->p2p_src, P->c_beg, P->c_end,
+    k_mu_count<<<grid1(m, 4), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->p2p_near, P->p2p_src, P->c_beg, P->c_end,
                                              cnt, cnt + m, cnt + 2 * m, cnt + 3 * m);
     FMM_HIP(hipGetLastError());
     // one scan over [upper entries | touching (unused) | items | target slots]
@@ -1000,7 +1095,7 @@ static void p2p_mutual_prepare(fmm_plan *P, hipStream_t s)
     P->mu_it_leaf = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, P->mu_nitem)));
     P->mu_it_u = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * 4 * std::max<int64_t>(1, P->mu_nitem)));
     int32_t *usz = static_cast<int32_t *>(al.alloc(sizeof(int32_t) * std::max<int64_t>(1, nup)));
-    k_mu_fill<<<grid1(m, 256), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->p2p_src, P->c_beg, P->c_end, cnt + m, sc,
+    k_mu_fill<<<grid1(m, 4), 256, 0, s>>>(P->leaves, nl, P->p2p_off, P->p2p_src, P->c_beg, P->c_end, cnt + m, sc,
                                             sc + 2 * m, sc + 3 * m, P->mu_src, usz, P->mu_it_leaf, P->mu_it_u,
                                             P->mu_nitem, P->mu_li);
     FMM_HIP(hipGetLastError());
@@ -1008,13 +1103,14 @@ static void p2p_mutual_prepare(fmm_plan *P, hipStream_t s)
     al.free(sc);
     al.free(cnt);
     const size_t esz = P->precision == FMM_PREC_FP64 ? sizeof(double) : sizeof(float);
-    P->mu_pb = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * std::max<int64_t>(1, nup)));
+    P->mu_pb = static_cast<int64_t *>(plan_alloc(P, sizeof(int64_t) * (nup + 1)));
     P->mu_tkey = static_cast<uint64_t *>(plan_alloc(P, sizeof(uint64_t) * std::max<int64_t>(1, nup)));
     P->mu_tval = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, nup)));
     P->mu_nslot = 0;
     if (nup > 0) {
         int64_t *t2 = static_cast<int64_t *>(al.alloc(sizeof(int64_t)));
         scan_exclusive_i32to64(usz, P->mu_pb, nup, t2, al, s);
+        FMM_HIP(hipMemcpyAsync(P->mu_pb + nup, t2, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
         FMM_HIP(hipMemcpyAsync(&P->mu_nslot, t2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         k_mu_keys<<<grid1(nup, 256), 256, 0, s>>>(P->mu_src, nup, P->mu_tkey, P->mu_tval);
         FMM_HIP(hipGetLastError());
