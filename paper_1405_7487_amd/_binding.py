@@ -421,11 +421,13 @@ def let_evaluate(x: torch.Tensor, q: torch.Tensor, nrank: int, params: Params | 
                 stats={k: getattr(st, k) for k, _ in _LetStats._fields_})
 
 
-def mfma_layout(f64: bool) -> list:
-    """Accumulator values of the MFMA lane-layout diagnostic (host list)."""
+def mfma_layout(f64: bool, tail: bool = False) -> list:
+    """Accumulator values of the MFMA lane-layout diagnostic (host list);
+    tail=True probes the float32 4x4x1 blocks of the short last row tile."""
     import numpy as np
-    out = np.zeros(256, np.float64 if f64 else np.float32)
-    _check(load().fmm_debug_mfma_layout(1 if f64 else 0, C.c_void_p(out.ctypes.data)))
+    out = np.zeros(256, np.float64 if (f64 and not tail) else np.float32)
+    mode = 2 if tail else (1 if f64 else 0)
+    _check(load().fmm_debug_mfma_layout(mode, C.c_void_p(out.ctypes.data)))
     return out
 
 

@@ -911,6 +911,7 @@ fmm_status fmm_debug_mfma_layout(int32_t f64, void *out_host)
     g_err.clear();
     return guarded([&]() -> fmm_status {
         FMM_CHECK(out_host != nullptr, FMM_ERR_INVALID, "out is NULL");
+        FMM_CHECK(f64 >= 0 && f64 <= 2, FMM_ERR_INVALID, "f64 must be 0, 1 or 2");
         mfma_probe(f64, out_host);
         return FMM_OK;
     });

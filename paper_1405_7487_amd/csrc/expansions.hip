@@ -143,7 +143,7 @@ __host__ __device__ __forceinline__ void rdecode(int r, int &n, int &m, int &im)
 // input degree n by rho^n.
 template <class T>
 __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nops, int p, int P2pad, int SCH, int GST,
-                                                      int64_t OPSZ, T *Tf)
+                                                      int64_t OPSZ, int tail, T *Tf)
 {
     const int op = blockIdx.x;
     if (op >= nops) return;
@@ -158,10 +158,13 @@ __global__ __launch_bounds__(256) void k_make_m2l_ops(const double4 *tr, int nop
     const int RT = P2pad / 16;
     for (int e = threadIdx.x; e < P2pad * NCOL; e += blockDim.x) {
         const int row = e / NCOL, col = e % NCOL;
+        // tail: the last row tile holds its (at most 4) coefficient rows
+        // repeated in every group of 4 fragment lanes
+        const int vrow = (tail && row >= P2pad - 16) ? P2pad - 16 + (row & 3) : row;
         double v = 0.0;
-        if (row < P2 && col < P2) {
+        if (vrow < P2 && col < P2) {
             int j, s, rim, n, m, cim;
-            rdecode(row, j, s, rim);
+            rdecode(vrow, j, s, rim);
             rdecode(col, n, m, cim);
             cd d;
             if (m == 0) {
@@ -541,12 +544,12 @@ void make_operators(fmm_plan *P, hipStream_t s)
         if (P->nops > 0) {
             if (f64)
                 k_make_m2l_ops<double><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, m2l_sch(P2pad / 16, Q, 8),
-                                                               m2l_gst(P2pad / 16, Q, 8), m2l_opsz(P2pad / 16, Q, 8),
+                                                               m2l_gst(P2pad / 16, Q, 8), m2l_opsz(P2pad / 16, Q, 8), 0,
                                                                static_cast<double *>(C.ops));
             else
                 k_make_m2l_ops<float><<<P->nops, 256, 0, s>>>(d_ot, P->nops, P->p, P2pad, m2l_sch(P2pad / 16, Q, 4),
                                                               m2l_gst(P2pad / 16, Q, 4), m2l_opsz(P2pad / 16, Q, 4),
-                                                              static_cast<float *>(C.ops));
+                                                              m2l_tail_rows(P->p), static_cast<float *>(C.ops));
             FMM_HIP(hipGetLastError());
         }
         const size_t shn = (size_t)8 * P2pad * P2pad;
@@ -588,10 +591,10 @@ void make_m2l_ops(fmm_plan *P, const double4 *tr_dev, int nops, void *out, hipSt
     const int RT = P->P2pad / 16, Q = m2l_q(P->p);
     if (P->precision == FMM_PREC_FP64)
         k_make_m2l_ops<double><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, m2l_sch(RT, Q, 8), m2l_gst(RT, Q, 8),
-                                                    m2l_opsz(RT, Q, 8), static_cast<double *>(out));
+                                                    m2l_opsz(RT, Q, 8), 0, static_cast<double *>(out));
     else
         k_make_m2l_ops<float><<<nops, 256, 0, s>>>(tr_dev, nops, P->p, P->P2pad, m2l_sch(RT, Q, 4), m2l_gst(RT, Q, 4),
-                                                   m2l_opsz(RT, Q, 4), static_cast<float *>(out));
+                                                   m2l_opsz(RT, Q, 4), m2l_tail_rows(P->p), static_cast<float *>(out));
     FMM_HIP(hipGetLastError());
 }
 

@@ -86,6 +86,19 @@ __host__ __device__ constexpr int m2l_q(int p)
     return (best >= 4 || best == q0) ? q0 : 4 * RT;
 }
 __host__ __device__ constexpr int m2l_rt(int p) { return (p * p + 15) / 16; }
+// Coefficient rows in the last row tile when there are at most 4 of them
+// and p <= 10 (p = 1, 2, 6, 7, 9, 10), else 0.  In float32 such a tile runs
+// as one 4x4x1 MFMA (sixteen 4x4 blocks) per step instead of a 16x16x4 one:
+// its operator rows are stored as row 16 (RT - 1) + (j & 3) in fragment lane
+// j, so block (g, j / 4) multiplies those rows by the inputs of k-group g for
+// columns 4 (j / 4) .. + 3, a quarter of the matrix-core passes.  (At p = 14
+// and 15 the same change costs the kernel half its waves per SIMD, for 5 %
+// of the passes.)
+__host__ __device__ constexpr int m2l_tail_rows(int p)
+{
+    const int v = p * p - 16 * (m2l_rt(p) - 1);
+    return (p <= 10 && v >= 1 && v <= 4) ? v : 0;
+}
 // Whether the fragment reads of a step, lane (g, j) at word g G + j RT, fall
 // in 64 different LDS banks.
 __host__ __device__ constexpr bool m2l_banks_distinct(int G, int RT)

@@ -48,6 +48,31 @@ template <> struct Mfma<double> {
     }
 };
 
+// The last row tile with at most 4 coefficient rows (float32): one 4x4x1
+// MFMA, sixteen 4x4 blocks.  Block b = 4 g + j / 4 (lanes 4 b .. 4 b + 3)
+// multiplies A rows i = lane % 4 (the operator stores row 16 (RT - 1) + i in
+// fragment lane j) by the inputs of k-group g for columns 4 (j / 4) + jj; lane
+// 4 b + jj accumulates rows e = 0..3 of column jj in slot e, a partial sum over
+// k-group g that the four groups add at the end.
+template <class T>
+__device__ __forceinline__ typename Mfma<T>::acc_t mfma_tail(T a, T b, typename Mfma<T>::acc_t c)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+    else return Mfma<T>::run(a, b, c);
+}
+// Sum of the four k-groups' partials of the tail tile (lanes j, j + 16,
+// j + 32, j + 48), in a fixed order; every lane ends with its column's rows.
+template <class A>
+__device__ __forceinline__ A tail_sum(A v)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] += __shfl_xor(v[e], 16, 64);
+        v[e] += __shfl_xor(v[e], 32, 64);
+    }
+    return v;
+}
+
 // Widest vector of T (16 bytes at most) whose length divides SCH.
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
@@ -109,7 +134,7 @@ __device__ __forceinline__ void stage_copy(const T *src, T *dst, int wave, int l
     }
 }
 
-template <class T, int RT, int Q, int CG, int WV>
+template <class T, int RT, int Q, int CG, int WV, int TR>
 __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restrict__ tile_order, int ntpos,
                                                      const int32_t *__restrict__ tile_cls,
                                                      const int32_t *__restrict__ slots,
@@ -123,6 +148,7 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restri
 {
     constexpr int ESZ = (int)sizeof(T);
     constexpr int P2pad = 16 * RT, TW = 16 * CG * WV;
+    constexpr bool TAIL = TR > 0 && ESZ == 4;  // the last row tile on 4x4x1 blocks
     constexpr int SCH = m2l_sch(RT, Q, ESZ), NC = Q / SCH, GST = m2l_gst(RT, Q, ESZ);
     constexpr int64_t OPSZ = m2l_opsz(RT, Q, ESZ);
     constexpr int BUF = m2l_rounds(RT, Q, ESZ, WV) * 1024 * WV / ESZ;  // elements per LDS stage buffer
@@ -237,7 +263,9 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restri
                     _Pragma("unroll") for (int cg = 0; cg < CG; ++cg)                              \
                         if (CG == 1 || hv[cg]) /* (with one group, skipping costs more than it saves) */ \
                             _Pragma("unroll") for (int r = 0; r < RT; ++r)                         \
-                                acc[cg][r] = Mfma<T>::run(a[r], bq[cur][cg][ss], acc[cg][r]);      \
+                                acc[cg][r] = (TAIL && r == RT - 1)                                 \
+                                                 ? mfma_tail<T>(a[r], bq[cur][cg][ss], acc[cg][r]) \
+                                                 : Mfma<T>::run(a[r], bq[cur][cg][ss], acc[cg][r]); \
                 }                                                                                  \
             }                                                                                      \
         }                                                                                          \
@@ -270,20 +298,29 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_batched(const int32_t *__restri
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
         const int col = wave * CG * 16 + cg * 16 + j;
+        constexpr int RM = TAIL ? RT - 1 : RT;  // row tiles in the 16x16 layout
+        acc_t tl = acc[cg][RT - 1];
+        if (TAIL) tl = tail_sum(tl);  // rows 16 (RT - 1) + e of column col, in every group g
         if (G == 1) {
             const int tgt = tile_tgt[(int64_t)tile * TW + col];
             if (tgt < 0) continue;
             T *dst = L + (int64_t)tgt * P2pad;
 #pragma unroll
-            for (int r = 0; r < RT; ++r)
+            for (int r = 0; r < RM; ++r)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] += acc[cg][r][e];
+            if (TAIL && g == 0)
+#pragma unroll
+                for (int e = 0; e < TR; ++e) dst[16 * (RT - 1) + e] += tl[e];
         } else {
             T *dst = part + (((int64_t)gch * ntile + tile) * TW + col) * P2pad;
 #pragma unroll
-            for (int r = 0; r < RT; ++r)
+            for (int r = 0; r < RM; ++r)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
+            if (TAIL)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dst[16 * (RT - 1) + 4 * g + e] = g == 0 ? tl[e] : (T)0;
         }
     }
 }
@@ -671,7 +708,7 @@ __global__ __launch_bounds__(256) void k_x_segments(const uint64_t *k2, const in
 // products lie together for the reduction.
 // Block = WV waves; the operator passes through two LDS stage buffers, the
 // next stage copied while the current one is multiplied.
-template <class T, int RT, int Q, int CG, int WV>
+template <class T, int RT, int Q, int CG, int WV, int TR>
 __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict__ t_op,
                                                    const int64_t *__restrict__ t_first,
                                                    const int32_t *__restrict__ t_cnt, const int32_t *__restrict__ src,
@@ -681,6 +718,7 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
 {
     constexpr int ESZ = (int)sizeof(T);
     constexpr int P2pad = 16 * RT;
+    constexpr bool TAIL = TR > 0 && ESZ == 4;  // the last row tile on 4x4x1 blocks
     constexpr int SCH = m2l_sch(RT, Q, ESZ), NC = Q / SCH, GST = m2l_gst(RT, Q, ESZ);
     constexpr int BUF = m2l_rounds(RT, Q, ESZ, WV) * 1024 * WV / ESZ;
     constexpr int VN = BVec<T, Q>::n;
@@ -729,18 +767,26 @@ __global__ __launch_bounds__(64 * WV) void k_m2l_pairs(const int32_t *__restrict
 #pragma unroll
             for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
-                for (int r = 0; r < RT; ++r) acc[cg][r] = Mfma<T>::run(a[r], bq[cg][c * SCH + ss], acc[cg][r]);
+                for (int r = 0; r < RT; ++r)
+                    acc[cg][r] = (TAIL && r == RT - 1) ? mfma_tail<T>(a[r], bq[cg][c * SCH + ss], acc[cg][r])
+                                                       : Mfma<T>::run(a[r], bq[cg][c * SCH + ss], acc[cg][r]);
         }
     }
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg) {
         const int col = wave * CG * 16 + cg * 16 + j;
+        constexpr int RM = TAIL ? RT - 1 : RT;
+        acc_t tl = acc[cg][RT - 1];
+        if (TAIL) tl = tail_sum(tl);  // every lane takes part in the exchange
         if (col >= cnt) continue;
         T *dst = out + ((int64_t)rpos[first + col] - pos0) * P2pad;
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+        for (int r = 0; r < RM; ++r)
 #pragma unroll
             for (int e = 0; e < 4; ++e) dst[16 * r + Mfma<T>::acc_row(g, e)] = acc[cg][r][e];
+        if (TAIL)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dst[16 * (RT - 1) + 4 * g + e] = g == 0 ? tl[e] : (T)0;
     }
 }
 
@@ -771,6 +817,17 @@ __global__ void k_mfma_probe_f32(float *out)
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     for (int e = 0; e < 4; ++e) out[l * 4 + e] = acc[e];
 }
+__global__ void k_mfma_probe_f32_4x4(float *out)
+{
+    const int l = threadIdx.x;
+    v4f acc = {0, 0, 0, 0};
+    // block b = l / 4: A_b[i] = i + 1 + 16 b (lane 4 b + i), B_b[jj] = 1 + 1000 jj
+    // (lane 4 b + jj); so D_b[i][jj] = (i + 1 + 16 b)(1 + 1000 jj)
+    const float a = (float)((l & 3) + 1 + 16 * (l >> 2));
+    const float b = 1.0f + (float)(l & 3) * 1000.0f;
+    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc, 0, 0, 0);
+    for (int e = 0; e < 4; ++e) out[l * 4 + e] = acc[e];
+}
 __global__ void k_mfma_probe_f64(double *out)
 {
     const int l = threadIdx.x;
@@ -782,7 +839,7 @@ __global__ void k_mfma_probe_f64(double *out)
 }
 
 // Launches chunk after chunk (G chunks at a time) over every tile.
-template <class T, int RT, int Q>
+template <class T, int RT, int Q, int TR>
 void launch_batched(fmm_plan *P, hipStream_t s)
 {
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8), WV = m2l_wv(RT, sizeof(T) == 8);
@@ -792,7 +849,7 @@ void launch_batched(fmm_plan *P, hipStream_t s)
         const int g = std::min(P->G, P->NCH - c0);
         const int64_t nb = (int64_t)g * ntpos;
         FMM_CHECK(nb * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many tiles");
-        k_m2l_batched<T, RT, Q, CG, WV><<<(unsigned)nb, 64 * WV, 0, s>>>(
+        k_m2l_batched<T, RT, Q, CG, WV, TR><<<(unsigned)nb, 64 * WV, 0, s>>>(
             P->tile_order, ntpos, P->tile_cls, P->slots, P->tile_kl, P->tile_nk, P->st_op, P->K, P->E, c0, g,
             P->slot_none, (int)P->ncell, static_cast<const T *>(P->ops), static_cast<const T *>(P->Mc),
             static_cast<T *>(P->m2l_part), P->tile_tgt, static_cast<T *>(P->Lc), P->ntile);
@@ -815,14 +872,14 @@ void dispatch_tiles(fmm_plan *P, hipStream_t s)
 {
     switch (P->p) {
 #define M2L_CASE(pp)                                             \
-    case pp: launch_batched<T, m2l_rt(pp), m2l_q(pp)>(P, s); break;
+    case pp: launch_batched<T, m2l_rt(pp), m2l_q(pp), m2l_tail_rows(pp)>(P, s); break;
         M2L_FOR_EACH_P(M2L_CASE)
 #undef M2L_CASE
     default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported expansion order");
     }
 }
 
-template <class T, int RT, int Q>
+template <class T, int RT, int Q, int TR>
 void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 {
     constexpr int CG = m2l_cg(RT, sizeof(T) == 8), WV = m2l_wv(RT, sizeof(T) == 8);
@@ -830,7 +887,7 @@ void launch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
     const int64_t nt = ch.t1 - ch.t0;
     FMM_CHECK(nt * 64 * WV < (1ll << 32), FMM_ERR_UNSUPPORTED, "m2l: too many cross tiles");
     if (nt > 0) {
-        k_m2l_pairs<T, RT, Q, CG, WV><<<(unsigned)nt, 64 * WV, 0, s>>>(
+        k_m2l_pairs<T, RT, Q, CG, WV, TR><<<(unsigned)nt, 64 * WV, 0, s>>>(
             P->xt_op + ch.t0, P->xt_first + ch.t0, P->xt_cnt + ch.t0, P->xp_src, P->xr_inv, (int)P->ncell,
             static_cast<const T *>(P->xops), static_cast<const T *>(P->Mc), static_cast<T *>(P->xbuf), ch.p0);
         FMM_HIP(hipGetLastError());
@@ -848,7 +905,7 @@ void dispatch_pairs(fmm_plan *P, const XChunk &ch, hipStream_t s)
 {
     switch (P->p) {
 #define M2L_CASE(pp)                                                    \
-    case pp: launch_pairs<T, m2l_rt(pp), m2l_q(pp)>(P, ch, s); break;
+    case pp: launch_pairs<T, m2l_rt(pp), m2l_q(pp), m2l_tail_rows(pp)>(P, ch, s); break;
         M2L_FOR_EACH_P(M2L_CASE)
 #undef M2L_CASE
     default: throw Error(FMM_ERR_UNSUPPORTED, "m2l: unsupported expansion order");
@@ -1227,10 +1284,11 @@ void mfma_probe(int f64, void *out_host)
 {
     void *d = nullptr;
     FMM_HIP(hipMalloc(&d, 64 * 4 * sizeof(double)));
-    if (f64) k_mfma_probe_f64<<<1, 64>>>(static_cast<double *>(d));
+    if (f64 == 1) k_mfma_probe_f64<<<1, 64>>>(static_cast<double *>(d));
+    else if (f64 == 2) k_mfma_probe_f32_4x4<<<1, 64>>>(static_cast<float *>(d));
     else k_mfma_probe_f32<<<1, 64>>>(static_cast<float *>(d));
     FMM_HIP(hipGetLastError());
-    FMM_HIP(hipMemcpy(out_host, d, 64 * 4 * (f64 ? sizeof(double) : sizeof(float)), hipMemcpyDeviceToHost));
+    FMM_HIP(hipMemcpy(out_host, d, 64 * 4 * (f64 == 1 ? sizeof(double) : sizeof(float)), hipMemcpyDeviceToHost));
     FMM_HIP(hipFree(d));
 }
 

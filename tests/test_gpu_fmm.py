@@ -30,6 +30,10 @@ def test_mfma_lane_layout():
                 j = l % 16
                 exp[4 * l + e] = (i + 1) * (1 + 1000 * j)
         assert np.array_equal(out, exp), f"f64={f64}"
+    # the 4x4x1 blocks of the short last row tile (float32)
+    out = np.asarray(F.mfma_layout(False, tail=True), dtype=np.float64)
+    exp = np.array([(e + 1 + 16 * (l // 4)) * (1 + 1000 * (l % 4)) for l in range(64) for e in range(4)], float)
+    assert np.array_equal(out, exp), "4x4x1"
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
