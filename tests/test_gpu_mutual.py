@@ -129,3 +129,17 @@ def test_mutual_bits_reproducible_and_adjoint():
     dq, dx = plan.adjoint(dev(q), dev(w))
     assert rel(host(dq), pw) < 1e-11
     assert rel(host(dx), -(w[:, None] * Eq + q[:, None] * Ew)) < 1e-11
+
+
+def test_mutual_inside_virtual_ranks():
+    # every rank's local near field runs mutually; the remote lists stay
+    # one-sided: the same sums as the one-sided ranks up to rounding order
+    x, _, rng = W.plummer(30000, 41)
+    q = rng.uniform(-1.0, 1.0, 30000)
+    outs = {}
+    for mutual in (False, True):
+        prm = F.Params(p=5, theta=0.4, ncrit=16, precision="fp64", mutual=mutual)
+        out = F.let_evaluate(dev(x), dev(q), 3, prm)
+        outs[mutual] = (host(out["phi"]), host(out["E"]))
+    assert rel(outs[True][0], outs[False][0]) < 1e-12
+    assert rel(outs[True][1], outs[False][1]) < 1e-12
