@@ -141,6 +141,23 @@ def test_orders_and_padding(p):
     assert rel(pm, po) < 1e-4 and rel(Em, Eo) < 1e-4
 
 
+@pytest.mark.parametrize("p", [6, 7, 9, 10])
+def test_short_last_tile(p):
+    # p = 6, 7, 9, 10: in float32 the last row tile holds at most 4
+    # coefficient rows and runs on 4x4x1 blocks (same-level and pair-list
+    # products).  Those rows are top-degree coefficients, which matter only
+    # when the acceptance parameter is large: at theta = 0.9 the oracle's
+    # p - 1 and p results differ by 1.5e-3 (p = 6) down to 5e-5 (p = 10),
+    # while the mixed path's own rounding is 1e-7 to 6e-7 (measured), so the
+    # bar of 2e-6 leaves the top-degree rows no room to be wrong
+    x, _, _ = W.uniform_cube(20000, 66)
+    q = np.random.default_rng(86).uniform(-1.0, 1.0, 20000)
+    T = oracle.Tree(x, 32, 0.9)
+    po, Eo = T.fmm(q, p)
+    _, pm, Em = gpu_fmm(x, q, p, 0.9, 32, "mixed")
+    assert rel(pm, po) < 2e-6 and rel(Em, Eo) < 2e-6, (p, rel(pm, po), rel(Em, Eo))
+
+
 @pytest.mark.parametrize("p,n,ncrit,theta", [(4, 60000, 24, 0.35), (10, 12000, 8, 0.45)])
 def test_cross_level_pairs_plummer(p, n, ncrit, theta):
     # adaptive trees with many leaf-against-finer-cell pairs, at a tile width
