@@ -267,6 +267,7 @@ struct fmm_plan {
     int32_t *mu_it_leaf = nullptr;   // [nitem] target leaf
     int64_t *mu_it_u = nullptr;      // [4 nitem] first entry, end of the touching run, end, first target-side slot
     int64_t *mu_li = nullptr;        // [nleaf + 1] first item of each leaf (leaf order)
+    int32_t *mu_order = nullptr;     // [nitem] launch order of the items: most work first
     void *mu_bufA = nullptr;         // [nabody] target-side sums per item (phi, E) as 4-vectors
     void *mu_bufB = nullptr;         // [nslot] source-side sums per (upper entry, source body)
     int64_t *m2lx_off = nullptr; int32_t *m2lx_src = nullptr;  // cross-level M2L

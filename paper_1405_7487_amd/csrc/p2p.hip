@@ -727,18 +727,20 @@ __device__ void mu_pass(V4 *sb, int64_t *sd, GatherLds<T> *gs, int64_t *sdst, in
 }
 
 // it_u: [4 nitem] = first upper entry, end of its touching run, end, first
-// target-side slot.
+// target-side slot.  Block b runs item order[b]: the items with the most
+// pair work first, so that the short ones fill the end of the launch (a
+// leaf's share of upper entries runs from none to its whole list).
 template <class T, class V4, bool KAHAN>
-__global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *it_leaf, const int64_t *it_u, int64_t nitem,
-                                                   const int32_t *usrc, const int64_t *pb, const int32_t *beg,
-                                                   const int32_t *end, const double *ctr, const V4 *ub, const V4 *ul,
-                                                   V4 *bufA, V4 *bufB)
+__global__ __launch_bounds__(64) void k_p2p_mutual(const int32_t *order, const int32_t *it_leaf, const int64_t *it_u,
+                                                   int64_t nitem, const int32_t *usrc, const int64_t *pb,
+                                                   const int32_t *beg, const int32_t *end, const double *ctr,
+                                                   const V4 *ub, const V4 *ul, V4 *bufA, V4 *bufB)
 {
     __shared__ V4 sb[4 * kMuBatch];
     __shared__ int64_t sd[2 * kMuBatch];
     __shared__ int64_t sdst[64];
     __shared__ GatherLds<T> gs;
-    const int64_t item = blockIdx.x;
+    const int64_t item = order[blockIdx.x];
     const int A = it_leaf[item];
     const int64_t u0 = it_u[item], un = it_u[nitem + item], u1 = it_u[2 * nitem + item], a0 = it_u[3 * nitem + item];
     const int lane = threadIdx.x, row = lane >> 4, i = lane & 15;
@@ -983,6 +985,23 @@ __global__ __launch_bounds__(256) void k_mu_fill(const int32_t *leaves, int64_t 
     }
 }
 
+// Sort key of every item: its pair work (source-side slots, i.e. source
+// bodies times target chunks, times the target bodies of one chunk)
+// subtracted from 2^40, so that an ascending stable sort puts the most work
+// first.
+__global__ __launch_bounds__(256) void k_mu_work(const int32_t *it_leaf, const int64_t *it_u, int64_t nitem,
+                                                 const int64_t *pb, const int32_t *beg, const int32_t *end,
+                                                 uint64_t *key, int32_t *val)
+{
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitem) return;
+    const int A = it_leaf[it];
+    const int64_t u0 = it_u[it], u1 = it_u[2 * nitem + it];
+    const int64_t w = (pb[u1] - pb[u0]) * min(64, end[A] - beg[A]);
+    key[it] = (1ull << 40) - (uint64_t)min(w, (int64_t)(1ll << 40) - 1);
+    val[it] = (int32_t)it;
+}
+
 __global__ __launch_bounds__(256) void k_mu_keys(const int32_t *usrc, int64_t n, uint64_t *key, int32_t *val)
 {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1017,7 +1036,7 @@ void launch_items(fmm_plan *P, const void *ub, void *phi_s, void *E_s, hipStream
     if (P->mutual && P->mu_nitem > 0) {
         FMM_CHECK(P->mu_nitem < (1ll << 32), FMM_ERR_UNSUPPORTED, "p2p: too many mutual work items");
         k_p2p_mutual<T, V4, KAHAN><<<(unsigned)P->mu_nitem, 64, 0, s>>>(
-            P->mu_it_leaf, P->mu_it_u, P->mu_nitem, P->mu_src, P->mu_pb, P->c_beg, P->c_end, P->c_ctr,
+            P->mu_order, P->mu_it_leaf, P->mu_it_u, P->mu_nitem, P->mu_src, P->mu_pb, P->c_beg, P->c_end, P->c_ctr,
             static_cast<const V4 *>(ub), static_cast<const V4 *>(P->ulo), static_cast<V4 *>(P->mu_bufA),
             static_cast<V4 *>(P->mu_bufB));
         FMM_HIP(hipGetLastError());
@@ -1121,6 +1140,17 @@ static void p2p_mutual_prepare(fmm_plan *P, hipStream_t s)
         al.free(t2);
     }
     al.free(usz);
+    // launch order of the items, most work first
+    P->mu_order = static_cast<int32_t *>(plan_alloc(P, sizeof(int32_t) * std::max<int64_t>(1, P->mu_nitem)));
+    if (P->mu_nitem > 0) {
+        FMM_CHECK(P->mu_nitem < (1ll << 31), FMM_ERR_UNSUPPORTED, "mutual P2P: too many work items");
+        uint64_t *wk = static_cast<uint64_t *>(al.alloc(sizeof(uint64_t) * P->mu_nitem));
+        k_mu_work<<<grid1(P->mu_nitem, 256), 256, 0, s>>>(P->mu_it_leaf, P->mu_it_u, P->mu_nitem, P->mu_pb, P->c_beg,
+                                                          P->c_end, wk, P->mu_order);
+        FMM_HIP(hipGetLastError());
+        radix_sort_u64(wk, P->mu_order, P->mu_nitem, 41, al, s);
+        al.free(wk);
+    }
     P->mu_bufA = plan_alloc(P, esz * 4 * std::max<int64_t>(1, P->mu_nabody));
     P->mu_bufB = plan_alloc(P, esz * 4 * std::max<int64_t>(1, P->mu_nslot));
 }
